@@ -1,0 +1,323 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+dense brute force, closed forms, invariants and library routines."""
+import numpy as np
+import pytest
+
+from oracle import brute as bf
+from oracle import mpo_oracle as mo
+from paper_2604_21908_amd import circuitgen as cg
+
+X = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+
+
+def peak_operator(c):
+    """X^b K as a dense matrix, from the generator's undressed K gates."""
+    k = bf.circuit_unitary(c.n, c.k_gates)
+    xb = np.array([[1.0 + 0j]])
+    for q in range(c.n):
+        xb = np.kron(xb, X if c.peak[q] else np.eye(2))
+    return xb @ k
+
+
+# ------------------------------------------------------------------ inputs
+@pytest.mark.parametrize("reading", ["A", "B"])
+@pytest.mark.parametrize("n,depth,seed", [(6, 3, 1), (7, 4, 2), (8, 4, 3)])
+def test_generator_operator_is_planted_peak(reading, n, depth, seed):
+    c = cg.mirrored_peaked_circuit(n, depth, seed, reading=reading)
+    for q0, q1, u in c.gates:
+        assert q1 == q0 + 1
+        assert np.allclose(u.conj().T @ u, np.eye(4), atol=1e-12)
+    assert np.allclose(bf.circuit_unitary(n, c.gates), peak_operator(c), atol=1e-11)
+
+
+def test_generator_seeded_and_obfuscated():
+    a = cg.mirrored_peaked_circuit(10, 4, 7)
+    b = cg.mirrored_peaked_circuit(10, 4, 7)
+    c = cg.mirrored_peaked_circuit(10, 4, 8)
+    assert a.digest() == b.digest() and a.digest() != c.digest()
+    # no gate is a bare SWAP and no two consecutive gates on a pair cancel literally
+    for q0, q1, u in a.gates:
+        assert not np.allclose(np.abs(u), np.abs(mo.SWAP4))
+    for (p0, p1, u), (r0, r1, v) in zip(a.gates, a.gates[1:]):
+        if (p0, p1) == (r0, r1):
+            assert not np.allclose(v @ u, np.eye(4) * (v @ u)[0, 0], atol=1e-6)
+
+
+def test_oets_sorts_and_inverse_cancels():
+    rng = np.random.default_rng(0)
+    for n in (2, 5, 9, 16):
+        perm = rng.permutation(n)
+        a = list(perm)
+        for rnd in cg.oets_swaps(perm):
+            for i, j in rnd:
+                a[i], a[j] = a[j], a[i]
+        assert a == sorted(a)
+
+
+# ----------------------------------------------------------- truncation rule
+def brute_rank(s, chi_max, cutoff, mode):
+    s = np.asarray(s)
+    if mode == "rel_sv":
+        k = sum(1 for x in s if x > cutoff * s[0])
+    else:
+        tot = sum(x * x for x in s)
+        k = next(kk for kk in range(len(s) + 1) if sum(x * x for x in s[kk:]) <= cutoff * tot)
+    return max(1, min(k, chi_max, len(s)))
+
+
+def test_truncation_rank_hand_spectra():
+    assert mo.truncation_rank([1.0, 0.5, 1e-13], 10, 1e-12, "rel_sv") == 2
+    assert mo.truncation_rank(np.sqrt([0.9, 0.09, 0.009, 0.001]), 10, 0.002, "weight") == 3
+    assert mo.truncation_rank(np.sqrt([0.9, 0.09, 0.009, 0.001]), 2, 0.002, "weight") == 2
+    assert mo.truncation_rank(np.sqrt([0.9, 0.09, 0.009, 0.001]), 10, 0.0, "weight") == 4
+    assert mo.truncation_rank([1.0, 0.0, 0.0], 10, 1e-12, "weight") == 1
+    assert mo.truncation_rank([0.0, 0.0], 10, 1e-12, "rel_sv") == 1
+
+
+def test_truncation_rank_matches_brute_force_and_is_monotone():
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        s = np.sort(rng.exponential(size=rng.integers(1, 30)) ** 4)[::-1]
+        for mode in ("rel_sv", "weight"):
+            cut = 10.0 ** rng.uniform(-8, -1)
+            chi = int(rng.integers(1, 40))
+            k = mo.truncation_rank(s, chi, cut, mode)
+            assert k == brute_rank(s, chi, cut, mode)
+            assert mo.truncation_rank(s, chi, cut * 10, mode) <= k
+
+
+# --------------------------------------------------- single-gate closed forms
+def local(rng):
+    return np.kron(cg.haar_unitary(rng, 2), cg.haar_unitary(rng, 2))
+
+
+@pytest.mark.parametrize("abc", [(0.3, 0.2, 0.1), (0.7, 0.4, -0.2), (np.pi / 4, np.pi / 4, np.pi / 4),
+                                 (np.pi / 4, 0.0, 0.0), (0.0, 0.0, 0.0)])
+@pytest.mark.parametrize("side", ["out", "in"])
+def test_single_gate_operator_schmidt_values(abc, side):
+    rng = np.random.default_rng(5)
+    g = local(rng) @ bf.kak_gate(*abc) @ local(rng)
+    for n, bond in ((2, 0), (5, 2)):
+        m = mo.OracleMPO(n)
+        r = mo.bond_update(m, bond, g if side == "out" else None, g if side == "in" else None,
+                           64, 1e-12, "rel_sv")
+        want = bf.kak_schmidt_values(*abc)
+        got = np.zeros(4)
+        got[:len(r.s)] = r.s[:4]
+        assert np.allclose(got, want, atol=1e-12)
+        assert r.k == int(np.count_nonzero(want > 1e-12 * want[0]))
+
+
+def test_swap_and_cnot_spectra():
+    m = mo.OracleMPO(3)
+    r = mo.bond_update(m, 1, mo.SWAP4, None, 64, 1e-12, "rel_sv")
+    assert np.allclose(r.s, [0.5] * 4, atol=1e-14) and r.k == 4
+    cnot = np.eye(4, dtype=complex)[[0, 1, 3, 2]]
+    r = mo.bond_update(m, 0, None, cnot, 64, 1e-12, "rel_sv")
+    assert r.k == 2 and np.allclose(r.s[:2], [np.sqrt(0.5)] * 2, atol=1e-14)
+
+
+def test_mirrored_pair_on_identity_is_rank_one():
+    rng = np.random.default_rng(2)
+    g = cg.haar_su4(rng)
+    m = mo.OracleMPO(4)
+    r = mo.bond_update(m, 1, g.conj().T, g, 64, 1e-12, "rel_sv")
+    assert r.k == 1 and abs(r.s[0] - 1) < 1e-13
+
+
+# ------------------------------------------------- gate conventions vs dense
+def random_mpo(n, seed, layers=3):
+    rng = np.random.default_rng(seed)
+    m = mo.OracleMPO(n)
+    for l in range(layers):
+        for i in range(l % 2, n - 1, 2):
+            mo.commit(m, mo.bond_update(m, i, cg.haar_su4(rng), cg.haar_su4(rng), 256, 1e-14, "rel_sv"))
+    return m
+
+
+def embed(u, i, n):
+    return np.kron(np.kron(np.eye(2 ** i), u), np.eye(2 ** (n - i - 2)))
+
+
+@pytest.mark.parametrize("bond", [0, 2, 3])
+def test_bond_update_equals_dense_products(bond):
+    n = 5
+    m = random_mpo(n, 10 + bond)
+    before = m.dense_operator()
+    rng = np.random.default_rng(bond)
+    go, gi = cg.haar_su4(rng), cg.haar_su4(rng)
+    r = mo.bond_update(m, bond, go, gi, 1024, 0.0, "weight")
+    mo.commit(m, r)
+    after = m.dense_operator()
+    want = embed(go, bond, n) @ before @ embed(gi, bond, n)
+    assert np.allclose(after, want, atol=1e-12)
+    # the kept values are the operator-Schmidt values of the new operator at that cut
+    vec = m.dense_vector().reshape(4 ** (bond + 1), -1)
+    assert np.allclose(np.linalg.svd(vec, compute_uv=False)[:r.k], r.s[:r.k], atol=1e-12)
+    # canonical form survives: every B is right-canonical
+    for b in m.B:
+        mat = b.reshape(b.shape[0], -1)
+        assert np.allclose(mat @ mat.conj().T, np.eye(b.shape[0]), atol=1e-12)
+
+
+def test_identity_mpo_is_identity_operator():
+    m = mo.OracleMPO(4)
+    assert np.allclose(m.dense_operator() * 2 ** 2, np.eye(16))
+    assert m.size() == 16 and m.bond_dims() == [1, 1, 1]
+
+
+# ----------------------------------------------- whole contraction (Alg. 1)
+@pytest.mark.parametrize("reading", ["A", "B"])
+def test_contraction_reproduces_dense_unitary(reading):
+    c = cg.mirrored_peaked_circuit(8, 4, 21, reading=reading)
+    res = mo.contract(c.n, c.gates, mo.OracleConfig(chi_max=256, cutoff=1e-12, unswap="none"))
+    full = mo.full_operator(res) * 2 ** (c.n / 2)
+    assert np.allclose(full, bf.circuit_unitary(c.n, c.gates), atol=1e-10)
+    # unitarity bookkeeping: every update keeps sum s^2 = 1 when nothing is discarded
+    for t in res.trace:
+        if "k" in t:
+            assert abs(t["total"] - 1.0) < 1e-10
+
+
+def test_discarded_weight_bounds_the_error():
+    c = cg.mirrored_peaked_circuit(8, 4, 22, reading="B")
+    exact = bf.circuit_unitary(c.n, c.gates) / 2 ** (c.n / 2)
+    res = mo.contract(c.n, c.gates, mo.OracleConfig(chi_max=6, cutoff=1e-12, unswap="none"))
+    err = np.linalg.norm(mo.full_operator(res) - exact)
+    bound = sum(np.sqrt(t["discarded"]) for t in res.trace if "k" in t)
+    assert bound > 1e-3          # truncation really happened
+    assert err <= bound * 1.01 + 1e-10
+
+
+def test_collapse_invariant_of_the_unobfuscated_mirror():
+    c = cg.mirror_only_circuit(10, 6, 3)
+    res = mo.contract(c.n, c.gates, mo.OracleConfig(chi_max=64, cutoff=1e-12, unswap="none"))
+    ups = [t for t in res.trace if "k" in t]
+    assert len(ups) == len(c.gates) // 2
+    assert all(t["k"] == 1 and abs(t["s"][0] - 1) < 1e-12 for t in ups)
+
+
+@pytest.mark.parametrize("schedule", ["sequential", "parallel"])
+@pytest.mark.parametrize("relaxed", [False, True])
+def test_unswap_reconstructs_operator_and_rewiring_is_exact(schedule, relaxed):
+    c = cg.mirrored_peaked_circuit(8, 3, 31, reading="B")
+    cfg = mo.OracleConfig(chi_max=256, cutoff=1e-12, tau=300, unswap=schedule, relaxed=relaxed)
+    ct = mo.Contraction(c.n, c.gates, cfg)
+    checked = 0
+    while ct.left or ct.right:
+        ct.absorb_step()
+        while ct.m.size() < cfg.tau and (ct.left or ct.right):
+            ct.absorb_step()
+        before = mo.full_operator(mo.OracleResult(None, 0, 0, None, list(ct.lay_l.site_of),
+                                                  list(ct.lay_r.site_of), [], ct.m))
+        dims0 = sum(ct.m.bond_dims())
+        log = ct.unswap()
+        after = mo.full_operator(mo.OracleResult(None, 0, 0, None, list(ct.lay_l.site_of),
+                                                 list(ct.lay_r.site_of), [], ct.m))
+        assert np.allclose(before, after, atol=1e-10)           # M = P_L M~ P_R
+        if not relaxed:
+            assert sum(ct.m.bond_dims()) <= dims0
+        checked += len(log)
+    assert checked > 0
+    site_bits, p, n2 = mo.extract_peak(ct.m)
+    res = mo.OracleResult(None, p, n2, site_bits, list(ct.lay_l.site_of), list(ct.lay_r.site_of), [], ct.m)
+    full = mo.full_operator(res) * 2 ** (c.n / 2)
+    assert np.allclose(full, bf.circuit_unitary(c.n, c.gates), atol=1e-9)
+
+
+def test_unswap_removes_a_bare_swap_layer():
+    n = 7
+    m = mo.OracleMPO(n)
+    for i in range(0, n - 1, 2):
+        mo.commit(m, mo.bond_update(m, i, mo.SWAP4, None, 64, 1e-12, "rel_sv"))
+    for i in range(1, n - 1, 2):
+        mo.commit(m, mo.bond_update(m, i, None, mo.SWAP4, 64, 1e-12, "rel_sv"))
+    assert max(m.bond_dims()) == 4
+    for sched in ("sequential", "parallel"):
+        mm = m.copy()
+        cfg = mo.OracleConfig(chi_max=64, cutoff=1e-12, unswap=sched)
+        log = (mo.unswap_sequential if sched == "sequential" else mo.unswap_parallel)(mm, cfg)
+        assert mm.bond_dims() == [1] * (n - 1) and len(log) == n - 1
+
+
+# ------------------------------------------------------- peak extraction
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_extraction_matches_statevector_brute_force(seed):
+    c = cg.mirrored_peaked_circuit(9, 3, 40 + seed)
+    res = mo.contract(c.n, c.gates, mo.OracleConfig(chi_max=256, cutoff=1e-12, tau=400, unswap="parallel"))
+    psi = bf.circuit_state(c.n, c.gates)
+    prob = np.abs(psi) ** 2
+    best = int(np.argmax(prob))
+    assert (res.bits == bf.bits_of(best, c.n)).all()
+    assert (res.bits == c.peak).all()
+    assert abs(res.prob - prob[best]) < 1e-10
+    assert abs(res.norm2 - 2.0 ** -c.n) < 1e-12 * 2.0 ** -c.n * 100
+
+
+def test_extraction_probability_of_returned_string_is_exact():
+    # on a generic (not peaked) MPO the greedy string need not be the argmax,
+    # but the returned probability must be that string's exact weight
+    rng = np.random.default_rng(3)
+    n = 6
+    m = random_mpo(n, 77, layers=4)
+    bits, p, n2 = mo.extract_peak(m)
+    op = m.dense_operator()
+    psi = op[:, 0]
+    idx = int("".join(str(int(b)) for b in bits), 2)
+    assert abs(p - abs(psi[idx]) ** 2 / np.vdot(psi, psi).real) < 1e-12
+    assert abs(n2 - np.vdot(psi, psi).real) < 1e-14
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 8, 9])
+def test_closed_form_peak_probability_vs_statevector(n):
+    c = cg.mirrored_peaked_circuit(n, 2, 11 + n)
+    psi = bf.circuit_state(n, c.k_gates)
+    assert abs(bf.peak_probability_closed_form(n, c.k_gates) - abs(psi[0]) ** 2) < 1e-13
+    full = bf.circuit_state(n, c.gates)
+    idx = int(c.peak_string, 2)
+    assert abs(abs(full[idx]) ** 2 - abs(psi[0]) ** 2) < 1e-12
+
+
+@pytest.mark.parametrize("n", [4, 7, 10])
+def test_k_margins_vs_statevector(n):
+    c = cg.mirrored_peaked_circuit(n, 2, 60 + n)
+    psi = np.abs(bf.circuit_state(n, c.k_gates).reshape([2] * n)) ** 2
+    got = bf.k_state_margins(n, c.k_gates)
+    for i in range(n):
+        pre = psi[(0,) * i]
+        marg = pre.reshape(2, -1).sum(axis=1)
+        assert abs(got[i] - marg[0] / marg.sum()) < 1e-12
+
+
+@pytest.mark.parametrize("config", [0, 1, 2])
+def test_workload_peaks_are_greedy_readable(config):
+    c = cg.config_circuit(config)
+    assert bf.k_state_margins(c.n, c.k_gates).min() > 0.5
+    p = bf.peak_probability_closed_form(c.n, c.k_gates)
+    assert 1e-5 < p < 1
+
+
+# ------------------------------------------------ planted mistakes must fail
+def test_planted_mistakes_are_caught(monkeypatch):
+    """A transposed input gate, a dropped Lambda or a dropped conjugate in the
+    oracle each break the dense pin above."""
+    n, bond = 5, 2
+    m = random_mpo(n, 12)
+    before = m.dense_operator()
+    rng = np.random.default_rng(0)
+    go, gi = cg.haar_su4(rng), cg.haar_su4(rng)
+    want = embed(go, bond, n) @ before @ embed(gi, bond, n)
+
+    def run():
+        mm = m.copy()
+        mo.commit(mm, mo.bond_update(mm, bond, go, gi, 1024, 0.0, "weight"))
+        return np.allclose(mm.dense_operator(), want, atol=1e-10)
+
+    assert run()
+    orig = mo.apply_gates_to_theta
+    monkeypatch.setattr(mo, "apply_gates_to_theta", lambda t, a, b: orig(t, a, None if b is None else b.T))
+    assert not run()
+    monkeypatch.setattr(mo, "apply_gates_to_theta", lambda t, a, b: orig(t, a, None if b is None else b.conj()))
+    assert not run()
+    monkeypatch.setattr(mo, "apply_gates_to_theta", lambda t, a, b: orig(t, b, a))
+    assert not run()
