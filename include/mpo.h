@@ -1,0 +1,192 @@
+/*
+ * mpo.h -- C ABI of the MI355X (gfx950) MPO bond-update library (libmpo.so).
+ *
+ * The library holds one matrix product operator M per handle, in device
+ * memory, and applies to it the operations of the middle-MPO contraction of
+ * mirrored peaked circuits (Kremer & Dupuis, Sec. II and Alg. 1):
+ *
+ *   mpo_init_identity     M <- I^{(x)N}                         (Alg. 1, Sec. II.A)
+ *   mpo_absorb_gate_pair  two-site absorption + truncated SVD   (Sec. II.B.1)
+ *   mpo_unswap_sweep      greedy SWAP extraction, M = P_L M~ P_R (Sec. II.B.2, Eq. (1), App. A.1, A.2)
+ *   mpo_extract_peak      M|0...0> as an MPS, greedy peak readout (Alg. 1 last step, Sec. II.C)
+ *
+ * Representation.  Site i is a tensor B_i[a][s][b] of shape chi_{i-1} x 4 x chi_i
+ * (chi_{-1} = chi_{N-1} = 1) with physical index s = 2*o + p, o the output bit
+ * and p the input bit.  The MPO is kept in Vidal/Hastings form: every B_i is
+ * right-canonical as a vectorised tensor and bond i carries the operator-Schmidt
+ * values lambda_i (FP64).  The identity has B_i = (1, 0, 0, 1)/sqrt(2), so the
+ * vectorised MPO has unit norm.
+ *
+ * Gates.  A gate is a 4x4 complex matrix, row-major, interleaved (re, im)
+ * doubles (32 doubles), in the basis |q_bond q_bond+1> with site `bond` the
+ * most significant bit.  g_out acts on the output legs (M <- G M; gates of the
+ * circuit half applied after the midpoint), g_in on the input legs (M <- M G;
+ * gates of the half applied before it).  NULL means identity.  Gate data is
+ * read before the call returns.
+ *
+ * Truncation (Sec. II.B.1, App. A.4).  After each SVD the kept rank k is
+ *   MPO_CUT_REL_SV:            #{ s_j > cutoff * s_0 }
+ *   MPO_CUT_DISCARDED_WEIGHT:  smallest k with sum_{j>=k} s_j^2 <= cutoff * sum_j s_j^2
+ * then k <- min(k, chi_max) and k >= 1.  The decision is taken in FP64 in
+ * every precision.  Kept values are not renormalised.
+ *
+ * Streams.  All device work of a handle is enqueued on the HIP stream given at
+ * init (NULL = the default stream).  Calls that return host data synchronise
+ * that stream.  A handle is not thread-safe; different handles may be used
+ * from different threads on different streams.
+ *
+ * Errors.  Every call returns an mpo_status_t; no C++ exception crosses the
+ * ABI.  On a negative status the MPO is unchanged (all checks and allocations
+ * happen before the first write).  mpo_last_error() gives a message.
+ *
+ * Memory.  The handle owns its device memory (hipMalloc); the caller owns
+ * every host array passed in.  Site tensors are allocated at init for their
+ * largest possible shape, so later calls do not allocate for the MPO itself;
+ * SVD workspaces grow on demand and are kept until mpo_free.
+ */
+#ifndef MPO_H
+#define MPO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpo_ctx* mpo_handle_t;
+
+typedef enum {
+  MPO_OK = 0,
+  MPO_WARN_NOCONV = 1,   /* result written, but a Jacobi SVD reached its sweep cap */
+  MPO_EINVAL = -1,       /* bad argument (range, NULL, inconsistent sizes)        */
+  MPO_ENOMEM = -2,       /* device allocation failed                             */
+  MPO_EHIP = -3,         /* HIP runtime error                                    */
+  MPO_ENUMERIC = -4,     /* NaN/Inf in a gate or in the singular values          */
+  MPO_EOVERFLOW = -5     /* log truncated at log_cap (the sweep itself completed) */
+} mpo_status_t;
+
+typedef enum { MPO_CUT_REL_SV = 0, MPO_CUT_DISCARDED_WEIGHT = 1 } mpo_cutoff_mode_t;
+
+/* Arithmetic of the contraction and SVD kernels.  The truncation decision,
+ * rotation angles, lambdas and the peak readout are FP64 in all three. */
+typedef enum {
+  MPO_FP64 = 0,             /* complex128 tensors, FP64 MFMA                          */
+  MPO_FP32 = 1,             /* complex64 tensors, FP32 arithmetic                      */
+  MPO_MIXED_SPLITBF16 = 2   /* complex64 tensors, Jacobi rotations as split-BF16 MFMA
+                               products with FP32 accumulation, then an FP64
+                               re-orthogonalisation and an FP32 polish              */
+} mpo_precision_t;
+
+typedef struct {
+  int32_t n;              /* number of sites (qubits), >= 2                      */
+  int32_t chi_max;        /* bond-dimension cap (App. A.4), 1..1024              */
+  double cutoff;          /* SVD cutoff epsilon (App. A.4)                       */
+  int32_t cutoff_mode;    /* mpo_cutoff_mode_t                                  */
+  int32_t precision;      /* mpo_precision_t                                    */
+  int32_t max_sweeps;     /* Jacobi sweep cap per SVD; 0 = default (30)          */
+  double jacobi_tol;      /* off-diagonal tolerance; 0 = default for precision */
+} mpo_config_t;
+
+typedef struct {
+  int32_t chi_new;          /* kept rank k                                     */
+  int32_t sweeps;           /* Jacobi sweeps used                              */
+  double discarded_weight;  /* sum of dropped s_j^2 (absolute)                 */
+  double total_weight;      /* sum of all s_j^2                                */
+} mpo_update_info_t;
+
+typedef struct {
+  int32_t schedule;   /* 0 = sequential (Alg. 1), 1 = parallel (App. A.1)          */
+  int32_t relaxed;    /* 1 = also accept swaps that keep the bond (App. A.2)       */
+  int32_t max_iters;  /* App. A.4; parallel: full 6-batch cycles, sequential:
+                         max_iters * (n-1) accepted swaps; 0 = 20                  */
+} mpo_unswap_opts_t;
+
+typedef struct {
+  int32_t side;   /* 0 = left (output legs, P_L), 1 = right (input legs, P_R), 2 = both */
+  int32_t bond;   /* SWAP acts on sites (bond, bond+1)                                  */
+} mpo_swap_t;
+
+/* Alg. 1, "Initialize MPO M <- I^{(x)N}": allocates the handle and all site
+ * tensors (shape caps from chi_max and the 4^i edge bounds), writes the
+ * identity.  `hip_stream` is a hipStream_t or NULL.  *out receives the handle. */
+mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_handle_t* out);
+
+/* Sec. II.B.1: absorbs g_out (output legs) and g_in (input legs) at sites
+ * (bond, bond+1): theta = (G_out (x) G_in^T) lambda_{bond-1} B_bond B_bond+1
+ * as a (4 chi_l) x (4 chi_r) matrix, truncated SVD theta = U S V^dag,
+ * B_bond+1 <- V_k^dag, B_bond <- (theta without lambda) V_k, lambda_bond <- s_<k.
+ * bond in [0, n-2].  `info` may be NULL. */
+mpo_status_t mpo_absorb_gate_pair(mpo_handle_t h, int32_t bond, const double* g_out,
+                                  const double* g_in, mpo_update_info_t* info);
+
+/* Batched absorption of `count` updates on pairwise non-adjacent bonds
+ * (|bond_a - bond_b| >= 2), which are independent in Vidal form.  g_out / g_in
+ * hold `count` gates of 32 doubles each; a NULL array means identity for all,
+ * and a gate whose 32 entries are all zero also means identity.  `info` may be
+ * NULL or hold `count` entries. */
+mpo_status_t mpo_absorb_batch(mpo_handle_t h, int32_t count, const int32_t* bonds,
+                              const double* g_out, const double* g_in, mpo_update_info_t* info);
+
+/* Sec. II.B.2 / Alg. 1 (schedule 0) or App. A.1 (schedule 1): SWAP trials from
+ * the left, right or both sides, each followed by the truncated SVD; a trial
+ * is kept when it lowers (relaxed: does not raise) its bond's dimension.
+ * Sequential: largest available bond first (ties: lowest index), best of
+ * L/R/B by (k, discarded weight, side order).  Parallel: batches in the order
+ * both-even, both-odd, left-even, left-odd, right-even, right-odd until a full
+ * cycle lowers nothing.  Accepted swaps are written to log[0..log_cap) in
+ * order; *n_accepted gets the total count (which may exceed log_cap, then
+ * MPO_EOVERFLOW is returned after the sweep completed). */
+mpo_status_t mpo_unswap_sweep(mpo_handle_t h, const mpo_unswap_opts_t* opts, mpo_swap_t* log,
+                              int32_t log_cap, int32_t* n_accepted);
+
+/* Alg. 1 last step and Sec. II.C: A_i = B_i[:, s in {0, 2}, :] (input legs
+ * projected on |0>), exact right environments, then a left-to-right greedy
+ * conditional argmax (ties -> 0).  bits_per_site[n] receives site bits,
+ * *prob the product of the chosen conditionals (the normalised probability of
+ * that string) and *norm2 = <psi|psi>.  Either pointer may be NULL. */
+mpo_status_t mpo_extract_peak(mpo_handle_t h, uint8_t* bits_per_site, double* prob, double* norm2);
+
+/* ---- helpers ------------------------------------------------------------ */
+void mpo_free(mpo_handle_t h);
+/* dims[n-1] receives chi_0 .. chi_{n-2}. */
+mpo_status_t mpo_bond_dims(mpo_handle_t h, int32_t* dims);
+/* size(M) = sum_i chi_{i-1} * 4 * chi_i  (the tau test of Alg. 1). */
+mpo_status_t mpo_total_elements(mpo_handle_t h, int64_t* out);
+/* lambda_bond into out[0..cap), *count = chi_bond. */
+mpo_status_t mpo_singular_values(mpo_handle_t h, int32_t bond, double* out, int32_t cap, int32_t* count);
+/* Copies site i (chi_{i-1} x 4 x chi_i complex, interleaved, as complex128)
+ * into out (cap doubles); *chi_l / *chi_r receive its shape. */
+mpo_status_t mpo_read_site(mpo_handle_t h, int32_t site, double* out, int64_t cap,
+                           int32_t* chi_l, int32_t* chi_r);
+/* Replaces the whole state: dims[n-1] bond dimensions, sites = concatenation
+ * of all site tensors (complex128 interleaved, row-major [a][s][b]), lams =
+ * concatenation of all bond vectors.  Values are converted to the handle's
+ * precision.  The caller is responsible for the state being in Vidal form. */
+mpo_status_t mpo_load_state(mpo_handle_t h, const int32_t* dims, const double* sites,
+                            const double* lams);
+mpo_status_t mpo_sync(mpo_handle_t h);
+
+/* Kernel timing.  While profiling is on, every kernel launch of the handle is
+ * bracketed by HIP events on the handle's stream and its device time is added
+ * to one of the classes below.  A call synchronises the stream, writes the
+ * accumulated milliseconds and launch counts of each class (either pointer may
+ * be NULL), resets them, and then switches profiling on (on != 0) or off. */
+enum {
+  MPO_PROF_THETA_GEMM = 0,     /* theta0 = B_i B_{i+1} (MFMA complex GEMM)        */
+  MPO_PROF_GATE = 1,           /* gate pair + lambda, column-major copy for the SVD */
+  MPO_PROF_JACOBI_INIT = 2,    /* V = I, padding                                  */
+  MPO_PROF_JACOBI_STEP = 3,    /* one round-robin step of the block Jacobi SVD    */
+  MPO_PROF_FINALIZE = 4,       /* column norms, sort, truncation decision         */
+  MPO_PROF_WRITEBACK = 5,      /* B_{i+1} <- V_k^dag, lambda                        */
+  MPO_PROF_WRITEBACK_GEMM = 6, /* B_i <- theta_noLambda V_k (MFMA complex GEMM)    */
+  MPO_PROF_CLASSES = 7
+};
+mpo_status_t mpo_profile(mpo_handle_t h, int32_t on, double* ms_out, int64_t* launches_out);
+const char* mpo_last_error(mpo_handle_t h);
+/* Library build string (kernels compiled for, precision variants). */
+const char* mpo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPO_H */

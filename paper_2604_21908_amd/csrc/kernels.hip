@@ -1,0 +1,761 @@
+// HIP kernels of libmpo for gfx950 (CDNA4).
+//
+//   k_gemm         complex GEMM on real MFMA (4M: four real products per
+//                  complex K step), LDS-staged 64x64 tiles, batched
+//   k_gate         gate pair (G_out (x) G_in^T) on the physical legs of theta,
+//                  lambda scaling, column-major copy for the SVD
+//   k_jac_*        block one-sided (Hestenes) Jacobi SVD: Brent-Luk round-robin
+//                  over 16-column blocks; each block pair's 32x32 Gram matrix
+//                  is diagonalised by a cyclic Jacobi EVD in FP64 in LDS and
+//                  the panel of theta (and V) is rotated by its eigenvectors
+//   k_colnorms     singular values as column norms (FP64)
+//   k_sort_trunc   descending sort + truncation decision (FP64)
+//   k_wb_gather    B_{i+1} <- V_k^dag, lambda_i <- s_<k
+//   k_env / k_greedy  peak readout of M|0...0> (FP64)
+#include "common.h"
+
+namespace mpo {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+template <typename T> struct V4;
+template <> struct V4<float> { typedef v4f t; };
+template <> struct V4<double> { typedef v4d t; };
+
+__device__ __forceinline__ v4f mfma16x16x4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ============================================================== GEMM
+// One 256-thread workgroup computes a 64x64 complex tile; wave w owns the
+// 32x32 quadrant (w>>1, w&1) as 2x2 MFMA 16x16 tiles.  A 16x16x4 MFMA takes
+// A[i][k] from lane i + 16k and B[k][j] from lane j + 16k.  Element r of the
+// result holds D[4*(lane>>4) + r][lane & 15] for the f32 instruction and
+// D[(lane>>4) + 4*r][lane & 15] for the f64 one (measured on gfx950).
+constexpr int GT = 64;
+constexpr int GK = 16;
+
+template <typename T> __device__ __forceinline__ int mfma_row(int lane, int r);
+template <> __device__ __forceinline__ int mfma_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+template <> __device__ __forceinline__ int mfma_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm(GemmBatch gb) {
+  const int pi = blockIdx.z;
+  if (pi >= gb.count) return;
+  const GemmProb P = gb.p[pi];
+  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  if (m0 >= P.M || n0 >= P.N) return;
+  __shared__ cx<T> As[GT][GK + 1];
+  __shared__ cx<T> Bs[GK][GT + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  typedef typename V4<T>::t acc_t;
+  acc_t accr[2][2], acci[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) { accr[i][j][r] = 0; acci[i][j][r] = 0; }
+  const cx<T>* A = (const cx<T>*)P.A;
+  const cx<T>* B = (const cx<T>*)P.B;
+  for (int k0 = 0; k0 < P.K; k0 += GK) {
+    {
+      const int r = tid >> 2, kk = (tid & 3) * 4;
+      const int gr = m0 + r;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gk = k0 + kk + u;
+        cx<T> v = {0, 0};
+        if (gr < P.M && gk < P.K) v = A[(size_t)gr * P.lda + gk];
+        As[r][kk + u] = v;
+      }
+    }
+    if (P.bmode == 0) {
+      const int r = tid >> 4, c = (tid & 15) * 4;
+      const int gk = k0 + r;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gc = n0 + c + u;
+        cx<T> v = {0, 0};
+        if (gk < P.K && gc < P.N) v = B[(size_t)gk * P.ldb + gc];
+        Bs[r][c + u] = v;
+      }
+    } else {
+      const int r = tid >> 2, kk = (tid & 3) * 4;
+      const int gn = n0 + r;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gk = k0 + kk + u;
+        cx<T> v = {0, 0};
+        if (gn < P.N && gk < P.K) v = B[(size_t)gn * P.ldb + gk];
+        Bs[kk + u][r] = cx<T>{v.re, -v.im};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      cx<T> a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[wm + t * 16 + (lane & 15)][kk + (lane >> 4)];
+        b[t] = Bs[kk + (lane >> 4)][wn + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accr[i][j] = mfma16x16x4(a[i].re, b[j].re, accr[i][j]);
+          accr[i][j] = mfma16x16x4(-a[i].im, b[j].im, accr[i][j]);
+          acci[i][j] = mfma16x16x4(a[i].re, b[j].im, acci[i][j]);
+          acci[i][j] = mfma16x16x4(a[i].im, b[j].re, acci[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  cx<T>* C = (cx<T>*)P.C;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + mfma_row<T>(lane, r);
+        const int col = n0 + wn + j * 16 + (lane & 15);
+        if (row < P.M && col < P.N) C[(size_t)row * P.ldc + col] = cx<T>{accr[i][j][r], acci[i][j][r]};
+      }
+}
+
+// ============================================================== gate
+// T[(s1' s2'), (s1 s2)] = G_out[(o1' o2'), (o1 o2)] * G_in[(p1 p2), (p1' p2')],
+// s = 2o + p.  One thread per (a, b) applies T to the 16 entries theta0[a, :, :, b].
+template <typename T>
+__global__ __launch_bounds__(256) void k_gate(GateBatch gb) {
+  const int pi = blockIdx.y;
+  if (pi >= gb.count) return;
+  const GateProb P = gb.p[pi];
+  __shared__ cx<T> Tm[16][16];
+  const int tid = threadIdx.x;
+  {
+    const int row = tid >> 4, col = tid & 15;
+    const int s1p = row >> 2, s2p = row & 3, s1 = col >> 2, s2 = col & 3;
+    const int o1p = s1p >> 1, p1p = s1p & 1, o2p = s2p >> 1, p2p = s2p & 1;
+    const int o1 = s1 >> 1, p1 = s1 & 1, o2 = s2 >> 1, p2 = s2 & 1;
+    double gre, gim, hre, him;
+    if (P.has_out) {
+      const int idx = ((o1p * 2 + o2p) * 4 + (o1 * 2 + o2)) * 2;
+      gre = P.gates[idx];
+      gim = P.gates[idx + 1];
+    } else {
+      gre = (o1p == o1 && o2p == o2) ? 1.0 : 0.0;
+      gim = 0.0;
+    }
+    if (P.has_in) {
+      const int idx = 32 + ((p1 * 2 + p2) * 4 + (p1p * 2 + p2p)) * 2;
+      hre = P.gates[idx];
+      him = P.gates[idx + 1];
+    } else {
+      hre = (p1 == p1p && p2 == p2p) ? 1.0 : 0.0;
+      him = 0.0;
+    }
+    Tm[row][col] = cx<T>{(T)(gre * hre - gim * him), (T)(gre * him + gim * hre)};
+  }
+  __syncthreads();
+  const int chir = P.chir, n = 4 * chir;
+  const int total = P.chil * chir;
+  const cx<T>* th0 = (const cx<T>*)P.theta0;
+  cx<T>* thn = (cx<T>*)P.theta_nolam;
+  cx<T>* A = (cx<T>*)P.A;
+  for (int idx = blockIdx.x * 256 + tid; idx < total; idx += gridDim.x * 256) {
+    const int a = idx / chir, b = idx - a * chir;
+    cx<T> in[16];
+#pragma unroll
+    for (int s1 = 0; s1 < 4; ++s1)
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) in[s1 * 4 + s2] = th0[(size_t)(4 * a + s1) * n + s2 * chir + b];
+    const T lam = (T)P.lam[a];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      T re = 0, im = 0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const cx<T> t = Tm[r][c];
+        re += t.re * in[c].re - t.im * in[c].im;
+        im += t.re * in[c].im + t.im * in[c].re;
+      }
+      const int s1p = r >> 2, s2p = r & 3;
+      thn[(size_t)(4 * a + s1p) * n + s2p * chir + b] = cx<T>{re, im};
+      A[(size_t)(s2p * chir + b) * P.lda + 4 * a + s1p] = cx<T>{re * lam, im * lam};
+    }
+  }
+}
+
+// ============================================================== Jacobi SVD
+// Round-robin (circle method) pairing of N items (N even): over N-1 steps
+// every pair meets exactly once; step s pairs (s, N-1) and (s+t, s-t) mod N-1.
+__device__ __forceinline__ void rr_pair(int N, int step, int t, int& a, int& b) {
+  if (t == 0) {
+    a = step;
+    b = N - 1;
+  } else {
+    a = (step + t) % (N - 1);
+    b = (step - t + (N - 1)) % (N - 1);
+  }
+  if (a > b) {
+    const int x = a;
+    a = b;
+    b = x;
+  }
+}
+
+template <typename T>
+__global__ void k_jac_init(JacBatch jb) {
+  const int pi = blockIdx.y;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    P.st->active = 1;
+    P.st->rot = 0;
+    P.st->sweeps = 0;
+  }
+  const size_t npad = (size_t)P.ncol_pad;
+  const size_t nv = P.V ? npad * npad : 0;
+  const size_t na = (size_t)(P.ncol_pad - P.ncol) * P.lda;
+  cx<T>* V = (cx<T>*)P.V;
+  cx<T>* A = (cx<T>*)P.A + (size_t)P.ncol * P.lda;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv + na; i += (size_t)gridDim.x * blockDim.x) {
+    if (i < nv) {
+      const size_t r = i % npad, c = i / npad;
+      V[i] = cx<T>{(T)(r == c ? 1 : 0), (T)0};
+    } else {
+      A[i - nv] = cx<T>{0, 0};
+    }
+  }
+}
+
+struct Rot2 {
+  int px, qx;          // pair of this index
+  double jpr, jpi;     // J[px][x]
+  double jqr, jqi;     // J[qx][x]
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_step(JacBatch jb, int step) {
+  const int pi = blockIdx.y;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
+  if (P.st->active == 0) return;
+  const double tol = P.tol;
+  int bi, bj;
+  rr_pair(P.nblk, step, blockIdx.x, bi, bj);
+
+  __shared__ cx<double> G[2][32][33];
+  __shared__ cx<double> W[2][32][33];
+  __shared__ cx<T> Pc[64][33];
+  __shared__ Rot2 rot[32];
+  __shared__ int flag, anyrot;
+
+  const int tid = threadIdx.x;
+  cx<T>* A = (cx<T>*)P.A;
+  cx<T>* V = (cx<T>*)P.V;
+  const int colbase0 = bi * JB, colbase1 = bj * JB;
+
+  // ---- Gram matrix of the 32-column panel, FP64 accumulation
+  const int gi = tid >> 3, gj0 = (tid & 7) * 4;
+  double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+  for (int r0 = 0; r0 < P.m; r0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = (tid >> 6) + 4 * u;
+      const int r = tid & 63;
+      const int gc = c < JB ? colbase0 + c : colbase1 + c - JB;
+      cx<T> v = {0, 0};
+      if (r0 + r < P.m) v = A[(size_t)gc * P.lda + r0 + r];
+      Pc[r][c] = v;
+    }
+    __syncthreads();
+    const int rmax = min(64, P.m - r0);
+    for (int r = 0; r < rmax; ++r) {
+      const cx<T> x = Pc[r][gi];
+      const double xr = x.re, xi = x.im;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const cx<T> y = Pc[r][gj0 + u];
+        const double yr = y.re, yi = y.im;
+        ar[u] += xr * yr + xi * yi;   // conj(x) * y
+        ai[u] += xr * yi - xi * yr;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) flag = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    G[0][gi][gj0 + u] = cx<double>{ar[u], ai[u]};
+    W[0][gi][gj0 + u] = cx<double>{(gi == gj0 + u) ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  // ---- convergence test of this panel
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = gj0 + u;
+    if (j > gi) {
+      const double d = G[0][gi][gi].re * G[0][j][j].re;
+      const double o = ar[u] * ar[u] + ai[u] * ai[u];
+      if (d > 0 && o > tol * tol * d) flag = 1;
+    }
+  }
+  __syncthreads();
+  if (!flag) return;
+  if (tid == 0) atomicAdd(&P.st->rot, 1);
+
+  // ---- cyclic Jacobi EVD of the 32x32 Hermitian G (FP64), W accumulates J
+  int cur = 0;
+  for (int isw = 0; isw < 16; ++isw) {
+    if (tid == 0) anyrot = 0;
+    __syncthreads();
+    for (int st = 0; st < 31; ++st) {
+      if (tid < 16) {
+        int p, q;
+        rr_pair(32, st, tid, p, q);
+        const double app = G[cur][p][p].re, aqq = G[cur][q][q].re;
+        const cx<double> g = G[cur][p][q];
+        const double mag = sqrt(g.re * g.re + g.im * g.im);
+        double c = 1.0, zr = 0.0, zi = 0.0;
+        if (mag > 0.0 && mag > tol * sqrt(fmax(app * aqq, 0.0))) {
+          const double zeta = (aqq - app) / (2.0 * mag);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          const double s = t * c;
+          zr = s * g.re / mag;
+          zi = s * g.im / mag;
+          anyrot = 1;
+        }
+        // J = [[c, z], [-conj(z), c]] on columns (p, q)
+        rot[p] = Rot2{p, q, c, 0.0, -zr, zi};
+        rot[q] = Rot2{p, q, zr, zi, c, 0.0};
+      }
+      __syncthreads();
+      const int nxt = cur ^ 1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = gi, c = gj0 + u;
+        const Rot2 R = rot[r], C = rot[c];
+        // G'[r][c] = sum_{x in (px,qx) of r} sum_{y in (px,qx) of c} conj(J[x][r]) G[x][y] J[y][c]
+        const cx<double> g00 = G[cur][R.px][C.px], g01 = G[cur][R.px][C.qx];
+        const cx<double> g10 = G[cur][R.qx][C.px], g11 = G[cur][R.qx][C.qx];
+        // h0 = G[px_r][y] J[y][c] summed over y
+        const double h0r = g00.re * C.jpr - g00.im * C.jpi + g01.re * C.jqr - g01.im * C.jqi;
+        const double h0i = g00.re * C.jpi + g00.im * C.jpr + g01.re * C.jqi + g01.im * C.jqr;
+        const double h1r = g10.re * C.jpr - g10.im * C.jpi + g11.re * C.jqr - g11.im * C.jqi;
+        const double h1i = g10.re * C.jpi + g10.im * C.jpr + g11.re * C.jqi + g11.im * C.jqr;
+        // conj(J[px][r]) h0 + conj(J[qx][r]) h1
+        const double gr = R.jpr * h0r + R.jpi * h0i + R.jqr * h1r + R.jqi * h1i;
+        const double gim = R.jpr * h0i - R.jpi * h0r + R.jqr * h1i - R.jqi * h1r;
+        G[nxt][r][c] = cx<double>{gr, gim};
+        // W' = W J
+        const cx<double> w0 = W[cur][r][C.px], w1 = W[cur][r][C.qx];
+        W[nxt][r][c] = cx<double>{w0.re * C.jpr - w0.im * C.jpi + w1.re * C.jqr - w1.im * C.jqi,
+                                  w0.re * C.jpi + w0.im * C.jpr + w1.re * C.jqi + w1.im * C.jqr};
+      }
+      cur = nxt;
+      __syncthreads();
+    }
+    // read the flag before anyone can reset it for the next sweep
+    const int any = anyrot;
+    __syncthreads();
+    if (!any) break;
+  }
+
+  // ---- rotate the panel of theta (m rows) and of V (ncol rows) by W,
+  // applied as x + x (W - I): W - I is rounded to T entry by entry, so the
+  // rounding error each output picks up from another column is relative to
+  // that (small) coupling, not to the other column's norm.
+  cx<T>(*Wt)[33] = Pc;   // reuse: 32 x 32 of the 64 x 33 staging buffer
+  for (int e = tid; e < 32 * 32; e += 256) {
+    const int r = e >> 5, c = e & 31;
+    Wt[r][c] = cx<T>{(T)(W[cur][r][c].re - (r == c ? 1.0 : 0.0)), (T)W[cur][r][c].im};
+  }
+  __syncthreads();
+  const int nrow_v = V ? P.ncol : 0;
+  for (int rr = tid; rr < P.m + nrow_v; rr += 256) {
+    cx<T>* base;
+    size_t ld;
+    int r;
+    if (rr < P.m) {
+      base = A;
+      ld = P.lda;
+      r = rr;
+    } else {
+      base = V;
+      ld = P.ncol_pad;
+      r = rr - P.m;
+    }
+    cx<T> x[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int gc = c < JB ? colbase0 + c : colbase1 + c - JB;
+      x[c] = base[(size_t)gc * ld + r];
+    }
+#pragma unroll 4
+    for (int j = 0; j < 32; ++j) {
+      T re = x[j].re, im = x[j].im;
+#pragma unroll
+      for (int c = 0; c < 32; ++c) {
+        const cx<T> w = Wt[c][j];
+        re += x[c].re * w.re - x[c].im * w.im;
+        im += x[c].re * w.im + x[c].im * w.re;
+      }
+      const int gc = j < JB ? colbase0 + j : colbase1 + j - JB;
+      base[(size_t)gc * ld + r] = cx<T>{re, im};
+    }
+  }
+}
+
+__global__ void k_jac_sweep_end(JacBatch jb) {
+  const int i = threadIdx.x;
+  if (i >= jb.count) return;
+  JacState* s = jb.p[i].st;
+  if (s->active) {
+    s->sweeps += 1;
+    if (s->rot == 0) s->active = 0;
+    s->rot = 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_colnorms(JacBatch jb) {
+  const int pi = blockIdx.y;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= P.ncol_pad) return;
+  const cx<T>* A = (const cx<T>*)P.A + (size_t)col * P.lda;
+  double acc = 0.0;
+  if (col < P.ncol)
+    for (int r = lane; r < P.m; r += 64) {
+      const double xr = A[r].re, xi = A[r].im;
+      acc += xr * xr + xi * xi;
+    }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) P.norms[col] = sqrt(acc);
+}
+
+// ============================================================== sort + truncation
+__global__ __launch_bounds__(1024) void k_sort_trunc(TruncBatch tb) {
+  const int pi = blockIdx.x;
+  if (pi >= tb.count) return;
+  const TruncProb P = tb.p[pi];
+  __shared__ double key[4096];
+  __shared__ int idx[4096];
+  int N2 = 1;
+  while (N2 < P.ncol_pad) N2 <<= 1;
+  for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+    key[i] = (i < P.ncol) ? P.norms[i] : -1.0;
+    idx[i] = i;
+  }
+  __syncthreads();
+  // bitonic sort: descending key, ascending index on ties
+  for (int k = 2; k <= N2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = ((i & k) == 0);
+          const double ki = key[i], kl = key[l];
+          const int ii = idx[i], il = idx[l];
+          // "before(x, y)": x sorts ahead of y
+          const bool l_before_i = (kl > ki) || (kl == ki && il < ii);
+          if (up ? l_before_i : !l_before_i) {
+            key[i] = kl;
+            key[l] = ki;
+            idx[i] = il;
+            idx[l] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < P.ncol; i += blockDim.x) {
+    P.s_sorted[i] = key[i] > 0.0 ? key[i] : 0.0;
+    P.perm[i] = idx[i];
+  }
+  if (threadIdx.x == 0) {
+    const int nvals = P.nval;
+    int bad = 0;
+    double total = 0.0;
+    for (int j = nvals - 1; j >= 0; --j) {
+      const double s = key[j] > 0.0 ? key[j] : 0.0;
+      if (!isfinite(s)) bad = 1;
+      total += s * s;
+    }
+    const double s0 = key[0] > 0.0 ? key[0] : 0.0;
+    int k;
+    if (tb.mode == 0) {
+      k = 0;
+      for (int j = 0; j < nvals; ++j)
+        if (key[j] > tb.cutoff * s0) ++k;
+    } else {
+      const double thr = tb.cutoff * total;
+      double tail = 0.0;
+      k = 0;
+      for (int j = nvals - 1; j >= 0; --j) {
+        const double s = key[j] > 0.0 ? key[j] : 0.0;
+        tail += s * s;
+        if (tail > thr) {
+          k = j + 1;
+          break;
+        }
+      }
+    }
+    if (k > tb.chi_max) k = tb.chi_max;
+    if (k > nvals) k = nvals;
+    if (k < 1) k = 1;
+    double disc = 0.0;
+    for (int j = nvals - 1; j >= k; --j) {
+      const double s = key[j] > 0.0 ? key[j] : 0.0;
+      disc += s * s;
+    }
+    P.res->k = k;
+    P.res->nvals = nvals;
+    P.res->discarded = disc;
+    P.res->total = total;
+    P.res->s0 = s0;
+    P.res->bad = bad || !isfinite(total);
+  }
+}
+
+// ============================================================== write-back
+template <typename T>
+__global__ __launch_bounds__(256) void k_wb_gather(WbBatch wb) {
+  const int pi = blockIdx.y;
+  if (pi >= wb.count) return;
+  const WbProb P = wb.p[pi];
+  const cx<T>* V = (const cx<T>*)P.V;
+  cx<T>* R = (cx<T>*)P.right;
+  const size_t total = (size_t)P.k * P.ncol;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const int j = (int)(e / P.ncol), c = (int)(e - (size_t)j * P.ncol);
+    const cx<T> v = V[(size_t)P.perm[j] * P.ldv + c];
+    R[e] = cx<T>{v.re, -v.im};
+    if (c == 0) P.lam[j] = P.s_sorted[j];
+  }
+}
+
+// ============================================================== peak readout
+// C[i][j] (+)= sum_k opA(i,k) opB(k,j); opX(i,k) = X[off + i*s0 + k*s1] (conj if cX)
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_zgemm_small(cx<double>* C, int ldc, const cx<TA>* A, long long as0,
+                                                      long long as1, int cA, const cx<TB>* B, long long bs0,
+                                                      long long bs1, int cB, int M, int N, int K, int beta) {
+  __shared__ cx<double> As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+  double cr = 0, ci = 0;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    {
+      const int ii = blockIdx.y * 16 + ty, kk = k0 + tx;
+      cx<double> v = {0, 0};
+      if (ii < M && kk < K) {
+        const cx<TA> x = A[ii * as0 + kk * as1];
+        v = cx<double>{(double)x.re, cA ? -(double)x.im : (double)x.im};
+      }
+      As[ty][tx] = v;
+    }
+    {
+      const int kk = k0 + ty, jj = blockIdx.x * 16 + tx;
+      cx<double> v = {0, 0};
+      if (kk < K && jj < N) {
+        const cx<TB> x = B[kk * bs0 + jj * bs1];
+        v = cx<double>{(double)x.re, cB ? -(double)x.im : (double)x.im};
+      }
+      Bs[ty][tx] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const cx<double> a = As[ty][k], b = Bs[k][tx];
+      cr += a.re * b.re - a.im * b.im;
+      ci += a.re * b.im + a.im * b.re;
+    }
+    __syncthreads();
+  }
+  if (i < M && j < N) {
+    cx<double>* c = C + (size_t)i * ldc + j;
+    if (beta) {
+      c->re += cr;
+      c->im += ci;
+    } else {
+      *c = cx<double>{cr, ci};
+    }
+  }
+}
+
+// One workgroup: w_o = v A_o (o = 0, 1), p_o = w_o E w_o^dag, pick the larger
+// (ties -> 0), v <- w_o / |w_o|, accumulate log of the conditional.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_greedy(const cx<T>* site, int chil, int chir, const cx<double>* E,
+                                                 const cx<double>* v, cx<double>* vout, cx<double>* work,
+                                                 unsigned char* bit_out, double* logp) {
+  __shared__ double red[2][1024];
+  __shared__ int choice;
+  __shared__ double nrm;
+  const int tid = threadIdx.x;
+  cx<double>* w0 = work;
+  cx<double>* w1 = work + chir;
+  for (int b = tid; b < chir; b += blockDim.x) {
+    double r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+    for (int a = 0; a < chil; ++a) {
+      const cx<double> va = v[a];
+      const cx<T> x0 = site[(size_t)a * 4 * chir + 0 * chir + b];
+      const cx<T> x1 = site[(size_t)a * 4 * chir + 2 * chir + b];
+      r0 += va.re * (double)x0.re - va.im * (double)x0.im;
+      i0 += va.re * (double)x0.im + va.im * (double)x0.re;
+      r1 += va.re * (double)x1.re - va.im * (double)x1.im;
+      i1 += va.re * (double)x1.im + va.im * (double)x1.re;
+    }
+    w0[b] = cx<double>{r0, i0};
+    w1[b] = cx<double>{r1, i1};
+  }
+  __syncthreads();
+  double p0 = 0, p1 = 0;
+  for (int b = tid; b < chir; b += blockDim.x) {
+    // y_o[b] = sum_b' E[b][b'] conj(w_o[b']);  p_o += w_o[b] y_o[b]
+    double y0r = 0, y0i = 0, y1r = 0, y1i = 0;
+    for (int bp = 0; bp < chir; ++bp) {
+      const cx<double> e = E[(size_t)b * chir + bp];
+      const cx<double> a0 = w0[bp], a1 = w1[bp];
+      y0r += e.re * a0.re + e.im * a0.im;
+      y0i += e.im * a0.re - e.re * a0.im;
+      y1r += e.re * a1.re + e.im * a1.im;
+      y1i += e.im * a1.re - e.re * a1.im;
+    }
+    p0 += w0[b].re * y0r - w0[b].im * y0i;
+    p1 += w1[b].re * y1r - w1[b].im * y1i;
+  }
+  red[0][tid] = p0;
+  red[1][tid] = p1;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      red[0][tid] += red[0][tid + s];
+      red[1][tid] += red[1][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double q0 = red[0][0], q1 = red[1][0];
+    const int o = (q1 > q0) ? 1 : 0;
+    choice = o;
+    *bit_out = (unsigned char)o;
+    *logp += log((o ? q1 : q0) / (q0 + q1));
+  }
+  __syncthreads();
+  const cx<double>* w = choice ? w1 : w0;
+  double ss = 0;
+  for (int b = tid; b < chir; b += blockDim.x) ss += w[b].re * w[b].re + w[b].im * w[b].im;
+  red[0][tid] = ss;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[0][tid] += red[0][tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) nrm = sqrt(red[0][0]);
+  __syncthreads();
+  const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  for (int b = tid; b < chir; b += blockDim.x) vout[b] = cx<double>{w[b].re * inv, w[b].im * inv};
+}
+
+template <typename TD, typename TS>
+__global__ void k_convert(cx<TD>* dst, const cx<TS>* src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = cx<TD>{(TD)src[i].re, (TD)src[i].im};
+}
+
+// ============================================================== launchers
+template <typename T>
+void launch_gemm(const GemmBatch& b, int maxM, int maxN, hipStream_t s) {
+  dim3 grid((maxN + GT - 1) / GT, (maxM + GT - 1) / GT, b.count);
+  hipLaunchKernelGGL(k_gemm<T>, grid, dim3(256), 0, s, b);
+}
+template <typename T>
+void launch_gate(const GateBatch& b, int maxtotal, hipStream_t s) {
+  int gx = (maxtotal + 255) / 256;
+  if (gx > 512) gx = 512;
+  if (gx < 1) gx = 1;
+  hipLaunchKernelGGL(k_gate<T>, dim3(gx, b.count), dim3(256), 0, s, b);
+}
+template <typename T>
+void launch_jac_init(const JacBatch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_init<T>, dim3(256, b.count), dim3(256), 0, s, b);
+}
+template <typename T>
+void launch_jac_step(const JacBatch& b, int maxpairs, int step, hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_step<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step);
+}
+void launch_jac_sweep_end(const JacBatch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_sweep_end, dim3(1), dim3(64), 0, s, b);
+}
+template <typename T>
+void launch_colnorms(const JacBatch& b, int maxcols, hipStream_t s) {
+  hipLaunchKernelGGL(k_colnorms<T>, dim3((maxcols + 3) / 4, b.count), dim3(256), 0, s, b);
+}
+void launch_sort_trunc(const TruncBatch& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_trunc, dim3(b.count), dim3(1024), 0, s, b);
+}
+template <typename T>
+void launch_wb_gather(const WbBatch& b, size_t maxelems, hipStream_t s) {
+  size_t gx = (maxelems + 255) / 256;
+  if (gx > 1024) gx = 1024;
+  if (gx < 1) gx = 1;
+  hipLaunchKernelGGL(k_wb_gather<T>, dim3((unsigned)gx, b.count), dim3(256), 0, s, b);
+}
+template <typename TA, typename TB>
+void launch_zgemm_small(cx<double>* C, int ldc, const cx<TA>* A, long long as0, long long as1, int cA,
+                        const cx<TB>* B, long long bs0, long long bs1, int cB, int M, int N, int K, int beta,
+                        hipStream_t s) {
+  dim3 grid((N + 15) / 16, (M + 15) / 16);
+  hipLaunchKernelGGL((k_zgemm_small<TA, TB>), grid, dim3(256), 0, s, C, ldc, A, as0, as1, cA, B, bs0, bs1, cB, M,
+                     N, K, beta);
+}
+template <typename T>
+void launch_greedy(const cx<T>* site, int chil, int chir, const cx<double>* E, const cx<double>* v,
+                   cx<double>* vout, cx<double>* work, unsigned char* bit, double* logp, hipStream_t s) {
+  hipLaunchKernelGGL(k_greedy<T>, dim3(1), dim3(1024), 0, s, site, chil, chir, E, v, vout, work, bit, logp);
+}
+template <typename TD, typename TS>
+void launch_convert(cx<TD>* d, const cx<TS>* src, size_t n, hipStream_t s) {
+  size_t g = (n + 255) / 256;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL((k_convert<TD, TS>), dim3((unsigned)g), dim3(256), 0, s, d, src, n);
+}
+
+#define INST(T)                                                                                          \
+  template void launch_gemm<T>(const GemmBatch&, int, int, hipStream_t);                                 \
+  template void launch_gate<T>(const GateBatch&, int, hipStream_t);                                      \
+  template void launch_jac_init<T>(const JacBatch&, hipStream_t);                                        \
+  template void launch_jac_step<T>(const JacBatch&, int, int, hipStream_t);                      \
+  template void launch_colnorms<T>(const JacBatch&, int, hipStream_t);                                   \
+  template void launch_wb_gather<T>(const WbBatch&, size_t, hipStream_t);                                \
+  template void launch_greedy<T>(const cx<T>*, int, int, const cx<double>*, const cx<double>*,           \
+                                 cx<double>*, cx<double>*, unsigned char*, double*, hipStream_t);
+
+INST(float)
+INST(double)
+
+#define INST2(TA, TB)                                                                                    \
+  template void launch_zgemm_small<TA, TB>(cx<double>*, int, const cx<TA>*, long long, long long, int,   \
+                                           const cx<TB>*, long long, long long, int, int, int, int, int, \
+                                           hipStream_t);                                                 \
+  template void launch_convert<TA, TB>(cx<TA>*, const cx<TB>*, size_t, hipStream_t);
+
+INST2(float, double)
+INST2(double, float)
+INST2(double, double)
+
+}  // namespace mpo

@@ -1,0 +1,820 @@
+// Host runtime and C ABI of libmpo (see include/mpo.h for the contract).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "mpo.h"
+
+namespace mpo {
+template <typename T> void launch_gemm(const GemmBatch&, int, int, hipStream_t);
+template <typename T> void launch_gate(const GateBatch&, int, hipStream_t);
+template <typename T> void launch_jac_init(const JacBatch&, hipStream_t);
+template <typename T> void launch_jac_step(const JacBatch&, int, int, hipStream_t);
+void launch_jac_sweep_end(const JacBatch&, hipStream_t);
+template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
+void launch_sort_trunc(const TruncBatch&, hipStream_t);
+template <typename T> void launch_wb_gather(const WbBatch&, size_t, hipStream_t);
+template <typename TA, typename TB>
+void launch_zgemm_small(cx<double>*, int, const cx<TA>*, long long, long long, int, const cx<TB>*, long long,
+                        long long, int, int, int, int, int, hipStream_t);
+template <typename T>
+void launch_greedy(const cx<T>*, int, int, const cx<double>*, const cx<double>*, cx<double>*, cx<double>*,
+                   unsigned char*, double*, hipStream_t);
+template <typename TD, typename TS> void launch_convert(cx<TD>*, const cx<TS>*, size_t, hipStream_t);
+}  // namespace mpo
+
+using namespace mpo;
+
+namespace {
+
+constexpr double WEIGHT_TIE_REL = 1e-9;   // L/R/B trials with closer discarded weights tie
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+inline void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError{e, what};
+}
+struct NoMem {};
+
+// Workspace of one problem in a batch; grows on demand, never shrinks.
+struct Slot {
+  void* theta0 = nullptr;
+  void* thetan = nullptr;
+  void* A = nullptr;
+  void* V = nullptr;
+  double* norms = nullptr;
+  double* s_sorted = nullptr;
+  int* perm = nullptr;
+  size_t cap_mn = 0, cap_A = 0, cap_V = 0, cap_n = 0;
+};
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+void* dalloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    throw NoMem{};
+  }
+  return p;
+}
+
+struct Req {
+  int bond;
+  const double* gout;   // 32 doubles or NULL
+  const double* gin;
+};
+struct Res {
+  int k = 0;
+  int sweeps = 0;
+  bool noconv = false;
+  bool bad = false;
+  double disc = 0, total = 0;
+};
+
+}  // namespace
+
+struct mpo_ctx {
+  mpo_config_t cfg{};
+  int prec = 0;
+  size_t esz = 16;
+  hipStream_t stream = nullptr;
+  int n = 0;
+  int max_sweeps = 30;
+  std::vector<int> chi;           // chi[0] = chi[n] = 1, chi[i+1] = bond i
+  std::vector<int> bond_cap;      // per bond
+  std::vector<void*> site;
+  std::vector<size_t> site_cap;   // complex elements
+  std::vector<double*> lam;       // per bond
+  double* ones = nullptr;
+  std::vector<Slot> slots;
+  JacState* states = nullptr;
+  TruncResult* results = nullptr;
+  JacState* h_states = nullptr;
+  TruncResult* h_results = nullptr;
+  double* d_gates = nullptr;
+  double* h_gates = nullptr;
+  std::string err;
+  size_t bytes_allocated = 0;
+  // kernel timing (mpo_profile): launches bracketed by events on `stream`
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  double prof_ms[MPO_PROF_CLASSES] = {0};
+  int64_t prof_n[MPO_PROF_CLASSES] = {0};
+};
+
+namespace {
+
+mpo_status_t fail(mpo_ctx* h, mpo_status_t st, const std::string& msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+hipEvent_t take_event(mpo_ctx* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  hip_check(hipEventCreate(&e), "event create");
+  return e;
+}
+
+// Runs `launch` bracketed by two events when profiling is on.
+template <typename F>
+void timed(mpo_ctx* h, int cls, F&& launch) {
+  if (!h->prof_on) {
+    launch();
+    return;
+  }
+  hipEvent_t a = take_event(h), b = take_event(h);
+  hip_check(hipEventRecord(a, h->stream), "event record");
+  launch();
+  hip_check(hipEventRecord(b, h->stream), "event record");
+  h->pending.push_back(mpo_ctx::Pending{cls, a, b});
+}
+
+// Called after a stream synchronisation: every pending event has completed.
+void drain_events(mpo_ctx* h) {
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, p.a, p.b), "event elapsed");
+    h->prof_ms[p.cls] += ms;
+    h->prof_n[p.cls] += 1;
+    h->ev_pool.push_back(p.a);
+    h->ev_pool.push_back(p.b);
+  }
+  h->pending.clear();
+}
+
+double tol_for(const mpo_ctx* h, int m) {
+  if (h->cfg.jacobi_tol > 0) return h->cfg.jacobi_tol;
+  const double eps = (h->prec == MPO_FP64) ? 1.1102230246251565e-16 : 5.960464477539063e-08;
+  return std::max(8.0 * std::sqrt((double)std::max(m, 1)) * eps, eps * 4);
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+void ensure_slot(mpo_ctx* h, Slot& s, size_t mn, size_t nA, size_t nV, size_t nn) {
+  const size_t e = h->esz;
+  if (s.cap_mn < mn) {
+    dfree(s.theta0);
+    dfree(s.thetan);
+    s.theta0 = s.thetan = nullptr;
+    s.cap_mn = 0;
+    s.theta0 = dalloc(mn * e);
+    s.thetan = dalloc(mn * e);
+    s.cap_mn = mn;
+  }
+  if (s.cap_A < nA) {
+    dfree(s.A);
+    s.A = nullptr;
+    s.cap_A = 0;
+    s.A = dalloc(nA * e);
+    s.cap_A = nA;
+  }
+  if (nV && s.cap_V < nV) {
+    dfree(s.V);
+    s.V = nullptr;
+    s.cap_V = 0;
+    s.V = dalloc(nV * e);
+    s.cap_V = nV;
+  }
+  if (s.cap_n < nn) {
+    dfree(s.norms);
+    dfree(s.s_sorted);
+    dfree(s.perm);
+    s.norms = nullptr;
+    s.s_sorted = nullptr;
+    s.perm = nullptr;
+    s.cap_n = 0;
+    s.norms = (double*)dalloc(nn * sizeof(double));
+    s.s_sorted = (double*)dalloc(nn * sizeof(double));
+    s.perm = (int*)dalloc(nn * sizeof(int));
+    s.cap_n = nn;
+  }
+}
+
+bool finite_gate(const double* g) {
+  if (!g) return true;
+  for (int i = 0; i < 32; ++i)
+    if (!std::isfinite(g[i])) return false;
+  return true;
+}
+
+// One batch (<= MAXB problems): theta-build, gate, Jacobi SVD, truncation;
+// with `commit` the new tensors are written (bonds must be pairwise
+// non-adjacent).  Returns per-problem results.  Throws HipError / NoMem.
+template <typename T>
+mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool commit) {
+  hipStream_t st = h->stream;
+  struct Shape {
+    int i, chil, chim, chir, m, ncol, ncol_pad, nblk;
+  };
+  Shape sh[MAXB];
+  int maxM = 0, maxN = 0, maxtot = 0, maxcols = 0, maxpairs = 0, maxblk = 0;
+  for (int p = 0; p < count; ++p) {
+    Shape& s = sh[p];
+    s.i = reqs[p].bond;
+    s.chil = h->chi[s.i];
+    s.chim = h->chi[s.i + 1];
+    s.chir = h->chi[s.i + 2];
+    s.m = 4 * s.chil;
+    s.ncol = 4 * s.chir;
+    s.ncol_pad = round_up(s.ncol, 2 * JB);
+    s.nblk = s.ncol_pad / JB;
+    maxM = std::max(maxM, s.m);
+    maxN = std::max(maxN, s.ncol);
+    maxtot = std::max(maxtot, s.chil * s.chir);
+    maxcols = std::max(maxcols, s.ncol_pad);
+    maxpairs = std::max(maxpairs, s.nblk / 2);
+    maxblk = std::max(maxblk, s.nblk);
+    ensure_slot(h, h->slots[p], (size_t)s.m * s.ncol, (size_t)s.m * s.ncol_pad,
+                commit ? (size_t)s.ncol_pad * s.ncol_pad : 0, (size_t)s.ncol_pad);
+  }
+  // gates -> pinned staging -> device (the staging buffer is free: every
+  // call ends with a stream synchronisation)
+  for (int p = 0; p < count; ++p) {
+    double* g = h->h_gates + 64 * p;
+    if (reqs[p].gout) std::memcpy(g, reqs[p].gout, 32 * sizeof(double));
+    else std::memset(g, 0, 32 * sizeof(double));
+    if (reqs[p].gin) std::memcpy(g + 32, reqs[p].gin, 32 * sizeof(double));
+    else std::memset(g + 32, 0, 32 * sizeof(double));
+  }
+  hip_check(hipMemcpyAsync(h->d_gates, h->h_gates, (size_t)count * 64 * sizeof(double), hipMemcpyHostToDevice, st),
+            "gate upload");
+
+  GemmBatch gb{};
+  gb.count = count;
+  for (int p = 0; p < count; ++p) {
+    const Shape& s = sh[p];
+    gb.p[p] = GemmProb{h->site[s.i], h->site[s.i + 1], h->slots[p].theta0, s.m, s.ncol, s.chim,
+                       s.chim, s.ncol, s.ncol, 0};
+  }
+  timed(h, MPO_PROF_THETA_GEMM, [&] { launch_gemm<T>(gb, maxM, maxN, st); });
+
+  GateBatch tb{};
+  tb.count = count;
+  for (int p = 0; p < count; ++p) {
+    const Shape& s = sh[p];
+    tb.p[p] = GateProb{h->slots[p].theta0, h->slots[p].thetan, h->slots[p].A,
+                       s.i > 0 ? h->lam[s.i - 1] : h->ones, h->d_gates + 64 * p, s.chil, s.chir, s.m,
+                       reqs[p].gout != nullptr, reqs[p].gin != nullptr};
+  }
+  timed(h, MPO_PROF_GATE, [&] { launch_gate<T>(tb, maxtot, st); });
+
+  JacBatch jb{};
+  jb.count = count;
+  for (int p = 0; p < count; ++p) {
+    const Shape& s = sh[p];
+    jb.p[p] = JacProb{h->slots[p].A, commit ? h->slots[p].V : nullptr, h->states + p, h->slots[p].norms,
+                      tol_for(h, s.m), s.m, s.m, s.ncol, s.ncol_pad, s.nblk};
+  }
+  timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
+  int sweeps_run = 0;
+  bool active_left = true;
+  for (int sw = 0; sw < h->max_sweeps && active_left; ++sw) {
+    for (int step = 0; step < maxblk - 1; ++step)
+      timed(h, MPO_PROF_JACOBI_STEP, [&] { launch_jac_step<T>(jb, maxpairs, step, st); });
+    launch_jac_sweep_end(jb, st);
+    hip_check(hipMemcpyAsync(h->h_states, h->states, count * sizeof(JacState), hipMemcpyDeviceToHost, st),
+              "state readback");
+    hip_check(hipStreamSynchronize(st), "sweep sync");
+    drain_events(h);
+    ++sweeps_run;
+    active_left = false;
+    for (int p = 0; p < count; ++p) active_left |= (h->h_states[p].active != 0);
+  }
+  timed(h, MPO_PROF_FINALIZE, [&] { launch_colnorms<T>(jb, maxcols, st); });
+  TruncBatch trb{};
+  trb.count = count;
+  trb.chi_max = h->cfg.chi_max;
+  trb.mode = h->cfg.cutoff_mode;
+  trb.cutoff = h->cfg.cutoff;
+  for (int p = 0; p < count; ++p) {
+    const Shape& s = sh[p];
+    trb.p[p] = TruncProb{h->slots[p].norms, h->slots[p].s_sorted, h->slots[p].perm, h->results + p, s.ncol,
+                         s.ncol_pad, std::min(s.m, s.ncol)};
+  }
+  timed(h, MPO_PROF_FINALIZE, [&] { launch_sort_trunc(trb, st); });
+  hip_check(hipMemcpyAsync(h->h_results, h->results, count * sizeof(TruncResult), hipMemcpyDeviceToHost, st),
+            "result readback");
+  hip_check(hipStreamSynchronize(st), "result sync");
+  drain_events(h);
+  bool anybad = false;
+  for (int p = 0; p < count; ++p) {
+    out[p].k = h->h_results[p].k;
+    out[p].disc = h->h_results[p].discarded;
+    out[p].total = h->h_results[p].total;
+    out[p].bad = h->h_results[p].bad != 0;
+    out[p].sweeps = h->h_states[p].sweeps;
+    out[p].noconv = h->h_states[p].active != 0;
+    anybad |= out[p].bad;
+  }
+  if (anybad) return fail(h, MPO_ENUMERIC, "non-finite singular values");
+  if (!commit) return MPO_OK;
+
+  WbBatch wb{};
+  wb.count = count;
+  size_t maxel = 0;
+  GemmBatch lb{};
+  lb.count = count;
+  int maxK = 0;
+  for (int p = 0; p < count; ++p) {
+    const Shape& s = sh[p];
+    const int k = out[p].k;
+    wb.p[p] = WbProb{h->slots[p].V, h->slots[p].perm, h->slots[p].s_sorted, h->site[s.i + 1], h->lam[s.i],
+                     s.ncol_pad, s.ncol, k};
+    maxel = std::max(maxel, (size_t)k * s.ncol);
+    lb.p[p] = GemmProb{h->slots[p].thetan, h->site[s.i + 1], h->site[s.i], s.m, k, s.ncol, s.ncol, s.ncol, k, 1};
+    maxK = std::max(maxK, k);
+  }
+  timed(h, MPO_PROF_WRITEBACK, [&] { launch_wb_gather<T>(wb, maxel, st); });
+  timed(h, MPO_PROF_WRITEBACK_GEMM, [&] { launch_gemm<T>(lb, maxM, maxK, st); });
+  for (int p = 0; p < count; ++p) h->chi[sh[p].i + 1] = out[p].k;
+  return MPO_OK;
+}
+
+template <typename T>
+mpo_status_t run_updates(mpo_ctx* h, const std::vector<Req>& reqs, std::vector<Res>& res, bool commit) {
+  res.assign(reqs.size(), Res{});
+  for (size_t b = 0; b < reqs.size(); b += MAXB) {
+    const int cnt = (int)std::min<size_t>(MAXB, reqs.size() - b);
+    mpo_status_t s = run_batch<T>(h, reqs.data() + b, cnt, res.data() + b, commit);
+    if (s != MPO_OK) return s;
+  }
+  return MPO_OK;
+}
+
+mpo_status_t updates(mpo_ctx* h, const std::vector<Req>& reqs, std::vector<Res>& res, bool commit) {
+  if (h->prec == MPO_FP64) return run_updates<double>(h, reqs, res, commit);
+  return run_updates<float>(h, reqs, res, commit);
+}
+
+template <typename F>
+mpo_status_t guarded(mpo_ctx* h, F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    return fail(h, MPO_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+  } catch (const NoMem&) {
+    return fail(h, MPO_ENOMEM, "device allocation failed");
+  } catch (const std::bad_alloc&) {
+    return fail(h, MPO_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(h, MPO_EHIP, "unexpected exception");
+  }
+}
+
+const double SWAP_G[32] = {1, 0, 0, 0, 0, 0, 0, 0,  0, 0, 0, 0, 1, 0, 0, 0,
+                           0, 0, 1, 0, 0, 0, 0, 0,  0, 0, 0, 0, 0, 0, 1, 0};
+
+Req swap_req(int bond, int side) {
+  return Req{bond, (side == 0 || side == 2) ? SWAP_G : nullptr, (side == 1 || side == 2) ? SWAP_G : nullptr};
+}
+
+template <typename T>
+mpo_status_t extract_impl(mpo_ctx* h, uint8_t* bits, double* prob, double* norm2) {
+  hipStream_t st = h->stream;
+  const int n = h->n;
+  std::vector<size_t> eoff(n + 2, 0);
+  for (int i = 0; i <= n; ++i) eoff[i + 1] = eoff[i] + (size_t)h->chi[i] * h->chi[i];
+  int maxchi = 1;
+  for (int i = 0; i <= n; ++i) maxchi = std::max(maxchi, h->chi[i]);
+  const size_t bytes = (eoff[n + 1] + (size_t)maxchi * maxchi + 6 * (size_t)maxchi + 8) * sizeof(cx<double>) + n + 64;
+  char* buf = (char*)dalloc(bytes);
+  struct Free {
+    char* p;
+    ~Free() { dfree(p); }
+  } guard{buf};
+  cx<double>* E = (cx<double>*)buf;
+  cx<double>* tmp = E + eoff[n + 1];
+  cx<double>* v0 = tmp + (size_t)maxchi * maxchi;
+  cx<double>* v1 = v0 + maxchi;
+  cx<double>* work = v1 + maxchi;
+  double* logp = (double*)(work + 4 * maxchi);
+  unsigned char* dbits = (unsigned char*)(logp + 2);
+  const cx<double> one{1.0, 0.0};
+  hip_check(hipMemcpyAsync(E + eoff[n], &one, sizeof(one), hipMemcpyHostToDevice, st), "env init");
+  hip_check(hipMemcpyAsync(v0, &one, sizeof(one), hipMemcpyHostToDevice, st), "v init");
+  hip_check(hipMemsetAsync(logp, 0, sizeof(double), st), "logp init");
+  for (int i = n - 1; i >= 0; --i) {
+    const int cl = h->chi[i], cr = h->chi[i + 1];
+    const cx<T>* s = (const cx<T>*)h->site[i];
+    for (int o = 0; o < 2; ++o) {
+      launch_zgemm_small<T, double>(tmp, cr, s + 2 * o * cr, 4LL * cr, 1, 0, E + eoff[i + 1], cr, 1, 0, cl, cr, cr,
+                                    0, st);
+      launch_zgemm_small<double, T>(E + eoff[i], cl, tmp, cr, 1, 0, s + 2 * o * cr, 1, 4LL * cr, 1, cl, cl, cr, o,
+                                    st);
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    const int cl = h->chi[i], cr = h->chi[i + 1];
+    launch_greedy<T>((const cx<T>*)h->site[i], cl, cr, E + eoff[i + 1], (i % 2 == 0) ? v0 : v1,
+                     (i % 2 == 0) ? v1 : v0, work, dbits + i, logp, st);
+  }
+  std::vector<unsigned char> hb(n);
+  double lp = 0;
+  cx<double> e0{0, 0};
+  hip_check(hipMemcpyAsync(hb.data(), dbits, n, hipMemcpyDeviceToHost, st), "bits readback");
+  hip_check(hipMemcpyAsync(&lp, logp, sizeof(double), hipMemcpyDeviceToHost, st), "logp readback");
+  hip_check(hipMemcpyAsync(&e0, E, sizeof(e0), hipMemcpyDeviceToHost, st), "norm readback");
+  hip_check(hipStreamSynchronize(st), "extract sync");
+  if (!std::isfinite(lp) || !std::isfinite(e0.re)) return fail(h, MPO_ENUMERIC, "non-finite peak probability");
+  if (bits)
+    for (int i = 0; i < n; ++i) bits[i] = hb[i];
+  if (prob) *prob = std::exp(lp);
+  if (norm2) *norm2 = e0.re;
+  return MPO_OK;
+}
+
+int64_t pow4_capped(int e, int64_t cap) {
+  int64_t v = 1;
+  for (int i = 0; i < e; ++i) {
+    v *= 4;
+    if (v >= cap) return cap;
+  }
+  return std::min(v, cap);
+}
+
+void destroy(mpo_ctx* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->site) dfree(p);
+  for (double* p : h->lam) dfree(p);
+  for (Slot& s : h->slots) {
+    dfree(s.theta0);
+    dfree(s.thetan);
+    dfree(s.A);
+    dfree(s.V);
+    dfree(s.norms);
+    dfree(s.s_sorted);
+    dfree(s.perm);
+  }
+  for (auto& p : h->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  dfree(h->ones);
+  dfree(h->states);
+  dfree(h->results);
+  dfree(h->d_gates);
+  if (h->h_states) (void)hipHostFree(h->h_states);
+  if (h->h_results) (void)hipHostFree(h->h_results);
+  if (h->h_gates) (void)hipHostFree(h->h_gates);
+  delete h;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+extern "C" {
+
+const char* mpo_version(void) {
+  return "libmpo 0.1 gfx950: MFMA complex GEMM (f32/f64), block one-sided Jacobi SVD with FP64 angles";
+}
+
+mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_handle_t* out) {
+  if (!cfg || !out) return MPO_EINVAL;
+  *out = nullptr;
+  if (cfg->n < 2 || cfg->chi_max < 1 || cfg->chi_max > 1024 || !(cfg->cutoff >= 0) ||
+      (cfg->cutoff_mode != MPO_CUT_REL_SV && cfg->cutoff_mode != MPO_CUT_DISCARDED_WEIGHT) ||
+      cfg->precision < MPO_FP64 || cfg->precision > MPO_MIXED_SPLITBF16 || cfg->max_sweeps < 0)
+    return MPO_EINVAL;
+  mpo_ctx* h = new (std::nothrow) mpo_ctx();
+  if (!h) return MPO_ENOMEM;
+  h->cfg = *cfg;
+  h->prec = cfg->precision;
+  h->esz = (cfg->precision == MPO_FP64) ? 16 : 8;
+  h->stream = (hipStream_t)hip_stream;
+  h->n = cfg->n;
+  h->max_sweeps = cfg->max_sweeps > 0 ? cfg->max_sweeps : 30;
+  mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
+    const int n = h->n;
+    h->chi.assign(n + 1, 1);
+    h->bond_cap.resize(n - 1);
+    for (int b = 0; b < n - 1; ++b)
+      h->bond_cap[b] = (int)pow4_capped(std::min(b + 1, n - 1 - b), cfg->chi_max);
+    h->site.assign(n, nullptr);
+    h->site_cap.assign(n, 0);
+    h->lam.assign(n - 1, nullptr);
+    for (int i = 0; i < n; ++i) {
+      const size_t cl = i > 0 ? h->bond_cap[i - 1] : 1, cr = i < n - 1 ? h->bond_cap[i] : 1;
+      h->site_cap[i] = cl * 4 * cr;
+      h->site[i] = dalloc(h->site_cap[i] * h->esz);
+    }
+    for (int b = 0; b < n - 1; ++b) h->lam[b] = (double*)dalloc(h->bond_cap[b] * sizeof(double));
+    h->ones = (double*)dalloc(sizeof(double));
+    h->slots.assign(MAXB, Slot{});
+    h->states = (JacState*)dalloc(MAXB * sizeof(JacState));
+    h->results = (TruncResult*)dalloc(MAXB * sizeof(TruncResult));
+    h->d_gates = (double*)dalloc(MAXB * 64 * sizeof(double));
+    hip_check(hipHostMalloc((void**)&h->h_states, MAXB * sizeof(JacState), hipHostMallocDefault), "pinned");
+    hip_check(hipHostMalloc((void**)&h->h_results, MAXB * sizeof(TruncResult), hipHostMallocDefault), "pinned");
+    hip_check(hipHostMalloc((void**)&h->h_gates, MAXB * 64 * sizeof(double), hipHostMallocDefault), "pinned");
+    const double one = 1.0;
+    const double hv = 0.70710678118654752440;
+    const double idd[8] = {hv, 0, 0, 0, 0, 0, hv, 0};
+    const float idf[8] = {(float)hv, 0, 0, 0, 0, 0, (float)hv, 0};
+    for (int i = 0; i < n; ++i)
+      hip_check(hipMemcpyAsync(h->site[i], h->prec == MPO_FP64 ? (const void*)idd : (const void*)idf, 4 * h->esz,
+                               hipMemcpyHostToDevice, h->stream),
+                "identity");
+    for (int b = 0; b < n - 1; ++b)
+      hip_check(hipMemcpyAsync(h->lam[b], &one, sizeof(double), hipMemcpyHostToDevice, h->stream), "lambda init");
+    hip_check(hipMemcpyAsync(h->ones, &one, sizeof(double), hipMemcpyHostToDevice, h->stream), "ones");
+    hip_check(hipStreamSynchronize(h->stream), "init sync");
+    return MPO_OK;
+  });
+  if (s != MPO_OK) {
+    destroy(h);
+    return s;
+  }
+  *out = h;
+  return MPO_OK;
+}
+
+void mpo_free(mpo_handle_t h) { destroy(h); }
+
+static mpo_status_t absorb_common(mpo_handle_t h, int32_t count, const int32_t* bonds, const double* g_out,
+                                  const double* g_in, mpo_update_info_t* info, bool batch_form) {
+  if (!h) return MPO_EINVAL;
+  if (count < 0 || (count > 0 && !bonds)) return fail(h, MPO_EINVAL, "bad count/bonds");
+  std::vector<Req> reqs(count);
+  std::vector<int> sorted;
+  for (int p = 0; p < count; ++p) {
+    const int b = bonds[p];
+    if (b < 0 || b > h->n - 2) return fail(h, MPO_EINVAL, "bond out of range");
+    const double* go = g_out ? g_out + 32 * p : nullptr;
+    const double* gi = g_in ? g_in + 32 * p : nullptr;
+    if (batch_form) {
+      bool zo = go != nullptr, zi = gi != nullptr;
+      for (int j = 0; j < 32 && (zo || zi); ++j) {
+        if (go && go[j] != 0.0) zo = false;
+        if (gi && gi[j] != 0.0) zi = false;
+      }
+      if (zo) go = nullptr;
+      if (zi) gi = nullptr;
+    }
+    if (!finite_gate(go) || !finite_gate(gi)) return fail(h, MPO_ENUMERIC, "non-finite gate entry");
+    reqs[p] = Req{b, go, gi};
+    sorted.push_back(b);
+  }
+  std::sort(sorted.begin(), sorted.end());
+  for (size_t j = 1; j < sorted.size(); ++j)
+    if (sorted[j] - sorted[j - 1] < 2) return fail(h, MPO_EINVAL, "batched bonds must be non-adjacent");
+  std::vector<Res> res;
+  mpo_status_t s = guarded(h, [&]() { return updates(h, reqs, res, true); });
+  if (s < 0) return s;
+  bool noconv = false;
+  for (int p = 0; p < count; ++p) {
+    noconv |= res[p].noconv;
+    if (info) info[p] = mpo_update_info_t{res[p].k, res[p].sweeps, res[p].disc, res[p].total};
+  }
+  return noconv ? MPO_WARN_NOCONV : MPO_OK;
+}
+
+mpo_status_t mpo_absorb_gate_pair(mpo_handle_t h, int32_t bond, const double* g_out, const double* g_in,
+                                  mpo_update_info_t* info) {
+  return absorb_common(h, 1, &bond, g_out, g_in, info, false);
+}
+
+mpo_status_t mpo_absorb_batch(mpo_handle_t h, int32_t count, const int32_t* bonds, const double* g_out,
+                              const double* g_in, mpo_update_info_t* info) {
+  return absorb_common(h, count, bonds, g_out, g_in, info, true);
+}
+
+mpo_status_t mpo_unswap_sweep(mpo_handle_t h, const mpo_unswap_opts_t* opts, mpo_swap_t* log, int32_t log_cap,
+                              int32_t* n_accepted) {
+  if (!h || !opts || log_cap < 0 || (log_cap > 0 && !log)) return MPO_EINVAL;
+  if (opts->schedule != 0 && opts->schedule != 1) return fail(h, MPO_EINVAL, "schedule must be 0 or 1");
+  const int max_iters = opts->max_iters > 0 ? opts->max_iters : 20;
+  const bool relaxed = opts->relaxed != 0;
+  std::vector<mpo_swap_t> acc;
+  bool noconv = false;
+  mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
+    const int n = h->n;
+    if (opts->schedule == 1) {
+      static const int order[6][2] = {{2, 0}, {2, 1}, {0, 0}, {0, 1}, {1, 0}, {1, 1}};
+      for (int cyc = 0; cyc < max_iters; ++cyc) {
+        bool reduced = false;
+        for (int c = 0; c < 6; ++c) {
+          const int side = order[c][0], parity = order[c][1];
+          std::vector<Req> trials;
+          for (int b = parity; b <= n - 2; b += 2) trials.push_back(swap_req(b, side));
+          if (trials.empty()) continue;
+          std::vector<Res> tr;
+          mpo_status_t r = updates(h, trials, tr, false);
+          if (r != MPO_OK) return r;
+          std::vector<Req> commits;
+          for (size_t t = 0; t < trials.size(); ++t) {
+            noconv |= tr[t].noconv;
+            const int b = trials[t].bond;
+            const int chi_b = h->chi[b + 1];
+            if (tr[t].k < chi_b || (relaxed && tr[t].k == chi_b)) {
+              commits.push_back(trials[t]);
+              acc.push_back(mpo_swap_t{side, b});
+              if (tr[t].k < chi_b) reduced = true;
+            }
+          }
+          if (!commits.empty()) {
+            std::vector<Res> cr;
+            r = updates(h, commits, cr, true);
+            if (r != MPO_OK) return r;
+            for (auto& x : cr) noconv |= x.noconv;
+          }
+        }
+        if (!reduced) break;
+      }
+    } else {
+      std::set<int> avail;
+      for (int b = 0; b <= n - 2; ++b) avail.insert(b);
+      const size_t cap = (size_t)max_iters * (n - 1);
+      while (!avail.empty() && acc.size() < cap) {
+        int i = -1, best_chi = -1;
+        for (int b : avail)
+          if (h->chi[b + 1] > best_chi) {
+            best_chi = h->chi[b + 1];
+            i = b;
+          }
+        std::vector<Req> trials = {swap_req(i, 0), swap_req(i, 1), swap_req(i, 2)};
+        std::vector<Res> tr;
+        mpo_status_t r = updates(h, trials, tr, false);
+        if (r != MPO_OK) return r;
+        int bs = 0;
+        for (int sd = 1; sd < 3; ++sd) {
+          noconv |= tr[sd].noconv;
+          const double tol = WEIGHT_TIE_REL * std::max(tr[sd].total, tr[bs].total);
+          if (tr[sd].k < tr[bs].k || (tr[sd].k == tr[bs].k && tr[sd].disc < tr[bs].disc - tol)) bs = sd;
+        }
+        avail.erase(i);
+        const int chi_i = h->chi[i + 1];
+        if (tr[bs].k < chi_i || (relaxed && tr[bs].k == chi_i)) {
+          std::vector<Req> commit = {trials[bs]};
+          std::vector<Res> cr;
+          r = updates(h, commit, cr, true);
+          if (r != MPO_OK) return r;
+          noconv |= cr[0].noconv;
+          acc.push_back(mpo_swap_t{bs, i});
+          if (i - 1 >= 0) avail.insert(i - 1);
+          if (i + 1 <= n - 2) avail.insert(i + 1);
+        }
+      }
+    }
+    return MPO_OK;
+  });
+  if (s < 0) return s;
+  const int nacc = (int)acc.size();
+  for (int j = 0; j < nacc && j < log_cap; ++j) log[j] = acc[j];
+  if (n_accepted) *n_accepted = nacc;
+  if (nacc > log_cap) return fail(h, MPO_EOVERFLOW, "accepted-swap log truncated");
+  return noconv ? MPO_WARN_NOCONV : MPO_OK;
+}
+
+mpo_status_t mpo_extract_peak(mpo_handle_t h, uint8_t* bits_per_site, double* prob, double* norm2) {
+  if (!h) return MPO_EINVAL;
+  return guarded(h, [&]() {
+    if (h->prec == MPO_FP64) return extract_impl<double>(h, bits_per_site, prob, norm2);
+    return extract_impl<float>(h, bits_per_site, prob, norm2);
+  });
+}
+
+mpo_status_t mpo_bond_dims(mpo_handle_t h, int32_t* dims) {
+  if (!h || !dims) return MPO_EINVAL;
+  for (int b = 0; b < h->n - 1; ++b) dims[b] = h->chi[b + 1];
+  return MPO_OK;
+}
+
+mpo_status_t mpo_total_elements(mpo_handle_t h, int64_t* out) {
+  if (!h || !out) return MPO_EINVAL;
+  int64_t t = 0;
+  for (int i = 0; i < h->n; ++i) t += (int64_t)h->chi[i] * 4 * h->chi[i + 1];
+  *out = t;
+  return MPO_OK;
+}
+
+mpo_status_t mpo_singular_values(mpo_handle_t h, int32_t bond, double* out, int32_t cap, int32_t* count) {
+  if (!h || bond < 0 || bond > h->n - 2 || cap < 0 || (cap > 0 && !out)) return MPO_EINVAL;
+  const int k = h->chi[bond + 1];
+  if (count) *count = k;
+  return guarded(h, [&]() -> mpo_status_t {
+    const int c = std::min(k, (int)cap);
+    if (c > 0) hip_check(hipMemcpyAsync(out, h->lam[bond], c * sizeof(double), hipMemcpyDeviceToHost, h->stream), "lam");
+    hip_check(hipStreamSynchronize(h->stream), "lam sync");
+    return MPO_OK;
+  });
+}
+
+mpo_status_t mpo_read_site(mpo_handle_t h, int32_t site, double* out, int64_t cap, int32_t* chi_l, int32_t* chi_r) {
+  if (!h || site < 0 || site >= h->n || !out) return MPO_EINVAL;
+  const int cl = h->chi[site], cr = h->chi[site + 1];
+  const size_t ne = (size_t)cl * 4 * cr;
+  if (chi_l) *chi_l = cl;
+  if (chi_r) *chi_r = cr;
+  if ((int64_t)(2 * ne) > cap) return fail(h, MPO_EINVAL, "output too small");
+  return guarded(h, [&]() -> mpo_status_t {
+    if (h->prec == MPO_FP64) {
+      hip_check(hipMemcpyAsync(out, h->site[site], ne * 16, hipMemcpyDeviceToHost, h->stream), "read site");
+    } else {
+      void* tmp = dalloc(ne * 16);
+      struct F {
+        void* p;
+        ~F() { dfree(p); }
+      } g{tmp};
+      launch_convert<double, float>((cx<double>*)tmp, (const cx<float>*)h->site[site], ne, h->stream);
+      hip_check(hipMemcpyAsync(out, tmp, ne * 16, hipMemcpyDeviceToHost, h->stream), "read site");
+      hip_check(hipStreamSynchronize(h->stream), "read sync");
+    }
+    hip_check(hipStreamSynchronize(h->stream), "read sync");
+    return MPO_OK;
+  });
+}
+
+mpo_status_t mpo_load_state(mpo_handle_t h, const int32_t* dims, const double* sites, const double* lams) {
+  if (!h || !dims || !sites || !lams) return MPO_EINVAL;
+  const int n = h->n;
+  std::vector<int> chi(n + 1, 1);
+  for (int b = 0; b < n - 1; ++b) {
+    if (dims[b] < 1 || dims[b] > h->bond_cap[b]) return fail(h, MPO_EINVAL, "bond dimension exceeds its cap");
+    chi[b + 1] = dims[b];
+  }
+  for (int b = 0; b < n - 1; ++b)
+    if (chi[b + 1] > 4 * chi[b] || chi[b + 1] > 4 * chi[b + 2])
+      return fail(h, MPO_EINVAL, "bond dimensions are not reachable (chi_b > 4 chi_neighbour)");
+  return guarded(h, [&]() -> mpo_status_t {
+    size_t off = 0, loff = 0;
+    size_t maxe = 0;
+    for (int i = 0; i < n; ++i) maxe = std::max(maxe, (size_t)chi[i] * 4 * chi[i + 1]);
+    void* tmp = dalloc(maxe * 16);
+    struct F {
+      void* p;
+      ~F() { dfree(p); }
+    } g{tmp};
+    for (int i = 0; i < n; ++i) {
+      const size_t ne = (size_t)chi[i] * 4 * chi[i + 1];
+      if (h->prec == MPO_FP64) {
+        hip_check(hipMemcpyAsync(h->site[i], sites + 2 * off, ne * 16, hipMemcpyHostToDevice, h->stream), "load");
+      } else {
+        hip_check(hipMemcpyAsync(tmp, sites + 2 * off, ne * 16, hipMemcpyHostToDevice, h->stream), "load");
+        launch_convert<float, double>((cx<float>*)h->site[i], (const cx<double>*)tmp, ne, h->stream);
+      }
+      hip_check(hipStreamSynchronize(h->stream), "load sync");
+      off += ne;
+    }
+    for (int b = 0; b < n - 1; ++b) {
+      hip_check(hipMemcpyAsync(h->lam[b], lams + loff, chi[b + 1] * sizeof(double), hipMemcpyHostToDevice, h->stream),
+                "load lam");
+      loff += chi[b + 1];
+    }
+    hip_check(hipStreamSynchronize(h->stream), "load sync");
+    h->chi = chi;
+    return MPO_OK;
+  });
+}
+
+mpo_status_t mpo_sync(mpo_handle_t h) {
+  if (!h) return MPO_EINVAL;
+  return guarded(h, [&]() -> mpo_status_t {
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    return MPO_OK;
+  });
+}
+
+mpo_status_t mpo_profile(mpo_handle_t h, int32_t on, double* ms_out, int64_t* launches_out) {
+  if (!h) return MPO_EINVAL;
+  return guarded(h, [&]() -> mpo_status_t {
+    hip_check(hipStreamSynchronize(h->stream), "profile sync");
+    drain_events(h);
+    for (int c = 0; c < MPO_PROF_CLASSES; ++c) {
+      if (ms_out) ms_out[c] = h->prof_ms[c];
+      if (launches_out) launches_out[c] = h->prof_n[c];
+      h->prof_ms[c] = 0;
+      h->prof_n[c] = 0;
+    }
+    h->prof_on = on != 0;
+    return MPO_OK;
+  });
+}
+
+const char* mpo_last_error(mpo_handle_t h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+"""Host driver of the middle-MPO contraction over libmpo (Alg. 1).
+
+The driver owns only integer bookkeeping: layering, the midpoint split, the
+order of the updates of one absorption step, layouts (rewiring) and lazy
+routing.  Every tensor operation is a libmpo call.
+
+Update order of one absorption step (the innermost layer of C_L, whose gates
+act on the output legs, then the innermost layer of C_R, input legs):
+  for each C_L gate in layer order: route it with output-side SWAPs moving the
+  qubit on the lower site upwards; absorb it, together with the first not yet
+  absorbed C_R gate of the step that already sits on the same bond;
+  then route and absorb the remaining C_R gates with input-side SWAPs.
+Updates on bonds at distance >= 2 commute exactly (they touch disjoint
+tensors), so the ordered list is executed as waves of mutually distant bonds
+through mpo_absorb_batch; the result equals the one-by-one execution.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import mpo as _mpo
+
+SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+
+
+@dataclasses.dataclass
+class RunConfig:
+    chi_max: int = 64
+    cutoff: float = 1e-12
+    cutoff_mode: str = "rel_sv"       # "rel_sv" | "weight"
+    precision: str = "fp64"           # "fp64" | "fp32" | "mixed"
+    tau: float = float("inf")
+    unswap: str = "parallel"          # "parallel" | "sequential" | "none"
+    relaxed: bool = False
+    max_unswap_iters: int = 20
+    waves: bool = True                # batch independent updates
+
+
+@dataclasses.dataclass
+class Update:
+    bond: int
+    g_out: Optional[np.ndarray]
+    g_in: Optional[np.ndarray]
+    stage: str
+
+
+@dataclasses.dataclass
+class RunResult:
+    bits: np.ndarray
+    prob: float
+    norm2: float
+    site_bits: np.ndarray
+    out_layout: List[int]
+    in_layout: List[int]
+    trace: List[Dict]
+    seconds: float
+    bond_updates: int
+    trial_updates: int
+
+
+def time_layers(gates: Sequence[Tuple[int, int, np.ndarray]], n: int) -> List[list]:
+    """Gates grouped into layers; a gate is placed right after the last layer
+    that uses one of its wires."""
+    front = np.zeros(n, dtype=np.int64)
+    out: List[list] = []
+    for q0, q1, u in gates:
+        layer = int(max(front[q0], front[q1]))
+        while len(out) <= layer:
+            out.append([])
+        out[layer].append((q0, q1, u))
+        front[q0] = front[q1] = layer + 1
+    return out
+
+
+class Wires:
+    """site_of[logical] and logical_at[site] of one side of the MPO."""
+
+    def __init__(self, n: int):
+        self.site_of = np.arange(n)
+        self.logical_at = np.arange(n)
+
+    def exchange(self, bond: int) -> None:
+        a, b = self.logical_at[bond], self.logical_at[bond + 1]
+        self.logical_at[bond], self.logical_at[bond + 1] = b, a
+        self.site_of[a] = bond + 1
+        self.site_of[b] = bond
+
+
+def _on_bond(u: np.ndarray, sa: int, sb: int) -> Tuple[int, np.ndarray]:
+    if sb - sa == 1:
+        return sa, u
+    if sa - sb == 1:
+        return sb, SWAP @ u @ SWAP
+    raise ValueError("gate is not nearest-neighbour on the sites")
+
+
+def plan_step(lgates, rgates, out_w: Wires, in_w: Wires) -> List[Update]:
+    """Ordered updates of one absorption step; routing changes the layouts."""
+    ups: List[Update] = []
+
+    def route(w: Wires, a: int, b: int, side: str):
+        lo, hi = sorted((int(w.site_of[a]), int(w.site_of[b])))
+        for j in range(lo, hi - 1):
+            ups.append(Update(j, SWAP if side == "L" else None, SWAP if side == "R" else None, "route"))
+            w.exchange(j)
+
+    waiting = list(rgates)
+    for (a, b, u) in lgates:
+        route(out_w, a, b, "L")
+        bond, gl = _on_bond(u, int(out_w.site_of[a]), int(out_w.site_of[b]))
+        partner = None
+        for j, (ra, rb, _) in enumerate(waiting):
+            sa, sb = int(in_w.site_of[ra]), int(in_w.site_of[rb])
+            if abs(sa - sb) == 1 and min(sa, sb) == bond:
+                partner = j
+                break
+        if partner is None:
+            ups.append(Update(bond, gl, None, "absorb"))
+        else:
+            ra, rb, ru = waiting.pop(partner)
+            _, gr = _on_bond(ru, int(in_w.site_of[ra]), int(in_w.site_of[rb]))
+            ups.append(Update(bond, gl, gr, "absorb"))
+    for (a, b, u) in waiting:
+        route(in_w, a, b, "R")
+        bond, gr = _on_bond(u, int(in_w.site_of[a]), int(in_w.site_of[b]))
+        ups.append(Update(bond, None, gr, "absorb"))
+    return ups
+
+
+def wave_split(bonds: Sequence[int]) -> List[List[int]]:
+    """Indices of `bonds` grouped into waves: an update goes one wave after the
+    latest earlier update on a bond at distance <= 1."""
+    last: Dict[int, int] = {}
+    waves: List[List[int]] = []
+    for idx, b in enumerate(bonds):
+        w = 1 + max(last.get(b - 1, -1), last.get(b, -1), last.get(b + 1, -1))
+        while len(waves) <= w:
+            waves.append([])
+        waves[w].append(idx)
+        last[b] = w
+    return waves
+
+
+class Contractor:
+    def __init__(self, circuit, cfg: RunConfig, stream=None):
+        self.n = circuit.n
+        self.cfg = cfg
+        layers = time_layers(circuit.gates, self.n)
+        cut = (len(layers) + 1) // 2
+        self.c_left = layers[cut:]                     # innermost first
+        self.c_right = layers[:cut][::-1]              # innermost first
+        self.out_w = Wires(self.n)
+        self.in_w = Wires(self.n)
+        self.trace: List[Dict] = []
+        self.bond_updates = 0
+        self.trial_updates = 0
+        mode = _mpo.CUT_REL_SV if cfg.cutoff_mode == "rel_sv" else _mpo.CUT_WEIGHT
+        self.m = _mpo.MPO(self.n, cfg.chi_max, cfg.cutoff, mode, _mpo.PRECISIONS[cfg.precision], stream=stream)
+
+    def close(self):
+        self.m.close()
+
+    def _execute(self, ups: List[Update]):
+        if not ups:
+            return
+        infos: List[Optional[dict]] = [None] * len(ups)
+        if self.cfg.waves:
+            for wave in wave_split([u.bond for u in ups]):
+                res = self.m.absorb_batch([ups[i].bond for i in wave], [ups[i].g_out for i in wave],
+                                          [ups[i].g_in for i in wave])
+                for i, r in zip(wave, res):
+                    infos[i] = r
+        else:
+            for i, u in enumerate(ups):
+                infos[i] = self.m.absorb(u.bond, u.g_out, u.g_in)
+        for u, r in zip(ups, infos):
+            self.trace.append(dict(stage=u.stage, bond=u.bond, k=r["k"], discarded=r["discarded"],
+                                   total=r["total"], sweeps=r["sweeps"]))
+        self.bond_updates += len(ups)
+
+    def absorb_step(self):
+        lg = self.c_left.pop(0) if self.c_left else []
+        rg = self.c_right.pop(0) if self.c_right else []
+        self._execute(plan_step(lg, rg, self.out_w, self.in_w))
+
+    def unswap(self):
+        if self.cfg.unswap == "none":
+            return []
+        before = self.m.total_elements()
+        log = self.m.unswap(self.cfg.unswap, self.cfg.relaxed, self.cfg.max_unswap_iters)
+        for side, b in log:
+            if side in ("L", "B"):
+                self.out_w.exchange(b)
+            if side in ("R", "B"):
+                self.in_w.exchange(b)
+        self.trace.append(dict(stage="unswap", accepted=len(log), size_before=before,
+                               size=self.m.total_elements(), log=list(log)))
+        return log
+
+    def run(self) -> RunResult:
+        t0 = time.perf_counter()
+        while self.c_left or self.c_right:
+            self.absorb_step()
+            while self.m.total_elements() < self.cfg.tau and (self.c_left or self.c_right):
+                self.absorb_step()
+            self.unswap()
+        site_bits, p, n2 = self.m.extract_peak()
+        secs = time.perf_counter() - t0
+        bits = site_bits[self.out_w.site_of]
+        return RunResult(bits.astype(np.uint8), p, n2, site_bits, list(map(int, self.out_w.site_of)),
+                         list(map(int, self.in_w.site_of)), self.trace, secs, self.bond_updates,
+                         self.trial_updates)
+
+
+def contract(circuit, cfg: RunConfig, stream=None) -> RunResult:
+    c = Contractor(circuit, cfg, stream=stream)
+    try:
+        return c.run()
+    finally:
+        c.close()

@@ -1,0 +1,250 @@
+"""ctypes binding of libmpo (include/mpo.h): argument marshalling only.
+
+Every step of the bond update runs in the HIP kernels of libmpo.so; this
+module converts NumPy gate matrices to the C layout and status codes to
+exceptions.  Loading fails loudly when the library has not been built."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpo.so")
+
+FP64, FP32, MIXED = 0, 1, 2
+CUT_REL_SV, CUT_WEIGHT = 0, 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "mixed": MIXED}
+STATUS = {0: "MPO_OK", 1: "MPO_WARN_NOCONV", -1: "MPO_EINVAL", -2: "MPO_ENOMEM", -3: "MPO_EHIP",
+          -4: "MPO_ENUMERIC", -5: "MPO_EOVERFLOW"}
+SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
+
+EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_batch", "mpo_unswap_sweep",
+            "mpo_extract_peak", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
+            "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_profile", "mpo_last_error", "mpo_version"]
+PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_step", "finalize", "writeback", "writeback_gemm"]
+
+
+class MpoConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("chi_max", ctypes.c_int32), ("cutoff", ctypes.c_double),
+                ("cutoff_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("max_sweeps", ctypes.c_int32), ("jacobi_tol", ctypes.c_double)]
+
+
+class UpdateInfo(ctypes.Structure):
+    _fields_ = [("chi_new", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("discarded_weight", ctypes.c_double), ("total_weight", ctypes.c_double)]
+
+
+class UnswapOpts(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("relaxed", ctypes.c_int32), ("max_iters", ctypes.c_int32)]
+
+
+class SwapEntry(ctypes.Structure):
+    _fields_ = [("side", ctypes.c_int32), ("bond", ctypes.c_int32)]
+
+
+class MpoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libmpo.so is not built ({path}); run `python -m paper_2604_21908_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.mpo_init_identity.argtypes = [ctypes.POINTER(MpoConfig), P, ctypes.POINTER(P)]
+    lib.mpo_absorb_gate_pair.argtypes = [P, I32, dp, dp, ctypes.POINTER(UpdateInfo)]
+    lib.mpo_absorb_batch.argtypes = [P, I32, ctypes.POINTER(I32), dp, dp, ctypes.POINTER(UpdateInfo)]
+    lib.mpo_unswap_sweep.argtypes = [P, ctypes.POINTER(UnswapOpts), ctypes.POINTER(SwapEntry), I32,
+                                     ctypes.POINTER(I32)]
+    lib.mpo_extract_peak.argtypes = [P, ctypes.POINTER(ctypes.c_uint8), dp, dp]
+    lib.mpo_free.argtypes = [P]
+    lib.mpo_free.restype = None
+    lib.mpo_bond_dims.argtypes = [P, ctypes.POINTER(I32)]
+    lib.mpo_total_elements.argtypes = [P, ctypes.POINTER(I64)]
+    lib.mpo_singular_values.argtypes = [P, I32, dp, I32, ctypes.POINTER(I32)]
+    lib.mpo_read_site.argtypes = [P, I32, dp, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.mpo_load_state.argtypes = [P, ctypes.POINTER(I32), dp, dp]
+    lib.mpo_sync.argtypes = [P]
+    lib.mpo_profile.argtypes = [P, I32, dp, ctypes.POINTER(I64)]
+    lib.mpo_last_error.argtypes = [P]
+    lib.mpo_last_error.restype = ctypes.c_char_p
+    lib.mpo_version.argtypes = []
+    lib.mpo_version.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("mpo_free", "mpo_last_error", "mpo_version"):
+            getattr(lib, name).restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def _gate_ptr(g):
+    if g is None:
+        return None, None
+    a = np.ascontiguousarray(np.asarray(g, dtype=np.complex128).reshape(4, 4)).view(np.float64).reshape(32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class MPO:
+    """One device-resident MPO (a libmpo handle)."""
+
+    def __init__(self, n: int, chi_max: int, cutoff: float, cutoff_mode: int = CUT_REL_SV,
+                 precision: int = FP64, max_sweeps: int = 0, jacobi_tol: float = 0.0, stream=None):
+        self.lib = load_library()
+        self.n = n
+        self.precision = precision
+        cfg = MpoConfig(n, chi_max, cutoff, cutoff_mode, precision, max_sweeps, jacobi_tol)
+        h = ctypes.c_void_p()
+        st = stream if stream is not None else _current_stream()
+        s = self.lib.mpo_init_identity(ctypes.byref(cfg), st, ctypes.byref(h))
+        if s != 0:
+            raise MpoError(s, "mpo_init_identity failed")
+        self.h = h
+
+    # ---------------------------------------------------------------- utils
+    def _check(self, s: int, what: str, ok=(0,)):
+        if s in ok:
+            return s
+        msg = self.lib.mpo_last_error(self.h).decode() if self.h else ""
+        raise MpoError(s, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mpo_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---------------------------------------------------------------- calls
+    def absorb(self, bond: int, g_out=None, g_in=None) -> dict:
+        ko, po = _gate_ptr(g_out)
+        ki, pi = _gate_ptr(g_in)
+        info = UpdateInfo()
+        s = self.lib.mpo_absorb_gate_pair(self.h, bond, po, pi, ctypes.byref(info))
+        self._check(s, "mpo_absorb_gate_pair", ok=(0, 1))
+        return dict(k=info.chi_new, sweeps=info.sweeps, discarded=info.discarded_weight,
+                    total=info.total_weight, noconv=(s == 1))
+
+    def absorb_batch(self, bonds: Sequence[int], g_outs: Sequence, g_ins: Sequence) -> List[dict]:
+        cnt = len(bonds)
+        if cnt == 0:
+            return []
+        b = (ctypes.c_int32 * cnt)(*bonds)
+        go = np.zeros((cnt, 32))
+        gi = np.zeros((cnt, 32))
+        for j in range(cnt):
+            if g_outs[j] is not None:
+                go[j] = np.ascontiguousarray(np.asarray(g_outs[j], np.complex128)).view(np.float64).reshape(32)
+            if g_ins[j] is not None:
+                gi[j] = np.ascontiguousarray(np.asarray(g_ins[j], np.complex128)).view(np.float64).reshape(32)
+        infos = (UpdateInfo * cnt)()
+        dp = ctypes.POINTER(ctypes.c_double)
+        s = self.lib.mpo_absorb_batch(self.h, cnt, b, go.ctypes.data_as(dp), gi.ctypes.data_as(dp), infos)
+        self._check(s, "mpo_absorb_batch", ok=(0, 1))
+        return [dict(k=x.chi_new, sweeps=x.sweeps, discarded=x.discarded_weight, total=x.total_weight)
+                for x in infos]
+
+    def unswap(self, schedule: str = "parallel", relaxed: bool = False, max_iters: int = 20) -> List[Tuple[str, int]]:
+        opts = UnswapOpts(1 if schedule == "parallel" else 0, int(relaxed), max_iters)
+        cap = max(64, 4 * max_iters * self.n)
+        log = (SwapEntry * cap)()
+        nacc = ctypes.c_int32()
+        s = self.lib.mpo_unswap_sweep(self.h, ctypes.byref(opts), log, cap, ctypes.byref(nacc))
+        self._check(s, "mpo_unswap_sweep", ok=(0, 1))
+        return [(SIDE_NAMES[log[j].side], int(log[j].bond)) for j in range(nacc.value)]
+
+    def extract_peak(self) -> Tuple[np.ndarray, float, float]:
+        bits = (ctypes.c_uint8 * self.n)()
+        p = ctypes.c_double()
+        n2 = ctypes.c_double()
+        s = self.lib.mpo_extract_peak(self.h, bits, ctypes.byref(p), ctypes.byref(n2))
+        self._check(s, "mpo_extract_peak")
+        return np.array(bits[:], dtype=np.uint8), p.value, n2.value
+
+    def bond_dims(self) -> List[int]:
+        d = (ctypes.c_int32 * (self.n - 1))()
+        self._check(self.lib.mpo_bond_dims(self.h, d), "mpo_bond_dims")
+        return list(d)
+
+    def total_elements(self) -> int:
+        v = ctypes.c_int64()
+        self._check(self.lib.mpo_total_elements(self.h, ctypes.byref(v)), "mpo_total_elements")
+        return int(v.value)
+
+    def singular_values(self, bond: int) -> np.ndarray:
+        cap = 4096
+        out = np.zeros(cap)
+        cnt = ctypes.c_int32()
+        s = self.lib.mpo_singular_values(self.h, bond, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap,
+                                         ctypes.byref(cnt))
+        self._check(s, "mpo_singular_values")
+        return out[:cnt.value].copy()
+
+    def read_site(self, i: int) -> np.ndarray:
+        dims = self.bond_dims()
+        cl = 1 if i == 0 else dims[i - 1]
+        cr = 1 if i == self.n - 1 else dims[i]
+        out = np.zeros(cl * 4 * cr, dtype=np.complex128)
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        s = self.lib.mpo_read_site(self.h, i, out.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   2 * out.size, ctypes.byref(a), ctypes.byref(b))
+        self._check(s, "mpo_read_site")
+        return out.reshape(a.value, 4, b.value)
+
+    def load_state(self, sites: Sequence[np.ndarray], lams: Sequence[np.ndarray]) -> None:
+        dims = [int(l.size) for l in lams]
+        d = (ctypes.c_int32 * len(dims))(*dims)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(s, np.complex128).reshape(-1) for s in sites]))
+        lam = np.ascontiguousarray(np.concatenate([np.asarray(l, np.float64).reshape(-1) for l in lams]))
+        dp = ctypes.POINTER(ctypes.c_double)
+        s = self.lib.mpo_load_state(self.h, d, flat.view(np.float64).ctypes.data_as(dp), lam.ctypes.data_as(dp))
+        self._check(s, "mpo_load_state")
+
+    def sync(self):
+        self._check(self.lib.mpo_sync(self.h), "mpo_sync")
+
+    def profile(self, on: bool) -> dict:
+        """Returns {class: (ms, launches)} accumulated so far, resets, and
+        switches kernel timing on or off."""
+        nc = len(PROF_CLASSES)
+        ms = np.zeros(nc)
+        cnt = (ctypes.c_int64 * nc)()
+        s = self.lib.mpo_profile(self.h, int(on), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cnt)
+        self._check(s, "mpo_profile")
+        return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(PROF_CLASSES)}
+
+
+def version() -> str:
+    return load_library().mpo_version().decode()

@@ -1,0 +1,216 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: singular values are compared normwise over the kept range,
+max_j |s_j - s_j^ref| / |s^ref|_2 <= 1e-10 for FP64 and 1e-4 for FP32 and
+mixed; kept ranks, peak bits and accepted-swap logs must be identical; the
+peak probability must agree to 1e-3 relative (FP64 paths agree far tighter).
+SVD factors are gauge-dependent, so tensors are compared through contracted
+operators, never factor by factor."""
+import numpy as np
+import pytest
+
+from oracle import brute as bf
+from oracle import mpo_oracle as mo
+from paper_2604_21908_amd import circuitgen as cg
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4, "mixed": 1e-4}
+PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2604_21908_amd import mpo as mpolib
+    mpolib.load_library()
+    return mpolib
+
+
+def random_state(n, seed, layers, chi_max=256):
+    rng = np.random.default_rng(seed)
+    m = mo.OracleMPO(n)
+    for l in range(layers):
+        for i in range(l % 2, n - 1, 2):
+            mo.commit(m, mo.bond_update(m, i, cg.haar_su4(rng), cg.haar_su4(rng), chi_max, 1e-13, "rel_sv"))
+    return m
+
+
+def sv_err(a, b):
+    k = min(len(a), len(b))
+    return np.max(np.abs(np.asarray(a[:k]) - np.asarray(b[:k]))) / np.linalg.norm(b)
+
+
+def gpu_mpo(lib, m, prec, chi_max=256, cutoff=1e-12, mode=0):
+    g = lib.MPO(m.n, chi_max, cutoff, mode, PREC[prec])
+    g.load_state(m.B, m.lam)
+    return g
+
+
+def gpu_dense(g, n):
+    o = mo.OracleMPO(n)
+    o.B = [g.read_site(i) for i in range(n)]
+    return o.dense_operator()
+
+
+# ---------------------------------------------------------------- single updates
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("bond", [0, 2, 4])
+def test_single_update_matches_oracle(lib, prec, bond):
+    n = 6
+    m = random_state(n, 7 + bond, 4)
+    rng = np.random.default_rng(bond)
+    go, gi = cg.haar_su4(rng), cg.haar_su4(rng)
+    g = gpu_mpo(lib, m, prec)
+    info = g.absorb(bond, go, gi)
+    r = mo.bond_update(m, bond, go, gi, 256, 1e-12, "rel_sv")
+    mo.commit(m, r)
+    assert info["k"] == r.k
+    assert sv_err(g.singular_values(bond), r.s[:r.k]) <= TOL[prec]
+    assert np.max(np.abs(gpu_dense(g, n) - m.dense_operator())) <= TOL[prec] * 10
+    assert g.bond_dims() == m.bond_dims()
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_large_theta_update(lib, prec):
+    """A 256 x 256 theta (chi 64 on both sides) spans many 16-column blocks."""
+    n = 8
+    m = random_state(n, 3, 7, chi_max=64)
+    assert m.chi(2) == 64 and m.chi(4) == 64
+    rng = np.random.default_rng(9)
+    go, gi = cg.haar_su4(rng), cg.haar_su4(rng)
+    g = gpu_mpo(lib, m, prec, chi_max=64, cutoff=1e-8, mode=1)
+    info = g.absorb(3, go, gi)
+    r = mo.bond_update(m, 3, go, gi, 64, 1e-8, "weight")
+    assert info["k"] == r.k == 64
+    assert sv_err(g.singular_values(3), r.s[:r.k]) <= TOL[prec]
+    assert abs(info["discarded"] - r.discarded) <= TOL[prec] * r.total
+    g.close()
+
+
+@pytest.mark.parametrize("abc", [(0.3, 0.2, 0.1), (np.pi / 4, np.pi / 4, np.pi / 4), (np.pi / 4, 0, 0)])
+def test_kak_closed_form_on_gpu(lib, abc):
+    rng = np.random.default_rng(5)
+    u = np.kron(cg.haar_unitary(rng, 2), cg.haar_unitary(rng, 2)) @ bf.kak_gate(*abc)
+    g = lib.MPO(4, 16, 1e-12, 0, 0)
+    info = g.absorb(1, u, None)
+    want = bf.kak_schmidt_values(*abc)
+    k = int(np.count_nonzero(want > 1e-12 * want[0]))
+    assert info["k"] == k
+    assert np.allclose(g.singular_values(1), want[:k], atol=1e-12)
+    g.close()
+
+
+def test_mirrored_pair_collapses(lib):
+    rng = np.random.default_rng(1)
+    u = cg.haar_su4(rng)
+    g = lib.MPO(5, 16, 1e-12, 0, 0)
+    info = g.absorb(2, u.conj().T, u)
+    assert info["k"] == 1 and abs(g.singular_values(2)[0] - 1) < 1e-13
+    g.close()
+
+
+def test_batch_equals_one_by_one(lib):
+    n = 9
+    m = random_state(n, 21, 4)
+    rng = np.random.default_rng(2)
+    bonds = [0, 3, 5, 7]
+    gs = [(cg.haar_su4(rng), cg.haar_su4(rng)) for _ in bonds]
+    a = gpu_mpo(lib, m, "fp64")
+    b = gpu_mpo(lib, m, "fp64")
+    a.absorb_batch(bonds, [x[0] for x in gs], [x[1] for x in gs])
+    for bd, (go, gi) in zip(bonds, gs):
+        b.absorb(bd, go, gi)
+    for i in range(n):
+        assert np.array_equal(a.read_site(i), b.read_site(i))
+    a.close()
+    b.close()
+
+
+def test_error_codes_leave_state_unchanged(lib):
+    m = random_state(5, 4, 3)
+    g = gpu_mpo(lib, m, "fp64")
+    before = [g.read_site(i) for i in range(5)]
+    with pytest.raises(lib.MpoError) as e:
+        g.absorb(4, None, None)
+    assert e.value.status == -1
+    bad = np.eye(4, dtype=complex)
+    bad[0, 0] = np.nan
+    with pytest.raises(lib.MpoError) as e:
+        g.absorb(1, bad, None)
+    assert e.value.status == -4
+    with pytest.raises(lib.MpoError):
+        g.absorb_batch([1, 2], [None, None], [None, None])      # adjacent bonds
+    for i in range(5):
+        assert np.array_equal(g.read_site(i), before[i])
+    g.close()
+
+
+def test_two_sites_and_identity_gates(lib):
+    g = lib.MPO(2, 4, 1e-12, 0, 0)
+    info = g.absorb(0, None, None)
+    assert info["k"] == 1
+    bits, p, n2 = g.extract_peak()
+    assert list(bits) == [0, 0] and abs(p - 1) < 1e-12 and abs(n2 - 0.25) < 1e-14
+    g.close()
+
+
+# ---------------------------------------------------------------- whole contractions
+def run_both(circ, prec, chi_max, cutoff, mode, tau, unswap, relaxed=False):
+    from paper_2604_21908_amd import driver as dr
+    ocfg = mo.OracleConfig(chi_max=chi_max, cutoff=cutoff, mode=mode, tau=tau, unswap=unswap, relaxed=relaxed)
+    ref = mo.contract(circ.n, circ.gates, ocfg)
+    cfg = dr.RunConfig(chi_max=chi_max, cutoff=cutoff, cutoff_mode=mode, precision=prec, tau=tau,
+                       unswap=unswap, relaxed=relaxed)
+    c = dr.Contractor(circ, cfg)
+    res = c.run()
+    lams = [c.m.singular_values(b) for b in range(circ.n - 1)]
+    c.close()
+    return ref, res, lams
+
+
+def compare_runs(ref, res, lams, prec):
+    rk = [t for t in ref.trace if "k" in t]
+    gk = [t for t in res.trace if "k" in t]
+    assert [t["k"] for t in gk] == [t["k"] for t in rk]
+    assert [t["bond"] for t in gk] == [t["bond"] for t in rk]
+    ru = [t["log"] for t in ref.trace if t["stage"] == "unswap"]
+    gu = [t["log"] for t in res.trace if t["stage"] == "unswap"]
+    assert ru == gu
+    for b in range(len(lams)):
+        assert sv_err(lams[b], ref.mpo.lam[b]) <= TOL[prec]
+    assert np.array_equal(res.bits, ref.bits)
+    assert abs(res.prob - ref.prob) <= 1e-3 * ref.prob
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config0_contraction_matches_oracle(lib, prec):
+    circ = cg.config_circuit(0)
+    ref, res, lams = run_both(circ, prec, 64, 1e-12 if prec == "fp64" else 1e-8,
+                              "rel_sv" if prec == "fp64" else "weight", 2000, "parallel")
+    compare_runs(ref, res, lams, prec)
+    assert (res.bits == circ.peak).all()
+    assert abs(res.prob - bf.peak_probability_closed_form(circ.n, circ.k_gates)) < 1e-3 * res.prob
+
+
+def test_sequential_unswap_matches_oracle(lib):
+    circ = cg.mirrored_peaked_circuit(8, 3, 31, reading="B")
+    ref, res, lams = run_both(circ, "fp64", 256, 1e-12, "rel_sv", 300, "sequential")
+    compare_runs(ref, res, lams, "fp64")
+
+
+def test_relaxed_parallel_unswap_matches_oracle(lib):
+    circ = cg.mirrored_peaked_circuit(8, 3, 32, reading="B")
+    ref, res, lams = run_both(circ, "fp64", 256, 1e-12, "rel_sv", 300, "parallel", relaxed=True)
+    compare_runs(ref, res, lams, "fp64")
+
+
+def test_mirror_collapse_on_gpu(lib):
+    from paper_2604_21908_amd import driver as dr
+    circ = cg.mirror_only_circuit(12, 6, 3)
+    res = dr.contract(circ, dr.RunConfig(chi_max=64, unswap="none"))
+    ks = [t["k"] for t in res.trace if "k" in t]
+    assert ks and max(ks) == 1
+    assert abs(res.prob - 1.0) < 1e-10 and not res.bits.any()
