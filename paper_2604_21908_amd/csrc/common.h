@@ -36,14 +36,15 @@ struct GemmBatch {
 
 // ---------------------------------------------------------------- gate
 // theta0 (m x n row-major, m = 4 chil, n = 4 chir) -> theta_nolam (same) and
-// A = lam[a] * theta, column-major with leading dimension lda.
+// M = conj(lam[a] * theta) in the same row-major positions, i.e. the column-
+// major n x m matrix (lam theta)^dag; M may alias theta0.
 struct GateProb {
   const void* theta0;
   void* theta_nolam;
-  void* A;
+  void* M;
   const double* lam;      // chil values (FP64)
   const double* gates;    // 64 doubles: g_out (32) then g_in (32), device
-  int chil, chir, lda;
+  int chil, chir;
   int has_out, has_in;
 };
 struct GateBatch {
@@ -71,6 +72,64 @@ struct JacBatch {
   int count;
 };
 
+// ---------------------------------------------------------------- QR
+// Householder QR of M (n x m, column-major, leading dimension n) over its
+// first r = min(n, m) columns, in panels of QNB columns: R on and above the
+// diagonal, the reflector vectors v (unit first entry implied) below it,
+// tau[j] per reflector and, per panel, the upper-triangular T of the compact
+// WY form  H_p0 ... H_p0+nb-1 = I - V T V^dag.
+constexpr int QNB = 16;
+struct QrProb {
+  void* M;
+  void* tau;      // r entries
+  void* Tf;       // ceil(r / QNB) panels x QNB x QNB, row-major per panel
+  int n, m, r;
+};
+struct QrBatch {
+  QrProb p[MAXB];
+  int count;
+};
+// C (n rows, leading dimension ldc, columns [c0, c1)) <- (I - V op(T) V^dag) C
+// for the panel starting at column p0 of M; op(T) = T^dag (Q^dag from the left,
+// used for the trailing matrix) or T (Q from the left, used to form V).
+struct QrApplyProb {
+  const void* M;
+  const void* Tf;
+  void* C;
+  int n, r, ldc, c0, c1;
+};
+struct QrApplyBatch {
+  QrApplyProb p[MAXB];
+  int count;
+  int conj_t;     // 1: T^dag, 0: T
+};
+
+// A[j * lda + i] = conj(R[j][i]) = conj(M[i * n + j]) for i >= j (i < m, j < r);
+// zero above the diagonal and in the padding columns j in [r, rpad).
+struct LowerProb {
+  const void* M;
+  void* A;
+  int n, m, r, rpad, lda;
+};
+struct LowerBatch {
+  LowerProb p[MAXB];
+  int count;
+};
+
+struct VkProb {
+  const void* W;        // column-major, ldw rows
+  const int* perm;
+  const double* s_sorted;
+  void* Y;              // n x k column-major (ld n)
+  void* right;          // k x n row-major
+  double* lam;
+  int n, r, k, ldw;
+};
+struct VkBatch {
+  VkProb p[MAXB];
+  int count;
+};
+
 // ---------------------------------------------------------------- truncation
 struct TruncResult {
   int k;
@@ -95,20 +154,6 @@ struct TruncBatch {
   int chi_max;
   int mode;
   double cutoff;
-};
-
-// ---------------------------------------------------------------- write-back
-struct WbProb {
-  const void* V;       // column-major, ldv rows
-  const int* perm;
-  const double* s_sorted;
-  void* right;         // new B_{i+1}: k x ncol row-major
-  double* lam;         // new lambda_i: k values
-  int ldv, ncol, k;
-};
-struct WbBatch {
-  WbProb p[MAXB];
-  int count;
 };
 
 }  // namespace mpo

@@ -3,14 +3,13 @@
 //   k_gemm         complex GEMM on real MFMA (4M: four real products per
 //                  complex K step), LDS-staged 64x64 tiles, batched
 //   k_gate         gate pair (G_out (x) G_in^T) on the physical legs of theta,
-//                  lambda scaling, column-major copy for the SVD
+//                  lambda scaling, (lambda theta)^dag for the QR preconditioner
 //   k_jac_*        block one-sided (Hestenes) Jacobi SVD: Brent-Luk round-robin
 //                  over 16-column blocks; each block pair's 32x32 Gram matrix
 //                  is diagonalised by a cyclic Jacobi EVD in FP64 in LDS and
 //                  the panel of theta (and V) is rotated by its eigenvectors
 //   k_colnorms     singular values as column norms (FP64)
 //   k_sort_trunc   descending sort + truncation decision (FP64)
-//   k_wb_gather    B_{i+1} <- V_k^dag, lambda_i <- s_<k
 //   k_env / k_greedy  peak readout of M|0...0> (FP64)
 #include "common.h"
 
@@ -166,7 +165,7 @@ __global__ __launch_bounds__(256) void k_gate(GateBatch gb) {
   const int total = P.chil * chir;
   const cx<T>* th0 = (const cx<T>*)P.theta0;
   cx<T>* thn = (cx<T>*)P.theta_nolam;
-  cx<T>* A = (cx<T>*)P.A;
+  cx<T>* Mo = (cx<T>*)P.M;
   for (int idx = blockIdx.x * 256 + tid; idx < total; idx += gridDim.x * 256) {
     const int a = idx / chir, b = idx - a * chir;
     cx<T> in[16];
@@ -175,6 +174,8 @@ __global__ __launch_bounds__(256) void k_gate(GateBatch gb) {
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) in[s1 * 4 + s2] = th0[(size_t)(4 * a + s1) * n + s2 * chir + b];
     const T lam = (T)P.lam[a];
+    // every input of this thread is read before any output is written, so
+    // M may alias theta0
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       T re = 0, im = 0;
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(256) void k_gate(GateBatch gb) {
       }
       const int s1p = r >> 2, s2p = r & 3;
       thn[(size_t)(4 * a + s1p) * n + s2p * chir + b] = cx<T>{re, im};
-      A[(size_t)(s2p * chir + b) * P.lda + 4 * a + s1p] = cx<T>{re * lam, im * lam};
+      Mo[(size_t)(4 * a + s1p) * n + s2p * chir + b] = cx<T>{re * lam, -im * lam};
     }
   }
 }
@@ -529,23 +530,6 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(TruncBatch tb) {
   }
 }
 
-// ============================================================== write-back
-template <typename T>
-__global__ __launch_bounds__(256) void k_wb_gather(WbBatch wb) {
-  const int pi = blockIdx.y;
-  if (pi >= wb.count) return;
-  const WbProb P = wb.p[pi];
-  const cx<T>* V = (const cx<T>*)P.V;
-  cx<T>* R = (cx<T>*)P.right;
-  const size_t total = (size_t)P.k * P.ncol;
-  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
-    const int j = (int)(e / P.ncol), c = (int)(e - (size_t)j * P.ncol);
-    const cx<T> v = V[(size_t)P.perm[j] * P.ldv + c];
-    R[e] = cx<T>{v.re, -v.im};
-    if (c == 0) P.lam[j] = P.s_sorted[j];
-  }
-}
-
 // ============================================================== peak readout
 // C[i][j] (+)= sum_k opA(i,k) opB(k,j); opX(i,k) = X[off + i*s0 + k*s1] (conj if cX)
 template <typename TA, typename TB>
@@ -707,13 +691,6 @@ void launch_colnorms(const JacBatch& b, int maxcols, hipStream_t s) {
 void launch_sort_trunc(const TruncBatch& b, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_trunc, dim3(b.count), dim3(1024), 0, s, b);
 }
-template <typename T>
-void launch_wb_gather(const WbBatch& b, size_t maxelems, hipStream_t s) {
-  size_t gx = (maxelems + 255) / 256;
-  if (gx > 1024) gx = 1024;
-  if (gx < 1) gx = 1;
-  hipLaunchKernelGGL(k_wb_gather<T>, dim3((unsigned)gx, b.count), dim3(256), 0, s, b);
-}
 template <typename TA, typename TB>
 void launch_zgemm_small(cx<double>* C, int ldc, const cx<TA>* A, long long as0, long long as1, int cA,
                         const cx<TB>* B, long long bs0, long long bs1, int cB, int M, int N, int K, int beta,
@@ -741,7 +718,6 @@ void launch_convert(cx<TD>* d, const cx<TS>* src, size_t n, hipStream_t s) {
   template void launch_jac_init<T>(const JacBatch&, hipStream_t);                                        \
   template void launch_jac_step<T>(const JacBatch&, int, int, hipStream_t);                      \
   template void launch_colnorms<T>(const JacBatch&, int, hipStream_t);                                   \
-  template void launch_wb_gather<T>(const WbBatch&, size_t, hipStream_t);                                \
   template void launch_greedy<T>(const cx<T>*, int, int, const cx<double>*, const cx<double>*,           \
                                  cx<double>*, cx<double>*, unsigned char*, double*, hipStream_t);
 

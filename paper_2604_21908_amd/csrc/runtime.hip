@@ -21,7 +21,11 @@ template <typename T> void launch_jac_step(const JacBatch&, int, int, hipStream_
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
 void launch_sort_trunc(const TruncBatch&, hipStream_t);
-template <typename T> void launch_wb_gather(const WbBatch&, size_t, hipStream_t);
+template <typename T> void launch_qr_panel(const QrBatch&, int, hipStream_t);
+template <typename T> void launch_qr_apply(const QrApplyBatch&, int, int, hipStream_t);
+template <typename T> void launch_lower_from_r(const LowerBatch&, int, int, hipStream_t);
+template <typename T> void launch_build_y(const VkBatch&, size_t, hipStream_t);
+template <typename T> void launch_vh_rows(const VkBatch&, size_t, hipStream_t);
 template <typename TA, typename TB>
 void launch_zgemm_small(cx<double>*, int, const cx<TA>*, long long, long long, int, const cx<TB>*, long long,
                         long long, int, int, int, int, int, hipStream_t);
@@ -55,7 +59,10 @@ struct Slot {
   double* norms = nullptr;
   double* s_sorted = nullptr;
   int* perm = nullptr;
-  size_t cap_mn = 0, cap_A = 0, cap_V = 0, cap_n = 0;
+  void* tau = nullptr;
+  void* Tf = nullptr;
+  void* Y = nullptr;
+  size_t cap_mn = 0, cap_A = 0, cap_V = 0, cap_n = 0, cap_r = 0, cap_Y = 0;
 };
 
 void dfree(void* p) {
@@ -213,6 +220,26 @@ void ensure_slot(mpo_ctx* h, Slot& s, size_t mn, size_t nA, size_t nV, size_t nn
   }
 }
 
+void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY) {
+  const size_t e = h->esz;
+  if (s.cap_r < r) {
+    dfree(s.tau);
+    dfree(s.Tf);
+    s.tau = s.Tf = nullptr;
+    s.cap_r = 0;
+    s.tau = dalloc(r * e);
+    s.Tf = dalloc(((r + QNB - 1) / QNB) * QNB * QNB * e);
+    s.cap_r = r;
+  }
+  if (nY && s.cap_Y < nY) {
+    dfree(s.Y);
+    s.Y = nullptr;
+    s.cap_Y = 0;
+    s.Y = dalloc(nY * e);
+    s.cap_Y = nY;
+  }
+}
+
 bool finite_gate(const double* g) {
   if (!g) return true;
   for (int i = 0; i < 32; ++i)
@@ -220,17 +247,17 @@ bool finite_gate(const double* g) {
   return true;
 }
 
-// One batch (<= MAXB problems): theta-build, gate, Jacobi SVD, truncation;
-// with `commit` the new tensors are written (bonds must be pairwise
-// non-adjacent).  Returns per-problem results.  Throws HipError / NoMem.
+// One batch (<= MAXB problems): theta-build, gate, QR-preconditioned Jacobi
+// SVD, truncation; with `commit` the new tensors are written (bonds must be
+// pairwise non-adjacent).  Returns per-problem results.  Throws HipError / NoMem.
 template <typename T>
 mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool commit) {
   hipStream_t st = h->stream;
   struct Shape {
-    int i, chil, chim, chir, m, ncol, ncol_pad, nblk;
+    int i, chil, chim, chir, m, n, r, rpad, nblk;
   };
   Shape sh[MAXB];
-  int maxM = 0, maxN = 0, maxtot = 0, maxcols = 0, maxpairs = 0, maxblk = 0;
+  int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0;
   for (int p = 0; p < count; ++p) {
     Shape& s = sh[p];
     s.i = reqs[p].bond;
@@ -238,17 +265,21 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     s.chim = h->chi[s.i + 1];
     s.chir = h->chi[s.i + 2];
     s.m = 4 * s.chil;
-    s.ncol = 4 * s.chir;
-    s.ncol_pad = round_up(s.ncol, 2 * JB);
-    s.nblk = s.ncol_pad / JB;
+    s.n = 4 * s.chir;
+    s.r = std::min(s.m, s.n);
+    s.rpad = round_up(s.r, 2 * JB);
+    s.nblk = s.rpad / JB;
     maxM = std::max(maxM, s.m);
-    maxN = std::max(maxN, s.ncol);
+    maxN = std::max(maxN, s.n);
     maxtot = std::max(maxtot, s.chil * s.chir);
-    maxcols = std::max(maxcols, s.ncol_pad);
+    maxr = std::max(maxr, s.r);
+    maxrpad = std::max(maxrpad, s.rpad);
     maxpairs = std::max(maxpairs, s.nblk / 2);
     maxblk = std::max(maxblk, s.nblk);
-    ensure_slot(h, h->slots[p], (size_t)s.m * s.ncol, (size_t)s.m * s.ncol_pad,
-                commit ? (size_t)s.ncol_pad * s.ncol_pad : 0, (size_t)s.ncol_pad);
+    Slot& sl = h->slots[p];
+    ensure_slot(h, sl, (size_t)s.m * s.n, (size_t)s.m * s.rpad, commit ? (size_t)s.rpad * s.rpad : 0,
+                (size_t)s.rpad);
+    ensure_qr(h, sl, (size_t)s.r, commit ? (size_t)s.n * s.r : 0);
   }
   // gates -> pinned staging -> device (the staging buffer is free: every
   // call ends with a stream synchronisation)
@@ -262,34 +293,66 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   hip_check(hipMemcpyAsync(h->d_gates, h->h_gates, (size_t)count * 64 * sizeof(double), hipMemcpyHostToDevice, st),
             "gate upload");
 
+  // theta0 = B_i B_{i+1}
   GemmBatch gb{};
   gb.count = count;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
-    gb.p[p] = GemmProb{h->site[s.i], h->site[s.i + 1], h->slots[p].theta0, s.m, s.ncol, s.chim,
-                       s.chim, s.ncol, s.ncol, 0};
+    gb.p[p] = GemmProb{h->site[s.i], h->site[s.i + 1], h->slots[p].theta0, s.m, s.n, s.chim, s.chim, s.n, s.n, 0};
   }
   timed(h, MPO_PROF_THETA_GEMM, [&] { launch_gemm<T>(gb, maxM, maxN, st); });
 
+  // gate pair, lambda; M = (lambda theta)^dag overwrites theta0
   GateBatch tb{};
   tb.count = count;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
-    tb.p[p] = GateProb{h->slots[p].theta0, h->slots[p].thetan, h->slots[p].A,
-                       s.i > 0 ? h->lam[s.i - 1] : h->ones, h->d_gates + 64 * p, s.chil, s.chir, s.m,
+    tb.p[p] = GateProb{h->slots[p].theta0, h->slots[p].thetan, h->slots[p].theta0,
+                       s.i > 0 ? h->lam[s.i - 1] : h->ones, h->d_gates + 64 * p, s.chil, s.chir,
                        reqs[p].gout != nullptr, reqs[p].gin != nullptr};
   }
   timed(h, MPO_PROF_GATE, [&] { launch_gate<T>(tb, maxtot, st); });
+
+  // Householder QR of M (n x m), panel by panel
+  QrBatch qb{};
+  qb.count = count;
+  QrApplyBatch tr{};
+  tr.count = count;
+  tr.conj_t = 1;
+  for (int p = 0; p < count; ++p) {
+    const Shape& s = sh[p];
+    qb.p[p] = QrProb{h->slots[p].theta0, h->slots[p].tau, h->slots[p].Tf, s.n, s.m, s.r};
+  }
+  for (int p0 = 0; p0 < maxr; p0 += QNB) {
+    int maxtrail = 0;
+    for (int p = 0; p < count; ++p) {
+      const Shape& s = sh[p];
+      const int c0 = std::min(p0 + QNB, s.r), c1 = s.m;
+      tr.p[p] = QrApplyProb{h->slots[p].theta0, h->slots[p].Tf, h->slots[p].theta0, s.n, s.r, s.n, c0, c1};
+      if (p0 < s.r) maxtrail = std::max(maxtrail, c1 - c0);
+    }
+    timed(h, MPO_PROF_QR, [&] {
+      launch_qr_panel<T>(qb, p0, st);
+      launch_qr_apply<T>(tr, p0, maxtrail, st);
+    });
+  }
+  // L = R^dag, the Jacobi operand (m x r, column-major)
+  LowerBatch lwb{};
+  lwb.count = count;
+  for (int p = 0; p < count; ++p) {
+    const Shape& s = sh[p];
+    lwb.p[p] = LowerProb{h->slots[p].theta0, h->slots[p].A, s.n, s.m, s.r, s.rpad, s.m};
+  }
+  timed(h, MPO_PROF_QR, [&] { launch_lower_from_r<T>(lwb, maxM, maxrpad, st); });
 
   JacBatch jb{};
   jb.count = count;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
     jb.p[p] = JacProb{h->slots[p].A, commit ? h->slots[p].V : nullptr, h->states + p, h->slots[p].norms,
-                      tol_for(h, s.m), s.m, s.m, s.ncol, s.ncol_pad, s.nblk};
+                      tol_for(h, s.m), s.m, s.m, s.r, s.rpad, s.nblk};
   }
   timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
-  int sweeps_run = 0;
   bool active_left = true;
   for (int sw = 0; sw < h->max_sweeps && active_left; ++sw) {
     for (int step = 0; step < maxblk - 1; ++step)
@@ -299,11 +362,10 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
               "state readback");
     hip_check(hipStreamSynchronize(st), "sweep sync");
     drain_events(h);
-    ++sweeps_run;
     active_left = false;
     for (int p = 0; p < count; ++p) active_left |= (h->h_states[p].active != 0);
   }
-  timed(h, MPO_PROF_FINALIZE, [&] { launch_colnorms<T>(jb, maxcols, st); });
+  timed(h, MPO_PROF_FINALIZE, [&] { launch_colnorms<T>(jb, maxrpad, st); });
   TruncBatch trb{};
   trb.count = count;
   trb.chi_max = h->cfg.chi_max;
@@ -311,8 +373,8 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   trb.cutoff = h->cfg.cutoff;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
-    trb.p[p] = TruncProb{h->slots[p].norms, h->slots[p].s_sorted, h->slots[p].perm, h->results + p, s.ncol,
-                         s.ncol_pad, std::min(s.m, s.ncol)};
+    trb.p[p] = TruncProb{h->slots[p].norms, h->slots[p].s_sorted, h->slots[p].perm, h->results + p, s.r, s.rpad,
+                         s.r};
   }
   timed(h, MPO_PROF_FINALIZE, [&] { launch_sort_trunc(trb, st); });
   hip_check(hipMemcpyAsync(h->h_results, h->results, count * sizeof(TruncResult), hipMemcpyDeviceToHost, st),
@@ -332,23 +394,31 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   if (anybad) return fail(h, MPO_ENUMERIC, "non-finite singular values");
   if (!commit) return MPO_OK;
 
-  WbBatch wb{};
-  wb.count = count;
+  // V_k = Q [W_k; 0]; B_{i+1} <- V_k^dag, lambda_i <- s_<k; B_i <- theta_noLam V_k
+  VkBatch vb{};
+  vb.count = count;
   size_t maxel = 0;
+  int maxk = 0;
+  QrApplyBatch qa{};
+  qa.count = count;
+  qa.conj_t = 0;
   GemmBatch lb{};
   lb.count = count;
-  int maxK = 0;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
     const int k = out[p].k;
-    wb.p[p] = WbProb{h->slots[p].V, h->slots[p].perm, h->slots[p].s_sorted, h->site[s.i + 1], h->lam[s.i],
-                     s.ncol_pad, s.ncol, k};
-    maxel = std::max(maxel, (size_t)k * s.ncol);
-    lb.p[p] = GemmProb{h->slots[p].thetan, h->site[s.i + 1], h->site[s.i], s.m, k, s.ncol, s.ncol, s.ncol, k, 1};
-    maxK = std::max(maxK, k);
+    vb.p[p] = VkProb{h->slots[p].V, h->slots[p].perm, h->slots[p].s_sorted, h->slots[p].Y, h->site[s.i + 1],
+                     h->lam[s.i], s.n, s.r, k, s.rpad};
+    qa.p[p] = QrApplyProb{h->slots[p].theta0, h->slots[p].Tf, h->slots[p].Y, s.n, s.r, s.n, 0, k};
+    lb.p[p] = GemmProb{h->slots[p].thetan, h->site[s.i + 1], h->site[s.i], s.m, k, s.n, s.n, s.n, k, 1};
+    maxel = std::max(maxel, (size_t)k * s.n);
+    maxk = std::max(maxk, k);
   }
-  timed(h, MPO_PROF_WRITEBACK, [&] { launch_wb_gather<T>(wb, maxel, st); });
-  timed(h, MPO_PROF_WRITEBACK_GEMM, [&] { launch_gemm<T>(lb, maxM, maxK, st); });
+  timed(h, MPO_PROF_WRITEBACK, [&] { launch_build_y<T>(vb, maxel, st); });
+  for (int p0 = (maxr - 1) / QNB * QNB; p0 >= 0; p0 -= QNB)
+    timed(h, MPO_PROF_WRITEBACK, [&] { launch_qr_apply<T>(qa, p0, maxk, st); });
+  timed(h, MPO_PROF_WRITEBACK, [&] { launch_vh_rows<T>(vb, maxel, st); });
+  timed(h, MPO_PROF_WRITEBACK_GEMM, [&] { launch_gemm<T>(lb, maxM, maxk, st); });
   for (int p = 0; p < count; ++p) h->chi[sh[p].i + 1] = out[p].k;
   return MPO_OK;
 }
@@ -468,6 +538,9 @@ void destroy(mpo_ctx* h) {
     dfree(s.norms);
     dfree(s.s_sorted);
     dfree(s.perm);
+    dfree(s.tau);
+    dfree(s.Tf);
+    dfree(s.Y);
   }
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);
