@@ -16,6 +16,9 @@ constexpr int MAXB = 32;
 // Column-block width of the block one-sided Jacobi SVD (a block pair is a
 // panel of 2*JB columns).
 constexpr int JB = 16;
+// Rows per workgroup of the Jacobi Gram and rotation kernels.
+constexpr int GRC = 256;
+constexpr int RRC = 256;
 
 // ---------------------------------------------------------------- GEMM
 // C[M x N] = A[M x K] * op(B), complex, row-major.
@@ -64,8 +67,11 @@ struct JacProb {
   void* V;        // column-major, ldv = ncol_pad rows, ncol_pad columns (NULL: values only)
   JacState* st;
   double* norms;  // ncol_pad column norms (output of the norm kernel)
+  cx<double>* gpart;  // per pair, ngchunk partial 32x32 Gram matrices
+  void* dmat;     // per pair, D = W - I (32x32, working precision)
+  int* pflag;     // per pair, 1 if the panel is rotated in this step
   double tol;     // off-diagonal tolerance |g_ij| <= tol sqrt(g_ii g_jj)
-  int m, lda, ncol, ncol_pad, nblk;
+  int m, lda, ncol, ncol_pad, nblk, ngchunk;
 };
 struct JacBatch {
   JacProb p[MAXB];
@@ -79,6 +85,7 @@ struct JacBatch {
 // tau[j] per reflector and, per panel, the upper-triangular T of the compact
 // WY form  H_p0 ... H_p0+nb-1 = I - V T V^dag.
 constexpr int QNB = 16;
+constexpr int QAT = 16;   // columns per workgroup of the reflector application
 struct QrProb {
   void* M;
   void* tau;      // r entries

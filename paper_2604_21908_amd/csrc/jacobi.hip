@@ -1,0 +1,314 @@
+// Block one-sided Jacobi SVD steps (gfx950).
+//
+// Columns of the operand are grouped in blocks of JB = 16; a round-robin step
+// pairs every block with one other, giving 32-column panels P that are
+// processed independently:
+//
+//   k_jac_gram  partial Gram matrices P^dag P over row chunks of GRC rows on
+//               MFMA (f32 16x16x4 with an FP64 sum per 64-row slab, or f64);
+//               grid = pairs x row chunks x problems
+//   k_jac_evd   per panel: FP64 sum of the partial Grams, convergence test,
+//               at most INNER_SWEEPS sweeps of cyclic Jacobi on G with FP64
+//               angles (the outer iteration finishes what they leave), and
+//               D = W - I rounded to the working precision
+//   k_jac_rot   P <- P + P D on MFMA over row chunks of RRC rows of theta's
+//               and V's panels, computed as P^T <- P^T + D^T P^T so that
+//               each 16-lane group of a wave reads and writes 16 consecutive
+//               rows of one column
+#include "common.h"
+#include "mfma.h"
+
+namespace mpo {
+
+// Inner cyclic-Jacobi sweeps per panel EVD: two already give the outer
+// iteration its full convergence rate, more only add latency.
+constexpr int INNER_SWEEPS = 2;
+
+__device__ __forceinline__ void rr_pair2(int N, int step, int t, int& a, int& b) {
+  if (t == 0) {
+    a = step;
+    b = N - 1;
+  } else {
+    a = (step + t) % (N - 1);
+    b = (step - t + (N - 1)) % (N - 1);
+  }
+  if (a > b) {
+    const int x = a;
+    a = b;
+    b = x;
+  }
+}
+
+__device__ __forceinline__ int panel_col(int bi, int bj, int c) { return c < JB ? bi * JB + c : bj * JB + c - JB; }
+
+// ---------------------------------------------------------------- Gram
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_gram(JacBatch jb, int step) {
+  const int pi = blockIdx.z;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
+  if (P.st->active == 0) return;
+  const int r0 = blockIdx.y * GRC;
+  if (r0 >= P.m) return;
+  const int r1 = min(P.m, r0 + GRC);
+  int bi, bj;
+  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  __shared__ cx<T> Pc[64][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int I = wave >> 1, J = wave & 1;
+  const cx<T>* A = (const cx<T>*)P.A;
+  typedef typename MF<T>::acc acc_t;
+  double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
+  for (int s0 = r0; s0 < r1; s0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = (tid >> 6) + 4 * u, r = tid & 63;
+      cx<T> v = {0, 0};
+      if (s0 + r < r1) v = A[(size_t)panel_col(bi, bj, c) * P.lda + s0 + r];
+      Pc[r][c] = v;
+    }
+    __syncthreads();
+    acc_t are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = 0; kk < 64; kk += 4) {
+      const cx<T> x = Pc[kk + (lane >> 4)][I * 16 + (lane & 15)];   // A = P^dag: conj applied below
+      const cx<T> y = Pc[kk + (lane >> 4)][J * 16 + (lane & 15)];
+      are = MF<T>::mma(x.re, y.re, are);
+      are = MF<T>::mma(x.im, y.im, are);
+      aim = MF<T>::mma(x.re, y.im, aim);
+      aim = MF<T>::mma(-x.im, y.re, aim);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      gr[r] += (double)are[r];
+      gi[r] += (double)aim[r];
+    }
+    __syncthreads();
+  }
+  cx<double>* out = P.gpart + ((size_t)blockIdx.x * P.ngchunk + blockIdx.y) * 1024;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = I * 16 + MF<T>::row(lane, r), j = J * 16 + (lane & 15);
+    out[i * 32 + j] = cx<double>{gr[r], gi[r]};
+  }
+}
+
+// ---------------------------------------------------------------- EVD
+// In a round-robin step the 32 indices form 16 disjoint pairs; the rotation
+// J = [[c, z], [-conj(z), c]] of pair k acts on columns (p_k, q_k).  Thread
+// (kr, kc) owns the 2x2 block of G at rows (p_kr, q_kr) x columns (p_kc, q_kc)
+// and replaces it by J_kr^dag G_block J_kc, and likewise W's rows (p_kr, q_kr)
+// x columns (p_kc, q_kc) by W_block J_kc: every entry is read and written by
+// exactly one thread, so the update runs in place.
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step) {
+  const int pi = blockIdx.y;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
+  if (P.st->active == 0) return;
+  const double tol = P.tol;
+  __shared__ cx<double> G[32][33];
+  __shared__ cx<double> W[32][33];
+  __shared__ double rc[16], rzr[16], rzi[16];
+  __shared__ int flag, anyrot;
+  const int tid = threadIdx.x;
+  const int gi = tid >> 3, gj0 = (tid & 7) * 4;
+  int* pflag = P.pflag + blockIdx.x;
+  // sum of the partial Gram matrices in chunk order (deterministic)
+  const int nch = (P.m + GRC - 1) / GRC;
+  const cx<double>* gp = P.gpart + (size_t)blockIdx.x * P.ngchunk * 1024;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = gi * 32 + gj0 + u;
+    double sr = 0, si = 0;
+    for (int c = 0; c < nch; ++c) {
+      sr += gp[(size_t)c * 1024 + e].re;
+      si += gp[(size_t)c * 1024 + e].im;
+    }
+    G[gi][gj0 + u] = cx<double>{sr, si};
+    W[gi][gj0 + u] = cx<double>{(gi == gj0 + u) ? 1.0 : 0.0, 0.0};
+  }
+  if (tid == 0) flag = 0;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = gj0 + u;
+    if (j > gi) {
+      const cx<double> g = G[gi][j];
+      const double d = G[gi][gi].re * G[j][j].re;
+      if (d > 0 && g.re * g.re + g.im * g.im > tol * tol * d) flag = 1;
+    }
+  }
+  __syncthreads();
+  if (!flag) {
+    if (tid == 0) *pflag = 0;
+    return;
+  }
+  if (tid == 0) {
+    *pflag = 1;
+    atomicAdd(&P.st->rot, 1);
+  }
+  const int kr = tid >> 4, kc = tid & 15;
+  for (int isw = 0; isw < INNER_SWEEPS; ++isw) {
+    if (tid == 0) anyrot = 0;
+    __syncthreads();
+    for (int st = 0; st < 31; ++st) {
+      if (tid < 16) {
+        int p, q;
+        rr_pair2(32, st, tid, p, q);
+        const double app = G[p][p].re, aqq = G[q][q].re;
+        const cx<double> g = G[p][q];
+        const double mag = sqrt(g.re * g.re + g.im * g.im);
+        double c = 1.0, zr = 0.0, zi = 0.0;
+        if (mag > 0.0 && mag > tol * sqrt(fmax(app * aqq, 0.0))) {
+          const double zeta = (aqq - app) / (2.0 * mag);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          const double s = t * c;
+          zr = s * g.re / mag;
+          zi = s * g.im / mag;
+          anyrot = 1;
+        }
+        rc[tid] = c;
+        rzr[tid] = zr;
+        rzi[tid] = zi;
+      }
+      __syncthreads();
+      int pr, qr, pc, qc;
+      rr_pair2(32, st, kr, pr, qr);
+      rr_pair2(32, st, kc, pc, qc);
+      const double cr = rc[kr], zrr = rzr[kr], zri = rzi[kr];
+      const double cc = rc[kc], zcr = rzr[kc], zci = rzi[kc];
+      if (!(zrr == 0.0 && zri == 0.0 && zcr == 0.0 && zci == 0.0)) {
+        // H = G_block J_c, J_c = [[cc, zc], [-conj(zc), cc]]
+        const cx<double> a00 = G[pr][pc], a01 = G[pr][qc], a10 = G[qr][pc], a11 = G[qr][qc];
+        // x * (-conj(zc)) = -(x.re zcr + x.im zci) + i (x.re zci - x.im zcr)
+        const double h00r = a00.re * cc - (a01.re * zcr + a01.im * zci);
+        const double h00i = a00.im * cc + (a01.re * zci - a01.im * zcr);
+        const double h01r = a00.re * zcr - a00.im * zci + a01.re * cc;
+        const double h01i = a00.re * zci + a00.im * zcr + a01.im * cc;
+        const double h10r = a10.re * cc - (a11.re * zcr + a11.im * zci);
+        const double h10i = a10.im * cc + (a11.re * zci - a11.im * zcr);
+        const double h11r = a10.re * zcr - a10.im * zci + a11.re * cc;
+        const double h11i = a10.re * zci + a10.im * zcr + a11.im * cc;
+        // G' = J_r^dag H, J_r^dag = [[cr, -zr], [conj(zr), cr]]
+        G[pr][pc] = cx<double>{cr * h00r - (zrr * h10r - zri * h10i), cr * h00i - (zrr * h10i + zri * h10r)};
+        G[pr][qc] = cx<double>{cr * h01r - (zrr * h11r - zri * h11i), cr * h01i - (zrr * h11i + zri * h11r)};
+        G[qr][pc] = cx<double>{zrr * h00r + zri * h00i + cr * h10r, zrr * h00i - zri * h00r + cr * h10i};
+        G[qr][qc] = cx<double>{zrr * h01r + zri * h01i + cr * h11r, zrr * h01i - zri * h01r + cr * h11i};
+      }
+      if (!(zcr == 0.0 && zci == 0.0)) {
+        // W' = W_block J_c on rows (pr, qr)
+        const cx<double> w00 = W[pr][pc], w01 = W[pr][qc], w10 = W[qr][pc], w11 = W[qr][qc];
+        W[pr][pc] = cx<double>{w00.re * cc - (w01.re * zcr + w01.im * zci), w00.im * cc + (w01.re * zci - w01.im * zcr)};
+        W[pr][qc] = cx<double>{w00.re * zcr - w00.im * zci + w01.re * cc, w00.re * zci + w00.im * zcr + w01.im * cc};
+        W[qr][pc] = cx<double>{w10.re * cc - (w11.re * zcr + w11.im * zci), w10.im * cc + (w11.re * zci - w11.im * zcr)};
+        W[qr][qc] = cx<double>{w10.re * zcr - w10.im * zci + w11.re * cc, w10.re * zci + w10.im * zcr + w11.im * cc};
+      }
+      __syncthreads();
+    }
+    const int any = anyrot;
+    __syncthreads();
+    if (!any) break;
+  }
+  // D = W - I, rounded entry by entry (see k_jac_rot)
+  cx<T>* D = (cx<T>*)P.dmat + (size_t)blockIdx.x * 1024;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = gi, c = gj0 + u;
+    D[r * 32 + c] = cx<T>{(T)(W[r][c].re - (r == c ? 1.0 : 0.0)), (T)W[r][c].im};
+  }
+}
+
+// ---------------------------------------------------------------- rotation
+// Row space of a panel: rows [0, m) of theta's operand A, then rows [0, nv)
+// of V.  out^T = P^T + D^T P^T for 16-row strips; lane (l & 15) owns row
+// strip0 + (l & 15).
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step) {
+  const int pi = blockIdx.z;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
+  if (P.st->active == 0) return;
+  if (P.pflag[blockIdx.x] == 0) return;
+  const int nv = P.V ? P.ncol : 0;
+  const int rows = P.m + nv;
+  const int c0 = blockIdx.y * RRC;
+  if (c0 >= rows) return;
+  const int c1 = min(rows, c0 + RRC);
+  int bi, bj;
+  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  __shared__ cx<T> Ds[32][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const cx<T>* D = (const cx<T>*)P.dmat + (size_t)blockIdx.x * 1024;
+  for (int e = tid; e < 1024; e += 256) Ds[e >> 5][e & 31] = D[e];
+  __syncthreads();
+  cx<T>* A = (cx<T>*)P.A;
+  cx<T>* V = (cx<T>*)P.V;
+  typedef typename MF<T>::acc acc_t;
+  for (int s0 = c0 + wave * 16; s0 < c1; s0 += 64) {
+    const int rho = s0 + (lane & 15);
+    const bool valid = rho < c1;
+    cx<T>* base;
+    size_t ld;
+    int row;
+    if (rho < P.m) {
+      base = A;
+      ld = P.lda;
+      row = rho;
+    } else {
+      base = V;
+      ld = P.ncol_pad;
+      row = rho - P.m;
+    }
+    acc_t cre[2], cim[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = t * 16 + MF<T>::row(lane, r);
+        cx<T> v = {0, 0};
+        if (valid) v = base[(size_t)panel_col(bi, bj, c) * ld + row];
+        cre[t][r] = v.re;
+        cim[t][r] = v.im;
+      }
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      cx<T> x = {0, 0};
+      if (valid) x = base[(size_t)panel_col(bi, bj, k) * ld + row];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const cx<T> d = Ds[k][t * 16 + (lane & 15)];   // A[c][k] = D[k][c]
+        cre[t] = MF<T>::mma(d.re, x.re, cre[t]);
+        cre[t] = MF<T>::mma(-d.im, x.im, cre[t]);
+        cim[t] = MF<T>::mma(d.re, x.im, cim[t]);
+        cim[t] = MF<T>::mma(d.im, x.re, cim[t]);
+      }
+    }
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = t * 16 + MF<T>::row(lane, r);
+          base[(size_t)panel_col(bi, bj, c) * ld + row] = cx<T>{cre[t][r], cim[t][r]};
+        }
+    }
+  }
+}
+
+template <typename T>
+void launch_jac_step(const JacBatch& b, int maxpairs, int maxgch, int maxrch, int step, hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_gram<T>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
+  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step);
+  hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step);
+}
+
+template void launch_jac_step<float>(const JacBatch&, int, int, int, int, hipStream_t);
+template void launch_jac_step<double>(const JacBatch&, int, int, int, int, hipStream_t);
+
+}  // namespace mpo

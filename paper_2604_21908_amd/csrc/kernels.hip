@@ -4,10 +4,7 @@
 //                  complex K step), LDS-staged 64x64 tiles, batched
 //   k_gate         gate pair (G_out (x) G_in^T) on the physical legs of theta,
 //                  lambda scaling, (lambda theta)^dag for the QR preconditioner
-//   k_jac_*        block one-sided (Hestenes) Jacobi SVD: Brent-Luk round-robin
-//                  over 16-column blocks; each block pair's 32x32 Gram matrix
-//                  is diagonalised by a cyclic Jacobi EVD in FP64 in LDS and
-//                  the panel of theta (and V) is rotated by its eigenvectors
+//   k_jac_init / k_jac_sweep_end   state of the block Jacobi SVD (steps: jacobi.hip)
 //   k_colnorms     singular values as column norms (FP64)
 //   k_sort_trunc   descending sort + truncation decision (FP64)
 //   k_env / k_greedy  peak readout of M|0...0> (FP64)
@@ -231,186 +228,6 @@ __global__ void k_jac_init(JacBatch jb) {
       V[i] = cx<T>{(T)(r == c ? 1 : 0), (T)0};
     } else {
       A[i - nv] = cx<T>{0, 0};
-    }
-  }
-}
-
-struct Rot2 {
-  int px, qx;          // pair of this index
-  double jpr, jpi;     // J[px][x]
-  double jqr, jqi;     // J[qx][x]
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_jac_step(JacBatch jb, int step) {
-  const int pi = blockIdx.y;
-  if (pi >= jb.count) return;
-  const JacProb P = jb.p[pi];
-  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
-  if (P.st->active == 0) return;
-  const double tol = P.tol;
-  int bi, bj;
-  rr_pair(P.nblk, step, blockIdx.x, bi, bj);
-
-  __shared__ cx<double> G[2][32][33];
-  __shared__ cx<double> W[2][32][33];
-  __shared__ cx<T> Pc[64][33];
-  __shared__ Rot2 rot[32];
-  __shared__ int flag, anyrot;
-
-  const int tid = threadIdx.x;
-  cx<T>* A = (cx<T>*)P.A;
-  cx<T>* V = (cx<T>*)P.V;
-  const int colbase0 = bi * JB, colbase1 = bj * JB;
-
-  // ---- Gram matrix of the 32-column panel, FP64 accumulation
-  const int gi = tid >> 3, gj0 = (tid & 7) * 4;
-  double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-  for (int r0 = 0; r0 < P.m; r0 += 64) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int c = (tid >> 6) + 4 * u;
-      const int r = tid & 63;
-      const int gc = c < JB ? colbase0 + c : colbase1 + c - JB;
-      cx<T> v = {0, 0};
-      if (r0 + r < P.m) v = A[(size_t)gc * P.lda + r0 + r];
-      Pc[r][c] = v;
-    }
-    __syncthreads();
-    const int rmax = min(64, P.m - r0);
-    for (int r = 0; r < rmax; ++r) {
-      const cx<T> x = Pc[r][gi];
-      const double xr = x.re, xi = x.im;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const cx<T> y = Pc[r][gj0 + u];
-        const double yr = y.re, yi = y.im;
-        ar[u] += xr * yr + xi * yi;   // conj(x) * y
-        ai[u] += xr * yi - xi * yr;
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) flag = 0;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    G[0][gi][gj0 + u] = cx<double>{ar[u], ai[u]};
-    W[0][gi][gj0 + u] = cx<double>{(gi == gj0 + u) ? 1.0 : 0.0, 0.0};
-  }
-  __syncthreads();
-  // ---- convergence test of this panel
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int j = gj0 + u;
-    if (j > gi) {
-      const double d = G[0][gi][gi].re * G[0][j][j].re;
-      const double o = ar[u] * ar[u] + ai[u] * ai[u];
-      if (d > 0 && o > tol * tol * d) flag = 1;
-    }
-  }
-  __syncthreads();
-  if (!flag) return;
-  if (tid == 0) atomicAdd(&P.st->rot, 1);
-
-  // ---- cyclic Jacobi EVD of the 32x32 Hermitian G (FP64), W accumulates J
-  int cur = 0;
-  for (int isw = 0; isw < 16; ++isw) {
-    if (tid == 0) anyrot = 0;
-    __syncthreads();
-    for (int st = 0; st < 31; ++st) {
-      if (tid < 16) {
-        int p, q;
-        rr_pair(32, st, tid, p, q);
-        const double app = G[cur][p][p].re, aqq = G[cur][q][q].re;
-        const cx<double> g = G[cur][p][q];
-        const double mag = sqrt(g.re * g.re + g.im * g.im);
-        double c = 1.0, zr = 0.0, zi = 0.0;
-        if (mag > 0.0 && mag > tol * sqrt(fmax(app * aqq, 0.0))) {
-          const double zeta = (aqq - app) / (2.0 * mag);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          const double s = t * c;
-          zr = s * g.re / mag;
-          zi = s * g.im / mag;
-          anyrot = 1;
-        }
-        // J = [[c, z], [-conj(z), c]] on columns (p, q)
-        rot[p] = Rot2{p, q, c, 0.0, -zr, zi};
-        rot[q] = Rot2{p, q, zr, zi, c, 0.0};
-      }
-      __syncthreads();
-      const int nxt = cur ^ 1;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = gi, c = gj0 + u;
-        const Rot2 R = rot[r], C = rot[c];
-        // G'[r][c] = sum_{x in (px,qx) of r} sum_{y in (px,qx) of c} conj(J[x][r]) G[x][y] J[y][c]
-        const cx<double> g00 = G[cur][R.px][C.px], g01 = G[cur][R.px][C.qx];
-        const cx<double> g10 = G[cur][R.qx][C.px], g11 = G[cur][R.qx][C.qx];
-        // h0 = G[px_r][y] J[y][c] summed over y
-        const double h0r = g00.re * C.jpr - g00.im * C.jpi + g01.re * C.jqr - g01.im * C.jqi;
-        const double h0i = g00.re * C.jpi + g00.im * C.jpr + g01.re * C.jqi + g01.im * C.jqr;
-        const double h1r = g10.re * C.jpr - g10.im * C.jpi + g11.re * C.jqr - g11.im * C.jqi;
-        const double h1i = g10.re * C.jpi + g10.im * C.jpr + g11.re * C.jqi + g11.im * C.jqr;
-        // conj(J[px][r]) h0 + conj(J[qx][r]) h1
-        const double gr = R.jpr * h0r + R.jpi * h0i + R.jqr * h1r + R.jqi * h1i;
-        const double gim = R.jpr * h0i - R.jpi * h0r + R.jqr * h1i - R.jqi * h1r;
-        G[nxt][r][c] = cx<double>{gr, gim};
-        // W' = W J
-        const cx<double> w0 = W[cur][r][C.px], w1 = W[cur][r][C.qx];
-        W[nxt][r][c] = cx<double>{w0.re * C.jpr - w0.im * C.jpi + w1.re * C.jqr - w1.im * C.jqi,
-                                  w0.re * C.jpi + w0.im * C.jpr + w1.re * C.jqi + w1.im * C.jqr};
-      }
-      cur = nxt;
-      __syncthreads();
-    }
-    // read the flag before anyone can reset it for the next sweep
-    const int any = anyrot;
-    __syncthreads();
-    if (!any) break;
-  }
-
-  // ---- rotate the panel of theta (m rows) and of V (ncol rows) by W,
-  // applied as x + x (W - I): W - I is rounded to T entry by entry, so the
-  // rounding error each output picks up from another column is relative to
-  // that (small) coupling, not to the other column's norm.
-  cx<T>(*Wt)[33] = Pc;   // reuse: 32 x 32 of the 64 x 33 staging buffer
-  for (int e = tid; e < 32 * 32; e += 256) {
-    const int r = e >> 5, c = e & 31;
-    Wt[r][c] = cx<T>{(T)(W[cur][r][c].re - (r == c ? 1.0 : 0.0)), (T)W[cur][r][c].im};
-  }
-  __syncthreads();
-  const int nrow_v = V ? P.ncol : 0;
-  for (int rr = tid; rr < P.m + nrow_v; rr += 256) {
-    cx<T>* base;
-    size_t ld;
-    int r;
-    if (rr < P.m) {
-      base = A;
-      ld = P.lda;
-      r = rr;
-    } else {
-      base = V;
-      ld = P.ncol_pad;
-      r = rr - P.m;
-    }
-    cx<T> x[32];
-#pragma unroll
-    for (int c = 0; c < 32; ++c) {
-      const int gc = c < JB ? colbase0 + c : colbase1 + c - JB;
-      x[c] = base[(size_t)gc * ld + r];
-    }
-#pragma unroll 4
-    for (int j = 0; j < 32; ++j) {
-      T re = x[j].re, im = x[j].im;
-#pragma unroll
-      for (int c = 0; c < 32; ++c) {
-        const cx<T> w = Wt[c][j];
-        re += x[c].re * w.re - x[c].im * w.im;
-        im += x[c].re * w.im + x[c].im * w.re;
-      }
-      const int gc = j < JB ? colbase0 + j : colbase1 + j - JB;
-      base[(size_t)gc * ld + r] = cx<T>{re, im};
     }
   }
 }
@@ -677,10 +494,6 @@ template <typename T>
 void launch_jac_init(const JacBatch& b, hipStream_t s) {
   hipLaunchKernelGGL(k_jac_init<T>, dim3(256, b.count), dim3(256), 0, s, b);
 }
-template <typename T>
-void launch_jac_step(const JacBatch& b, int maxpairs, int step, hipStream_t s) {
-  hipLaunchKernelGGL(k_jac_step<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step);
-}
 void launch_jac_sweep_end(const JacBatch& b, hipStream_t s) {
   hipLaunchKernelGGL(k_jac_sweep_end, dim3(1), dim3(64), 0, s, b);
 }
@@ -716,7 +529,6 @@ void launch_convert(cx<TD>* d, const cx<TS>* src, size_t n, hipStream_t s) {
   template void launch_gemm<T>(const GemmBatch&, int, int, hipStream_t);                                 \
   template void launch_gate<T>(const GateBatch&, int, hipStream_t);                                      \
   template void launch_jac_init<T>(const JacBatch&, hipStream_t);                                        \
-  template void launch_jac_step<T>(const JacBatch&, int, int, hipStream_t);                      \
   template void launch_colnorms<T>(const JacBatch&, int, hipStream_t);                                   \
   template void launch_greedy<T>(const cx<T>*, int, int, const cx<double>*, const cx<double>*,           \
                                  cx<double>*, cx<double>*, unsigned char*, double*, hipStream_t);

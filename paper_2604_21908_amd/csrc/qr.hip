@@ -10,11 +10,12 @@
 //   k_qr_panel   one workgroup factors a QNB-column panel (complex Householder
 //                reflectors, LAPACK's sign convention) and builds the
 //                upper-triangular T of the compact WY form; FP64 reductions
-//   k_qr_apply   C <- (I - V op(T) V^dag) C on 32-column tiles: the trailing
+//   k_qr_apply   C <- (I - V op(T) V^dag) C on 16-column tiles: the trailing
 //                update (op = dag) and the formation of V (op = identity)
 //   k_lower_from_r  L = R^dag into the column-major Jacobi operand
 //   k_build_y / k_vh_rows   [W_k; 0] and B_{i+1} <- V_k^dag, lambda_i <- s_<k
 #include "common.h"
+#include "mfma.h"
 
 namespace mpo {
 
@@ -164,39 +165,45 @@ __global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
   }
 }
 
+// 16-column tile of C per workgroup (4 waves).  Phase 1: W1 = V^dag C over
+// rows [p0, n) on MFMA from LDS-staged 64-row slabs, one K range per wave,
+// then a cross-wave sum.  Phase 2: W2 = op(T) W1 (16 x 16, FP64), then
+// C^T <- C^T - W2^T V^T on MFMA with each 16-lane group on 16 consecutive
+// rows of one column of C.
 template <typename T>
 __global__ __launch_bounds__(256) void k_qr_apply(QrApplyBatch ab, int p0) {
   const int pi = blockIdx.y;
   if (pi >= ab.count) return;
   const QrApplyProb P = ab.p[pi];
   if (p0 >= P.r) return;
-  const int cbeg = P.c0 + blockIdx.x * 32;
+  const int cbeg = P.c0 + blockIdx.x * QAT;
   if (cbeg >= P.c1) return;
   const int nb = min(QNB, P.r - p0);
-  const int ncols = min(32, P.c1 - cbeg);
+  const int ncols = min(QAT, P.c1 - cbeg);
   const int n = P.n;
   const cx<T>* M = (const cx<T>*)P.M;
   cx<T>* C = (cx<T>*)P.C;
   const cx<T>* Tf = (const cx<T>*)P.Tf + (size_t)(p0 / QNB) * QNB * QNB;
+  typedef typename MF<T>::acc acc_t;
   __shared__ cx<T> Vs[64][QNB + 1];
-  __shared__ cx<T> Cs[64][33];
-  __shared__ cx<double> W1[QNB][33];
+  __shared__ cx<T> Cs[64][QAT + 1];
+  __shared__ double Wp[4][QNB][QAT][2];
+  __shared__ cx<double> W1[QNB][QAT + 1];
+  __shared__ cx<T> W2[QNB][QAT + 1];
   __shared__ cx<double> Tl[QNB][QNB];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
     const int a = tid / QNB, b = tid % QNB;
-    const cx<T> t = Tf[a * QNB + b];
-    // op(T)[a][b]: T or T^dag
     if (ab.conj_t) {
       const cx<T> u = Tf[b * QNB + a];
       Tl[a][b] = cx<double>{(double)u.re, -(double)u.im};
     } else {
+      const cx<T> t = Tf[a * QNB + b];
       Tl[a][b] = cx<double>{(double)t.re, (double)t.im};
     }
   }
-  // W1 = V^dag C over rows p0..n-1; thread -> (a = tid / 16, cols 2*(tid % 16) + {0, 1})
-  const int wa = tid >> 4, wc = (tid & 15) * 2;
-  double w0r = 0, w0i = 0, w1r = 0, w1i = 0;
+  // ---- phase 1: W1[a][c] = sum_i conj(V[i][a]) C[i][c]
+  acc_t wre = {0, 0, 0, 0}, wim = {0, 0, 0, 0};
   for (int r0 = p0; r0 < n; r0 += 64) {
     for (int e = tid; e < 64 * QNB; e += 256) {
       const int rr = e % 64, a = e / 64, i = r0 + rr;
@@ -207,70 +214,82 @@ __global__ __launch_bounds__(256) void k_qr_apply(QrApplyBatch ab, int p0) {
       }
       Vs[rr][a] = v;
     }
-    for (int e = tid; e < 64 * 32; e += 256) {
+    for (int e = tid; e < 64 * QAT; e += 256) {
       const int rr = e % 64, c = e / 64, i = r0 + rr;
       cx<T> v = {0, 0};
       if (i < n && c < ncols) v = C[(size_t)(cbeg + c) * P.ldc + i];
       Cs[rr][c] = v;
     }
     __syncthreads();
-    const int rmax = min(64, n - r0);
-    for (int rr = 0; rr < rmax; ++rr) {
-      const cx<T> v = Vs[rr][wa];
-      const cx<T> x0 = Cs[rr][wc], x1 = Cs[rr][wc + 1];
-      const double vr = v.re, vi = v.im;
-      w0r += vr * x0.re + vi * x0.im;
-      w0i += vr * x0.im - vi * x0.re;
-      w1r += vr * x1.re + vi * x1.im;
-      w1i += vr * x1.im - vi * x1.re;
+#pragma unroll
+    for (int kk = wave * 16; kk < wave * 16 + 16; kk += 4) {
+      const cx<T> x = Vs[kk + (lane >> 4)][lane & 15];   // A[a][k] = conj(V[k][a])
+      const cx<T> y = Cs[kk + (lane >> 4)][lane & 15];   // B[k][c] = C[k][c]
+      wre = MF<T>::mma(x.re, y.re, wre);
+      wre = MF<T>::mma(x.im, y.im, wre);
+      wim = MF<T>::mma(x.re, y.im, wim);
+      wim = MF<T>::mma(-x.im, y.re, wim);
     }
     __syncthreads();
   }
-  W1[wa][wc] = cx<double>{w0r, w0i};
-  W1[wa][wc + 1] = cx<double>{w1r, w1i};
-  __syncthreads();
-  // W2 = op(T) W1, kept in registers of the thread that owns (wa, wc..wc+1)
-  double y0r = 0, y0i = 0, y1r = 0, y1i = 0;
-  for (int b = 0; b < QNB; ++b) {
-    const cx<double> t = Tl[wa][b], u0 = W1[b][wc], u1 = W1[b][wc + 1];
-    y0r += t.re * u0.re - t.im * u0.im;
-    y0i += t.re * u0.im + t.im * u0.re;
-    y1r += t.re * u1.re - t.im * u1.im;
-    y1i += t.re * u1.im + t.im * u1.re;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a = MF<T>::row(lane, r), c = lane & 15;
+    Wp[wave][a][c][0] = (double)wre[r];
+    Wp[wave][a][c][1] = (double)wim[r];
   }
   __syncthreads();
-  W1[wa][wc] = cx<double>{y0r, y0i};
-  W1[wa][wc + 1] = cx<double>{y1r, y1i};
+  {
+    const int a = tid / QAT, c = tid % QAT;
+    W1[a][c] = cx<double>{Wp[0][a][c][0] + Wp[1][a][c][0] + Wp[2][a][c][0] + Wp[3][a][c][0],
+                          Wp[0][a][c][1] + Wp[1][a][c][1] + Wp[2][a][c][1] + Wp[3][a][c][1]};
+  }
   __syncthreads();
-  // C -= V W2
-  for (int r0 = p0; r0 < n; r0 += 64) {
-    for (int e = tid; e < 64 * QNB; e += 256) {
-      const int rr = e % 64, a = e / 64, i = r0 + rr;
+  {
+    const int a = tid / QAT, c = tid % QAT;
+    double yr = 0, yi = 0;
+    for (int b = 0; b < QNB; ++b) {
+      const cx<double> t = Tl[a][b], u = W1[b][c];
+      yr += t.re * u.re - t.im * u.im;
+      yi += t.re * u.im + t.im * u.re;
+    }
+    W2[a][c] = cx<T>{(T)yr, (T)yi};
+  }
+  __syncthreads();
+  // ---- phase 2: C^T[c][i] -= sum_a W2[a][c] V[i][a], 16-row strips per wave
+  for (int s0 = p0 + wave * 16; s0 < n; s0 += 64) {
+    const int i = s0 + (lane & 15);
+    const bool valid = i < n;
+    acc_t cre, cim;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = MF<T>::row(lane, r);
       cx<T> v = {0, 0};
-      if (i < n && a < nb) {
+      if (valid && c < ncols) v = C[(size_t)(cbeg + c) * P.ldc + i];
+      cre[r] = v.re;
+      cim[r] = v.im;
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < QNB; k0 += 4) {
+      const int a = k0 + (lane >> 4);
+      cx<T> v = {0, 0};
+      if (valid && a < nb) {
         if (i == p0 + a) v = cx<T>{1, 0};
         else if (i > p0 + a) v = M[(size_t)(p0 + a) * n + i];
       }
-      Vs[rr][a] = v;
+      const cx<T> w = W2[a][lane & 15];   // A[c][a] = W2[a][c], negated for the subtraction
+      cre = MF<T>::mma(-w.re, v.re, cre);
+      cre = MF<T>::mma(w.im, v.im, cre);
+      cim = MF<T>::mma(-w.re, v.im, cim);
+      cim = MF<T>::mma(-w.im, v.re, cim);
     }
-    __syncthreads();
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int rr = e % 64, c = e / 64, i = r0 + rr;
-      if (i < n && c < ncols) {
-        double sr = 0, si = 0;
+    if (valid) {
 #pragma unroll
-        for (int a = 0; a < QNB; ++a) {
-          const cx<T> v = Vs[rr][a];
-          const cx<double> w = W1[a][c];
-          sr += (double)v.re * w.re - (double)v.im * w.im;
-          si += (double)v.re * w.im + (double)v.im * w.re;
-        }
-        cx<T>* p = C + (size_t)(cbeg + c) * P.ldc + i;
-        const cx<T> x = *p;
-        *p = cx<T>{(T)((double)x.re - sr), (T)((double)x.im - si)};
+      for (int r = 0; r < 4; ++r) {
+        const int c = MF<T>::row(lane, r);
+        if (c < ncols) C[(size_t)(cbeg + c) * P.ldc + i] = cx<T>{cre[r], cim[r]};
       }
     }
-    __syncthreads();
   }
 }
 
@@ -338,7 +357,7 @@ void launch_qr_panel(const QrBatch& b, int p0, hipStream_t s) {
 }
 template <typename T>
 void launch_qr_apply(const QrApplyBatch& b, int p0, int maxcols, hipStream_t s) {
-  const int gx = (maxcols + 31) / 32;
+  const int gx = (maxcols + QAT - 1) / QAT;
   if (gx < 1) return;
   hipLaunchKernelGGL(k_qr_apply<T>, dim3(gx, b.count), dim3(256), 0, s, b, p0);
 }

@@ -17,7 +17,7 @@ namespace mpo {
 template <typename T> void launch_gemm(const GemmBatch&, int, int, hipStream_t);
 template <typename T> void launch_gate(const GateBatch&, int, hipStream_t);
 template <typename T> void launch_jac_init(const JacBatch&, hipStream_t);
-template <typename T> void launch_jac_step(const JacBatch&, int, int, hipStream_t);
+template <typename T> void launch_jac_step(const JacBatch&, int, int, int, int, hipStream_t);
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
 void launch_sort_trunc(const TruncBatch&, hipStream_t);
@@ -62,7 +62,11 @@ struct Slot {
   void* tau = nullptr;
   void* Tf = nullptr;
   void* Y = nullptr;
+  void* gpart = nullptr;
+  void* dmat = nullptr;
+  int* pflag = nullptr;
   size_t cap_mn = 0, cap_A = 0, cap_V = 0, cap_n = 0, cap_r = 0, cap_Y = 0;
+  size_t cap_pairs = 0, cap_gch = 0;
 };
 
 void dfree(void* p) {
@@ -240,6 +244,23 @@ void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY) {
   }
 }
 
+void ensure_jac(mpo_ctx* h, Slot& s, size_t pairs, size_t gch) {
+  if (s.cap_pairs < pairs || s.cap_gch < gch) {
+    const size_t np = std::max(pairs, s.cap_pairs), ng = std::max(gch, s.cap_gch);
+    dfree(s.gpart);
+    dfree(s.dmat);
+    dfree(s.pflag);
+    s.gpart = s.dmat = nullptr;
+    s.pflag = nullptr;
+    s.cap_pairs = s.cap_gch = 0;
+    s.gpart = dalloc(np * ng * 1024 * sizeof(cx<double>));
+    s.dmat = dalloc(np * 1024 * h->esz);
+    s.pflag = (int*)dalloc(np * sizeof(int));
+    s.cap_pairs = np;
+    s.cap_gch = ng;
+  }
+}
+
 bool finite_gate(const double* g) {
   if (!g) return true;
   for (int i = 0; i < 32; ++i)
@@ -257,7 +278,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     int i, chil, chim, chir, m, n, r, rpad, nblk;
   };
   Shape sh[MAXB];
-  int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0;
+  int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0, maxgch = 1, maxrch = 1;
   for (int p = 0; p < count; ++p) {
     Shape& s = sh[p];
     s.i = reqs[p].bond;
@@ -280,6 +301,9 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     ensure_slot(h, sl, (size_t)s.m * s.n, (size_t)s.m * s.rpad, commit ? (size_t)s.rpad * s.rpad : 0,
                 (size_t)s.rpad);
     ensure_qr(h, sl, (size_t)s.r, commit ? (size_t)s.n * s.r : 0);
+    ensure_jac(h, sl, (size_t)(s.nblk / 2), (size_t)((s.m + GRC - 1) / GRC));
+    maxgch = std::max(maxgch, (s.m + GRC - 1) / GRC);
+    maxrch = std::max(maxrch, (s.m + (commit ? s.r : 0) + RRC - 1) / RRC);
   }
   // gates -> pinned staging -> device (the staging buffer is free: every
   // call ends with a stream synchronisation)
@@ -349,14 +373,15 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   jb.count = count;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
-    jb.p[p] = JacProb{h->slots[p].A, commit ? h->slots[p].V : nullptr, h->states + p, h->slots[p].norms,
-                      tol_for(h, s.m), s.m, s.m, s.r, s.rpad, s.nblk};
+    Slot& sl = h->slots[p];
+    jb.p[p] = JacProb{sl.A, commit ? sl.V : nullptr, h->states + p, sl.norms, (cx<double>*)sl.gpart, sl.dmat,
+                      sl.pflag, tol_for(h, s.m), s.m, s.m, s.r, s.rpad, s.nblk, (int)sl.cap_gch};
   }
   timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
   bool active_left = true;
   for (int sw = 0; sw < h->max_sweeps && active_left; ++sw) {
     for (int step = 0; step < maxblk - 1; ++step)
-      timed(h, MPO_PROF_JACOBI_STEP, [&] { launch_jac_step<T>(jb, maxpairs, step, st); });
+      timed(h, MPO_PROF_JACOBI_STEP, [&] { launch_jac_step<T>(jb, maxpairs, maxgch, maxrch, step, st); });
     launch_jac_sweep_end(jb, st);
     hip_check(hipMemcpyAsync(h->h_states, h->states, count * sizeof(JacState), hipMemcpyDeviceToHost, st),
               "state readback");
@@ -541,6 +566,9 @@ void destroy(mpo_ctx* h) {
     dfree(s.tau);
     dfree(s.Tf);
     dfree(s.Y);
+    dfree(s.gpart);
+    dfree(s.dmat);
+    dfree(s.pflag);
   }
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);
