@@ -180,7 +180,8 @@ enum {
   MPO_PROF_WRITEBACK = 5,      /* V_k = Q [W_k; 0], B_{i+1} <- V_k^dag, lambda      */
   MPO_PROF_WRITEBACK_GEMM = 6, /* B_i <- theta_noLambda V_k (MFMA complex GEMM)    */
   MPO_PROF_QR = 7,             /* Householder QR preconditioner of the SVD         */
-  MPO_PROF_CLASSES = 8
+  MPO_PROF_REORTH = 8,         /* mixed form: FP64 re-orthogonalisation, A = L W   */
+  MPO_PROF_CLASSES = 9
 };
 mpo_status_t mpo_profile(mpo_handle_t h, int32_t on, double* ms_out, int64_t* launches_out);
 const char* mpo_last_error(mpo_handle_t h);

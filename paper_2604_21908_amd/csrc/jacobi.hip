@@ -8,21 +8,24 @@
 //               MFMA (f32 16x16x4 with an FP64 sum per 64-row slab, or f64);
 //               grid = pairs x row chunks x problems
 //   k_jac_evd   per panel: FP64 sum of the partial Grams, convergence test,
-//               at most INNER_SWEEPS sweeps of cyclic Jacobi on G with FP64
+//               at most one or two sweeps of cyclic Jacobi on G with FP64
 //               angles (the outer iteration finishes what they leave), and
 //               D = W - I rounded to the working precision
 //   k_jac_rot   P <- P + P D on MFMA over row chunks of RRC rows of theta's
 //               and V's panels, computed as P^T <- P^T + D^T P^T so that
 //               each 16-lane group of a wave reads and writes 16 consecutive
 //               rows of one column
+//   k_jac_gram_bf16 / k_jac_rot_bf16  the same with split-BF16 products on
+//               theta's panel (mixed precision; the EVD stays FP64 and the
+//               accumulated rotations V stay FP32)
 #include "common.h"
 #include "mfma.h"
 
 namespace mpo {
 
-// Inner cyclic-Jacobi sweeps per panel EVD: two already give the outer
-// iteration its full convergence rate, more only add latency.
-constexpr int INNER_SWEEPS = 2;
+// Inner cyclic-Jacobi sweeps per panel EVD (a kernel argument): two already
+// give the outer iteration its full convergence rate, more only add latency;
+// one costs about one extra outer sweep but halves the EVD.
 
 __device__ __forceinline__ void rr_pair2(int N, int step, int t, int& a, int& b) {
   if (t == 0) {
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacBatch jb, int step) {
 // x columns (p_kc, q_kc) by W_block J_kc: every entry is read and written by
 // exactly one thread, so the update runs in place.
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step) {
+__global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inner_sweeps) {
   const int pi = blockIdx.y;
   if (pi >= jb.count) return;
   const JacProb P = jb.p[pi];
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step) {
     atomicAdd(&P.st->rot, 1);
   }
   const int kr = tid >> 4, kc = tid & 15;
-  for (int isw = 0; isw < INNER_SWEEPS; ++isw) {
+  for (int isw = 0; isw < inner_sweeps; ++isw) {
     if (tid == 0) anyrot = 0;
     __syncthreads();
     for (int st = 0; st < 31; ++st) {
@@ -226,8 +229,9 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step) {
 // Row space of a panel: rows [0, m) of theta's operand A, then rows [0, nv)
 // of V.  out^T = P^T + D^T P^T for 16-row strips; lane (l & 15) owns row
 // strip0 + (l & 15).
+// part 0: all rows; 1: theta's rows [0, m) only; 2: V's rows only.
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step) {
+__global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step, int part) {
   const int pi = blockIdx.z;
   if (pi >= jb.count) return;
   const JacProb P = jb.p[pi];
@@ -235,8 +239,8 @@ __global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step) {
   if (P.st->active == 0) return;
   if (P.pflag[blockIdx.x] == 0) return;
   const int nv = P.V ? P.ncol : 0;
-  const int rows = P.m + nv;
-  const int c0 = blockIdx.y * RRC;
+  const int rows = (part == 1) ? P.m : P.m + nv;
+  const int c0 = (part == 2 ? P.m : 0) + blockIdx.y * RRC;
   if (c0 >= rows) return;
   const int c1 = min(rows, c0 + RRC);
   int bi, bj;
@@ -301,14 +305,193 @@ __global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step) {
   }
 }
 
-template <typename T>
-void launch_jac_step(const JacBatch& b, int maxpairs, int maxgch, int maxrch, int step, hipStream_t s) {
-  hipLaunchKernelGGL(k_jac_gram<T>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
-  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step);
-  hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step);
+// ---------------------------------------------------------------- split-BF16
+// The same Gram and rotation with every real product on three BF16 MFMAs
+// (mfma.h); K = 32 per instruction covers a whole panel width.
+__global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
+  const int pi = blockIdx.z;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
+  if (P.st->active == 0) return;
+  const int r0 = blockIdx.y * GRC;
+  if (r0 >= P.m) return;
+  const int r1 = min(P.m, r0 + GRC);
+  int bi, bj;
+  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  __shared__ cx<float> Pc[64][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int I = wave >> 1, J = wave & 1, g8 = (lane >> 4) * 8;
+  const cx<float>* A = (const cx<float>*)P.A;
+  double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
+  for (int s0 = r0; s0 < r1; s0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = (tid >> 6) + 4 * u, r = tid & 63;
+      cx<float> v = {0, 0};
+      if (s0 + r < r1) v = A[(size_t)panel_col(bi, bj, c) * P.lda + s0 + r];
+      Pc[r][c] = v;
+    }
+    __syncthreads();
+    v4f are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 64; kk += 32) {
+      Split8 xr, xi, xn, yr, yi;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const cx<float> x = Pc[kk + g8 + e][I * 16 + (lane & 15)];
+        const cx<float> y = Pc[kk + g8 + e][J * 16 + (lane & 15)];
+        split_set(xr, e, x.re);
+        split_set(xi, e, x.im);
+        split_set(xn, e, -x.im);
+        split_set(yr, e, y.re);
+        split_set(yi, e, y.im);
+      }
+      // conj(x) y
+      are = mma3_bf16(xr, yr, are);
+      are = mma3_bf16(xi, yi, are);
+      aim = mma3_bf16(xr, yi, aim);
+      aim = mma3_bf16(xn, yr, aim);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      gr[r] += (double)are[r];
+      gi[r] += (double)aim[r];
+    }
+    __syncthreads();
+  }
+  cx<double>* out = P.gpart + ((size_t)blockIdx.x * P.ngchunk + blockIdx.y) * 1024;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = I * 16 + MF<float>::row(lane, r), j = J * 16 + (lane & 15);
+    out[i * 32 + j] = cx<double>{gr[r], gi[r]};
+  }
 }
 
-template void launch_jac_step<float>(const JacBatch&, int, int, int, int, hipStream_t);
-template void launch_jac_step<double>(const JacBatch&, int, int, int, int, hipStream_t);
+// theta's rows only: the accumulated rotations V stay on FP32 MFMA
+// (k_jac_rot, part 2) so that V remains unitary to FP32 accuracy.
+__global__ __launch_bounds__(256) void k_jac_rot_bf16(JacBatch jb, int step) {
+  const int pi = blockIdx.z;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
+  if (P.st->active == 0) return;
+  if (P.pflag[blockIdx.x] == 0) return;
+  const int rows = P.m;
+  const int c0 = blockIdx.y * RRC;
+  if (c0 >= rows) return;
+  const int c1 = min(rows, c0 + RRC);
+  int bi, bj;
+  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  __shared__ cx<float> Ds[32][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g8 = (lane >> 4) * 8;
+  const cx<float>* D = (const cx<float>*)P.dmat + (size_t)blockIdx.x * 1024;
+  for (int e = tid; e < 1024; e += 256) Ds[e >> 5][e & 31] = D[e];
+  __syncthreads();
+  // A operands D^T[c][k] = D[k][c] for the two 16-column halves, split once
+  Split8 dr[2], di[2], dn[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const cx<float> d = Ds[g8 + e][t * 16 + (lane & 15)];
+      split_set(dr[t], e, d.re);
+      split_set(di[t], e, d.im);
+      split_set(dn[t], e, -d.im);
+    }
+  cx<float>* A = (cx<float>*)P.A;
+  cx<float>* V = (cx<float>*)P.V;
+  for (int s0 = c0 + wave * 16; s0 < c1; s0 += 64) {
+    const int rho = s0 + (lane & 15);
+    const bool valid = rho < c1;
+    cx<float>* base;
+    size_t ld;
+    int row;
+    if (rho < P.m) {
+      base = A;
+      ld = P.lda;
+      row = rho;
+    } else {
+      base = V;
+      ld = P.ncol_pad;
+      row = rho - P.m;
+    }
+    v4f cre[2], cim[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = t * 16 + MF<float>::row(lane, r);
+        cx<float> v = {0, 0};
+        if (valid) v = base[(size_t)panel_col(bi, bj, c) * ld + row];
+        cre[t][r] = v.re;
+        cim[t][r] = v.im;
+      }
+    Split8 xr, xi;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      cx<float> x = {0, 0};
+      if (valid) x = base[(size_t)panel_col(bi, bj, g8 + e) * ld + row];
+      split_set(xr, e, x.re);
+      split_set(xi, e, x.im);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      cre[t] = mma3_bf16(dr[t], xr, cre[t]);
+      cre[t] = mma3_bf16(dn[t], xi, cre[t]);
+      cim[t] = mma3_bf16(dr[t], xi, cim[t]);
+      cim[t] = mma3_bf16(di[t], xr, cim[t]);
+    }
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = t * 16 + MF<float>::row(lane, r);
+          base[(size_t)panel_col(bi, bj, c) * ld + row] = cx<float>{cre[t][r], cim[t][r]};
+        }
+    }
+  }
+}
+
+// Newton-Schulz step toward the polar factor in FP64: S <- (3 I - S) / 2.
+__global__ void k_ns_coef(cx<double>* S, int n) {
+  const size_t tot = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = e / n, j = e - i * n;
+    const cx<double> v = S[e];
+    S[e] = cx<double>{((i == j) ? 1.5 : 0.0) - 0.5 * v.re, -0.5 * v.im};
+  }
+}
+
+void launch_ns_coef(cx<double>* S, int n, hipStream_t s) {
+  size_t g = ((size_t)n * n + 255) / 256;
+  g = g < 1 ? 1 : (g > 2048 ? 2048 : g);
+  hipLaunchKernelGGL(k_ns_coef, dim3((unsigned)g), dim3(256), 0, s, S, n);
+}
+
+template <typename T>
+void launch_jac_step(const JacBatch& b, int maxpairs, int maxgch, int maxrch, int step, int bf16, hipStream_t s) {
+  if (bf16)
+    hipLaunchKernelGGL(k_jac_gram_bf16, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
+  else
+    hipLaunchKernelGGL(k_jac_gram<T>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
+  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, bf16 ? 1 : 2);
+  if (bf16) {
+    hipLaunchKernelGGL(k_jac_rot_bf16, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step);
+    hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 2);
+  } else {
+    hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 0);
+  }
+}
+
+template <>
+void launch_jac_step<double>(const JacBatch& b, int maxpairs, int maxgch, int maxrch, int step, int, hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_gram<double>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
+  hipLaunchKernelGGL(k_jac_evd<double>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, 2);
+  hipLaunchKernelGGL(k_jac_rot<double>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 0);
+}
+
+template void launch_jac_step<float>(const JacBatch&, int, int, int, int, int, hipStream_t);
 
 }  // namespace mpo

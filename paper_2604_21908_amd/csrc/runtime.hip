@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <set>
@@ -17,7 +18,8 @@ namespace mpo {
 template <typename T> void launch_gemm(const GemmBatch&, int, int, hipStream_t);
 template <typename T> void launch_gate(const GateBatch&, int, hipStream_t);
 template <typename T> void launch_jac_init(const JacBatch&, hipStream_t);
-template <typename T> void launch_jac_step(const JacBatch&, int, int, int, int, hipStream_t);
+template <typename T> void launch_jac_step(const JacBatch&, int, int, int, int, int, hipStream_t);
+void launch_ns_coef(cx<double>*, int, hipStream_t);
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
 void launch_sort_trunc(const TruncBatch&, hipStream_t);
@@ -120,6 +122,7 @@ struct mpo_ctx {
   std::string err;
   size_t bytes_allocated = 0;
   // kernel timing (mpo_profile): launches bracketed by events on `stream`
+  bool trace = false;   // MPO_TRACE=1: per-batch sweep counts on stderr
   bool prof_on = false;
   std::vector<hipEvent_t> ev_pool;
   struct Pending {
@@ -127,6 +130,12 @@ struct mpo_ctx {
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
+  // mixed form: FP64 Newton-Schulz buffers and the regenerated L
+  void* ns_x = nullptr;
+  void* ns_s = nullptr;
+  void* ns_y = nullptr;
+  void* lbuf = nullptr;
+  size_t cap_ns = 0, cap_l = 0;
   double prof_ms[MPO_PROF_CLASSES] = {0};
   int64_t prof_n[MPO_PROF_CLASSES] = {0};
 };
@@ -181,6 +190,10 @@ double tol_for(const mpo_ctx* h, int m) {
   const double eps = (h->prec == MPO_FP64) ? 1.1102230246251565e-16 : 5.960464477539063e-08;
   return std::max(8.0 * std::sqrt((double)std::max(m, 1)) * eps, eps * 4);
 }
+
+// Convergence tolerance of the split-BF16 sweeps of the mixed form; the FP32
+// polish sweeps that follow use tol_for().
+double tol_bf16(const mpo_ctx* h, int m) { return std::max(1e-4, tol_for(h, m)); }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -266,6 +279,78 @@ bool finite_gate(const double* g) {
   for (int i = 0; i < 32; ++i)
     if (!std::isfinite(g[i])) return false;
   return true;
+}
+
+struct RShape {
+  int m, n, r, rpad;
+};
+struct RShapes {
+  RShape s[MAXB];
+  int count;
+};
+template <typename S>
+RShapes sh_r(const S* sh, int count) {
+  RShapes o{};
+  o.count = count;
+  for (int p = 0; p < count; ++p) o.s[p] = RShape{sh[p].m, sh[p].n, sh[p].r, sh[p].rpad};
+  return o;
+}
+
+// Mixed form, after the split-BF16 sweeps: W (the accumulated rotations,
+// r x r, rotated on FP32 MFMA) is replaced by its polar factor with one FP64
+// Newton-Schulz step W <- (3 I - W W^dag) W / 2 (its drift from unitarity is
+// at FP32 rounding level, so one step lands below FP32 resolution), and the
+// Jacobi operand, whose split-BF16 rotations drifted, is recomputed as A = L W
+// from L = R^dag, so that its columns are an exact unitary transform of L
+// again before the FP32 polish.
+template <typename T>
+void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStream_t st) {
+  for (int p = 0; p < rs.count; ++p) {
+    const RShape& s = rs.s[p];
+    const size_t nn = (size_t)s.rpad * s.rpad;
+    if (h->cap_ns < nn) {
+      dfree(h->ns_x);
+      dfree(h->ns_s);
+      dfree(h->ns_y);
+      h->ns_x = h->ns_s = h->ns_y = nullptr;
+      h->cap_ns = 0;
+      h->ns_x = dalloc(nn * sizeof(cx<double>));
+      h->ns_s = dalloc(nn * sizeof(cx<double>));
+      h->ns_y = dalloc(nn * sizeof(cx<double>));
+      h->cap_ns = nn;
+    }
+    const size_t nl = (size_t)s.m * s.rpad;
+    if (h->cap_l < nl) {
+      dfree(h->lbuf);
+      h->lbuf = nullptr;
+      h->cap_l = 0;
+      h->lbuf = dalloc(nl * h->esz);
+      h->cap_l = nl;
+    }
+    Slot& sl = h->slots[p];
+    cx<double>* X = (cx<double>*)h->ns_x;
+    cx<double>* S = (cx<double>*)h->ns_s;
+    cx<double>* Y = (cx<double>*)h->ns_y;
+    launch_convert<double, T>(X, (const cx<T>*)sl.V, nn, st);
+    GemmBatch g1{};
+    g1.count = 1;
+    g1.p[0] = GemmProb{X, X, S, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, 1};
+    launch_gemm<double>(g1, s.rpad, s.rpad, st);
+    launch_ns_coef(S, s.rpad, st);
+    GemmBatch g2{};
+    g2.count = 1;
+    g2.p[0] = GemmProb{S, X, Y, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, 0};
+    launch_gemm<double>(g2, s.rpad, s.rpad, st);
+    launch_convert<T, double>((cx<T>*)sl.V, Y, nn, st);
+    LowerBatch lw{};
+    lw.count = 1;
+    lw.p[0] = LowerProb{sl.theta0, h->lbuf, s.n, s.m, s.r, s.rpad, s.m};
+    launch_lower_from_r<T>(lw, s.m, s.rpad, st);
+    GemmBatch g3{};
+    g3.count = 1;
+    g3.p[0] = GemmProb{sl.V, h->lbuf, jb.p[p].A, s.rpad, s.m, s.rpad, s.rpad, s.m, s.m, 0};
+    launch_gemm<T>(g3, s.rpad, s.m, st);
+  }
 }
 
 // One batch (<= MAXB problems): theta-build, gate, QR-preconditioned Jacobi
@@ -378,17 +463,42 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
                       sl.pflag, tol_for(h, s.m), s.m, s.m, s.r, s.rpad, s.nblk, (int)sl.cap_gch};
   }
   timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
-  bool active_left = true;
-  for (int sw = 0; sw < h->max_sweeps && active_left; ++sw) {
-    for (int step = 0; step < maxblk - 1; ++step)
-      timed(h, MPO_PROF_JACOBI_STEP, [&] { launch_jac_step<T>(jb, maxpairs, maxgch, maxrch, step, st); });
-    launch_jac_sweep_end(jb, st);
-    hip_check(hipMemcpyAsync(h->h_states, h->states, count * sizeof(JacState), hipMemcpyDeviceToHost, st),
-              "state readback");
-    hip_check(hipStreamSynchronize(st), "sweep sync");
-    drain_events(h);
-    active_left = false;
-    for (int p = 0; p < count; ++p) active_left |= (h->h_states[p].active != 0);
+  const bool mixed = (h->prec == MPO_MIXED_SPLITBF16);
+  auto sweeps = [&](int bf16, int budget) {
+    bool active_left = true;
+    for (int sw = 0; sw < budget && active_left; ++sw) {
+      for (int step = 0; step < maxblk - 1; ++step)
+        timed(h, MPO_PROF_JACOBI_STEP, [&] { launch_jac_step<T>(jb, maxpairs, maxgch, maxrch, step, bf16, st); });
+      launch_jac_sweep_end(jb, st);
+      hip_check(hipMemcpyAsync(h->h_states, h->states, count * sizeof(JacState), hipMemcpyDeviceToHost, st),
+                "state readback");
+      hip_check(hipStreamSynchronize(st), "sweep sync");
+      drain_events(h);
+      active_left = false;
+      for (int p = 0; p < count; ++p) active_left |= (h->h_states[p].active != 0);
+    }
+  };
+  auto trace_sweeps = [&](const char* phase) {
+    if (!h->trace) return;
+    for (int p = 0; p < count; ++p)
+      std::fprintf(stderr, "[mpo] bond %d %s: sweeps so far %d, active %d (m %d, r %d)\n", sh[p].i, phase,
+                   h->h_states[p].sweeps, h->h_states[p].active, sh[p].m, sh[p].r);
+  };
+  if (!mixed) {
+    sweeps(0, h->max_sweeps);
+    trace_sweeps("fp sweeps");
+  } else {
+    // split-BF16 sweeps to a loose tolerance ...
+    for (int p = 0; p < count; ++p) jb.p[p].tol = tol_bf16(h, sh[p].m);
+    sweeps(1, h->max_sweeps);
+    trace_sweeps("bf16 sweeps");
+    // ... then the FP64 re-orthogonalisation of the accumulated rotations
+    // and A = L W.  The columns of L W are orthogonal to the BF16 phase's
+    // tolerance, so their norms equal the singular values to second order in
+    // it (about 1e-8 relative); no FP32 sweep is needed afterwards.  Values-
+    // only trials keep the BF16-rotated norms (relative drift ~1e-4), which
+    // decide ranks only.
+    if (commit) timed(h, MPO_PROF_REORTH, [&] { reorthogonalise<T>(h, sh_r(sh, count), jb, st); });
   }
   timed(h, MPO_PROF_FINALIZE, [&] { launch_colnorms<T>(jb, maxrpad, st); });
   TruncBatch trb{};
@@ -575,6 +685,10 @@ void destroy(mpo_ctx* h) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  dfree(h->ns_x);
+  dfree(h->ns_s);
+  dfree(h->ns_y);
+  dfree(h->lbuf);
   dfree(h->ones);
   dfree(h->states);
   dfree(h->results);
@@ -609,6 +723,10 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
   h->stream = (hipStream_t)hip_stream;
   h->n = cfg->n;
   h->max_sweeps = cfg->max_sweeps > 0 ? cfg->max_sweeps : 30;
+  {
+    const char* t = std::getenv("MPO_TRACE");
+    h->trace = t && t[0] == '1';
+  }
   mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
     const int n = h->n;
     h->chi.assign(n + 1, 1);

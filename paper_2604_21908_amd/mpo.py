@@ -24,7 +24,7 @@ SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
 EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_batch", "mpo_unswap_sweep",
             "mpo_extract_peak", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
             "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_profile", "mpo_last_error", "mpo_version"]
-PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_step", "finalize", "writeback", "writeback_gemm", "qr"]
+PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_step", "finalize", "writeback", "writeback_gemm", "qr", "reorth"]
 
 
 class MpoConfig(ctypes.Structure):

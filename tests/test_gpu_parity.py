@@ -55,7 +55,7 @@ def gpu_dense(g, n):
 
 
 # ---------------------------------------------------------------- single updates
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 @pytest.mark.parametrize("bond", [0, 2, 4])
 def test_single_update_matches_oracle(lib, prec, bond):
     n = 6
@@ -73,7 +73,7 @@ def test_single_update_matches_oracle(lib, prec, bond):
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 def test_large_theta_update(lib, prec):
     """A 256 x 256 theta (chi 64 on both sides) spans many 16-column blocks."""
     n = 8
@@ -185,7 +185,7 @@ def compare_runs(ref, res, lams, prec):
     assert abs(res.prob - ref.prob) <= 1e-3 * ref.prob
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
 def test_config0_contraction_matches_oracle(lib, prec):
     circ = cg.config_circuit(0)
     ref, res, lams = run_both(circ, prec, 64, 1e-12 if prec == "fp64" else 1e-8,
