@@ -77,6 +77,26 @@ def algorithmic_flops(chil, chi, chir, k):
                 total=theta + gate + gram + eig + back + wb)
 
 
+def kernel_flops(cls, chi, sweeps, rotations):
+    """Algorithmic real flops one bond update asks of a kernel class, at
+    (chi_l, chi, chi_r) = (chi, chi, chi): m = r = 4 chi rows/columns, 16-column
+    blocks, 32-column panels.  Rotation: each rotated panel is an
+    (m + r) x 32 x 32 complex product; Gram: every panel of every step is an
+    m x 32 x 32 complex product; theta-build and write-back are the GEMMs'
+    flops.  None where no such count is meaningful (latency-bound kernels)."""
+    m = r = 4 * chi
+    nblk = r // 16
+    if cls == "jacobi_rot":
+        return rotations * (m + r) * 32 * 32 * 8.0
+    if cls == "jacobi_gram":
+        return sweeps * (nblk - 1) * (nblk // 2) * m * 32 * 32 * 8.0
+    if cls == "theta_gemm":
+        return 128.0 * chi ** 3
+    if cls == "writeback_gemm":
+        return 8.0 * m * r * chi
+    return None
+
+
 def cpu_baseline(n, sites, lams, bond, chi, samples=1):
     """The CPU oracle (complex128 NumPy + LAPACK) on the same update shape."""
     from oracle import mpo_oracle as mo
@@ -99,12 +119,53 @@ def cpu_baseline(n, sites, lams, bond, chi, samples=1):
                       f"{dt:.1f} s on {os.cpu_count()} host cores", "seconds": dt, "k": int(r.k)}
 
 
+def run_precision(mpolib, torch, prec_name, args, n, sites, lams, bond, gates):
+    h = mpolib.MPO(n, args.chi, 1e-8, mpolib.CUT_WEIGHT, mpolib.PRECISIONS[prec_name])
+    h.load_state(sites, lams)
+    dims0 = h.bond_dims()
+    for w in range(args.warmup):
+        h.absorb(bond, *gates[w])
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [h.absorb(bond, *gates[args.warmup + s]) for s in range(args.steps)]
+    h.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = h.profile(False)
+    dims1 = h.bond_dims()
+    h.close()
+    return dict(secs=t1 - t0, infos=infos, prof=prof, dims_ok=dims0 == dims1)
+
+
+def roofline_of(run, prec_name, chi, steps):
+    prof = run["prof"]
+    dom = max(prof, key=lambda c: prof[c][0])
+    ms, launches = prof[dom]
+    sweeps = sum(i["sweeps"] for i in run["infos"])
+    rots = sum(i["rotations"] for i in run["infos"])
+    f = kernel_flops(dom, chi, sweeps, rots)
+    if prec_name == "mixed" and dom in ("jacobi_rot", "jacobi_gram"):
+        peak, bound = PEAK_TFLOPS["mixed"], "mfma"        # split-BF16 products: BF16 MFMA peak
+    elif dom == "jacobi_evd":
+        peak, bound = PEAK_TFLOPS["fp64"], "alu"          # FP64 panel EVD, latency bound
+    else:
+        peak, bound = PEAK_TFLOPS["fp64" if prec_name == "fp64" else "fp32"], "mfma"
+    achieved = (f / (ms * 1e-3) / 1e12) if f else None
+    return {"bound": bound, "kernel": dom, "achieved": None if achieved is None else round(achieved, 3),
+            "peak": peak, "unit": "TFLOP/s", "frac": None if achieved is None else round(achieved / peak, 5),
+            "traffic": None, "avg_launch_ms": round(ms / max(launches, 1), 5),
+            "launches_per_update": launches / steps,
+            "algorithmic_flops_per_launch": None if not f else f / max(launches, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--compare", default="fp32", help="second precision timed in the same run ('' for none)")
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -119,53 +180,33 @@ def main():
 
     torch.cuda.set_device(0)
     n, sites, lams, bond = micro_state(args.chi)
-    prec = mpolib.PRECISIONS[args.precision]
-    h = mpolib.MPO(n, args.chi, 1e-8, mpolib.CUT_WEIGHT, prec)
-    h.load_state(sites, lams)
     rng = np.random.default_rng(1234)
     gates = [(haar_su4(rng), haar_su4(rng)) for _ in range(args.warmup + args.steps)]
-    dims0 = h.bond_dims()
-    for w in range(args.warmup):
-        h.absorb(bond, *gates[w])
-    h.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ks, sweeps = [], []
-    for s in range(args.steps):
-        info = h.absorb(bond, *gates[args.warmup + s])
-        ks.append(info["k"])
-        sweeps.append(info["sweeps"])
-    h.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = h.profile(False)
-    dims1 = h.bond_dims()
-    h.close()
-    secs = t1 - t0
-    value = args.steps / secs
     chi = args.chi
+    run = run_precision(mpolib, torch, args.precision, args, n, sites, lams, bond, gates)
+    secs = run["secs"]
+    value = args.steps / secs
     flops = algorithmic_flops(chi, chi, chi, chi)
-    dom = max(prof, key=lambda c: prof[c][0])
-    dom_ms, dom_launches = prof[dom]
-    # algorithmic flops attributed to the dominant kernel class, per update
-    part = {"jacobi_step": flops["svd"], "theta_gemm": flops["theta"], "writeback_gemm": flops["writeback"],
-            "gate": flops["gate"]}.get(dom, flops["total"])
-    achieved = part * args.steps / (dom_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS["fp32" if args.precision == "mixed" else args.precision]
-    roofline = {"bound": "mfma", "kernel": f"k_{dom}", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": None,
-                "avg_launch_ms": dom_ms / max(dom_launches, 1), "launches_per_update": dom_launches / args.steps,
-                "update_roofline_frac": round(flops["total"] / (secs / args.steps) / 1e12 / peak, 5)}
     out = {"metric": "MPO bond updates/s at chi=1024", "value": round(value, 4), "unit": "bond updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * secs / args.steps, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[args.precision],
            "data": "synthetic (seeded random Vidal-form MPO bond, Haar SU(4) gate pairs)",
            "config": {"workload": f"MPO bond update (chi_l, chi, chi_r) = ({chi}, {chi}, {chi}), theta "
                                   f"{4 * chi}x{4 * chi} complex, chi_max {chi}, discarded-weight cutoff 1e-8",
-                      "precision": args.precision, "kept_rank": ks, "jacobi_sweeps": sweeps,
-                      "bond_dims_unchanged": dims0 == dims1},
-           "roofline": roofline,
-           "kernels_ms_per_update": {c: round(v[0] / args.steps, 3) for c, v in prof.items()}}
+                      "precision": args.precision, "kept_rank": [i["k"] for i in run["infos"]],
+                      "jacobi_sweeps": [i["sweeps"] for i in run["infos"]],
+                      "bond_dims_unchanged": run["dims_ok"]},
+           "roofline": roofline_of(run, args.precision, chi, args.steps),
+           "update_roofline_frac": round(flops["total"] / (secs / args.steps) / 1e12 /
+                                         PEAK_TFLOPS["fp32" if args.precision != "fp64" else "fp64"], 5),
+           "kernels_ms_per_update": {c: round(v[0] / args.steps, 3) for c, v in run["prof"].items() if v[1]}}
+    if args.compare and args.compare != args.precision:
+        cmp_run = run_precision(mpolib, torch, args.compare, args, n, sites, lams, bond, gates)
+        out["compare"] = {"precision": args.compare, "value": round(args.steps / cmp_run["secs"], 4),
+                          "ms_per_step": round(1e3 * cmp_run["secs"] / args.steps, 3),
+                          "jacobi_sweeps": [i["sweeps"] for i in cmp_run["infos"]],
+                          "roofline": roofline_of(cmp_run, args.compare, chi, args.steps),
+                          "speedup_of_headline": round(cmp_run["secs"] / secs, 3)}
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, sites, lams, bond, chi)
     print(json.dumps(out), flush=True)

@@ -92,6 +92,8 @@ typedef struct {
   int32_t sweeps;           /* Jacobi sweeps used                              */
   double discarded_weight;  /* sum of dropped s_j^2 (absolute)                 */
   double total_weight;      /* sum of all s_j^2                                */
+  int32_t panel_rotations;  /* 32-column panels rotated over all sweeps        */
+  int32_t reserved;
 } mpo_update_info_t;
 
 typedef struct {
@@ -173,15 +175,17 @@ mpo_status_t mpo_sync(mpo_handle_t h);
  * be NULL), resets them, and then switches profiling on (on != 0) or off. */
 enum {
   MPO_PROF_THETA_GEMM = 0,     /* theta0 = B_i B_{i+1} (MFMA complex GEMM)        */
-  MPO_PROF_GATE = 1,           /* gate pair + lambda, column-major copy for the SVD */
+  MPO_PROF_GATE = 1,           /* gate pair + lambda, (lambda theta)^dag          */
   MPO_PROF_JACOBI_INIT = 2,    /* V = I, padding                                  */
-  MPO_PROF_JACOBI_STEP = 3,    /* one round-robin step of the block Jacobi SVD    */
+  MPO_PROF_JACOBI_GRAM = 3,    /* panel Gram matrices of one round-robin step     */
   MPO_PROF_FINALIZE = 4,       /* column norms, sort, truncation decision         */
   MPO_PROF_WRITEBACK = 5,      /* V_k = Q [W_k; 0], B_{i+1} <- V_k^dag, lambda      */
   MPO_PROF_WRITEBACK_GEMM = 6, /* B_i <- theta_noLambda V_k (MFMA complex GEMM)    */
   MPO_PROF_QR = 7,             /* Householder QR preconditioner of the SVD         */
   MPO_PROF_REORTH = 8,         /* mixed form: FP64 re-orthogonalisation, A = L W   */
-  MPO_PROF_CLASSES = 9
+  MPO_PROF_JACOBI_EVD = 9,     /* FP64 EVD of every panel Gram matrix of a step    */
+  MPO_PROF_JACOBI_ROT = 10,    /* panel rotations of a step                        */
+  MPO_PROF_CLASSES = 11
 };
 mpo_status_t mpo_profile(mpo_handle_t h, int32_t on, double* ms_out, int64_t* launches_out);
 const char* mpo_last_error(mpo_handle_t h);

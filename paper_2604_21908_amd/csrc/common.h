@@ -60,7 +60,7 @@ struct JacState {
   int active;     // still sweeping
   int rot;        // block pairs rotated in the current sweep
   int sweeps;     // sweeps run
-  int pad;
+  int rot_total;  // block pairs rotated over all sweeps
 };
 struct JacProb {
   void* A;        // column-major, lda rows allocated, m used, ncol_pad columns

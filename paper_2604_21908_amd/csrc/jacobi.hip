@@ -471,12 +471,18 @@ void launch_ns_coef(cx<double>* S, int n, hipStream_t s) {
 }
 
 template <typename T>
-void launch_jac_step(const JacBatch& b, int maxpairs, int maxgch, int maxrch, int step, int bf16, hipStream_t s) {
+void launch_jac_gram(const JacBatch& b, int maxpairs, int maxgch, int step, int bf16, hipStream_t s) {
   if (bf16)
     hipLaunchKernelGGL(k_jac_gram_bf16, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
   else
     hipLaunchKernelGGL(k_jac_gram<T>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
-  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, bf16 ? 1 : 2);
+}
+template <typename T>
+void launch_jac_evd(const JacBatch& b, int maxpairs, int step, int inner_sweeps, hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, inner_sweeps);
+}
+template <typename T>
+void launch_jac_rot(const JacBatch& b, int maxpairs, int maxrch, int step, int bf16, hipStream_t s) {
   if (bf16) {
     hipLaunchKernelGGL(k_jac_rot_bf16, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step);
     hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 2);
@@ -484,14 +490,17 @@ void launch_jac_step(const JacBatch& b, int maxpairs, int maxgch, int maxrch, in
     hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 0);
   }
 }
-
 template <>
-void launch_jac_step<double>(const JacBatch& b, int maxpairs, int maxgch, int maxrch, int step, int, hipStream_t s) {
+void launch_jac_gram<double>(const JacBatch& b, int maxpairs, int maxgch, int step, int, hipStream_t s) {
   hipLaunchKernelGGL(k_jac_gram<double>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
-  hipLaunchKernelGGL(k_jac_evd<double>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, 2);
+}
+template <>
+void launch_jac_rot<double>(const JacBatch& b, int maxpairs, int maxrch, int step, int, hipStream_t s) {
   hipLaunchKernelGGL(k_jac_rot<double>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 0);
 }
-
-template void launch_jac_step<float>(const JacBatch&, int, int, int, int, int, hipStream_t);
+template void launch_jac_gram<float>(const JacBatch&, int, int, int, int, hipStream_t);
+template void launch_jac_rot<float>(const JacBatch&, int, int, int, int, hipStream_t);
+template void launch_jac_evd<float>(const JacBatch&, int, int, int, hipStream_t);
+template void launch_jac_evd<double>(const JacBatch&, int, int, int, hipStream_t);
 
 }  // namespace mpo

@@ -216,6 +216,7 @@ __global__ void k_jac_init(JacBatch jb) {
     P.st->active = 1;
     P.st->rot = 0;
     P.st->sweeps = 0;
+    P.st->rot_total = 0;
   }
   const size_t npad = (size_t)P.ncol_pad;
   const size_t nv = P.V ? npad * npad : 0;
@@ -238,6 +239,7 @@ __global__ void k_jac_sweep_end(JacBatch jb) {
   JacState* s = jb.p[i].st;
   if (s->active) {
     s->sweeps += 1;
+    s->rot_total += s->rot;
     if (s->rot == 0) s->active = 0;
     s->rot = 0;
   }

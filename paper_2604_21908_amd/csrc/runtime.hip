@@ -18,7 +18,9 @@ namespace mpo {
 template <typename T> void launch_gemm(const GemmBatch&, int, int, hipStream_t);
 template <typename T> void launch_gate(const GateBatch&, int, hipStream_t);
 template <typename T> void launch_jac_init(const JacBatch&, hipStream_t);
-template <typename T> void launch_jac_step(const JacBatch&, int, int, int, int, int, hipStream_t);
+template <typename T> void launch_jac_gram(const JacBatch&, int, int, int, int, hipStream_t);
+template <typename T> void launch_jac_evd(const JacBatch&, int, int, int, hipStream_t);
+template <typename T> void launch_jac_rot(const JacBatch&, int, int, int, int, hipStream_t);
 void launch_ns_coef(cx<double>*, int, hipStream_t);
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
@@ -92,6 +94,7 @@ struct Req {
 struct Res {
   int k = 0;
   int sweeps = 0;
+  int rotations = 0;
   bool noconv = false;
   bool bad = false;
   double disc = 0, total = 0;
@@ -467,8 +470,11 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   auto sweeps = [&](int bf16, int budget) {
     bool active_left = true;
     for (int sw = 0; sw < budget && active_left; ++sw) {
-      for (int step = 0; step < maxblk - 1; ++step)
-        timed(h, MPO_PROF_JACOBI_STEP, [&] { launch_jac_step<T>(jb, maxpairs, maxgch, maxrch, step, bf16, st); });
+      for (int step = 0; step < maxblk - 1; ++step) {
+        timed(h, MPO_PROF_JACOBI_GRAM, [&] { launch_jac_gram<T>(jb, maxpairs, maxgch, step, bf16, st); });
+        timed(h, MPO_PROF_JACOBI_EVD, [&] { launch_jac_evd<T>(jb, maxpairs, step, bf16 ? 1 : 2, st); });
+        timed(h, MPO_PROF_JACOBI_ROT, [&] { launch_jac_rot<T>(jb, maxpairs, maxrch, step, bf16, st); });
+      }
       launch_jac_sweep_end(jb, st);
       hip_check(hipMemcpyAsync(h->h_states, h->states, count * sizeof(JacState), hipMemcpyDeviceToHost, st),
                 "state readback");
@@ -523,6 +529,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     out[p].total = h->h_results[p].total;
     out[p].bad = h->h_results[p].bad != 0;
     out[p].sweeps = h->h_states[p].sweeps;
+    out[p].rotations = h->h_states[p].rot_total;
     out[p].noconv = h->h_states[p].active != 0;
     anybad |= out[p].bad;
   }
@@ -807,7 +814,7 @@ static mpo_status_t absorb_common(mpo_handle_t h, int32_t count, const int32_t* 
   bool noconv = false;
   for (int p = 0; p < count; ++p) {
     noconv |= res[p].noconv;
-    if (info) info[p] = mpo_update_info_t{res[p].k, res[p].sweeps, res[p].disc, res[p].total};
+    if (info) info[p] = mpo_update_info_t{res[p].k, res[p].sweeps, res[p].disc, res[p].total, res[p].rotations, 0};
   }
   return noconv ? MPO_WARN_NOCONV : MPO_OK;
 }

@@ -24,7 +24,8 @@ SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
 EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_batch", "mpo_unswap_sweep",
             "mpo_extract_peak", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
             "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_profile", "mpo_last_error", "mpo_version"]
-PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_step", "finalize", "writeback", "writeback_gemm", "qr", "reorth"]
+PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_gram", "finalize", "writeback", "writeback_gemm", "qr",
+                "reorth", "jacobi_evd", "jacobi_rot"]
 
 
 class MpoConfig(ctypes.Structure):
@@ -35,7 +36,8 @@ class MpoConfig(ctypes.Structure):
 
 class UpdateInfo(ctypes.Structure):
     _fields_ = [("chi_new", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("discarded_weight", ctypes.c_double), ("total_weight", ctypes.c_double)]
+                ("discarded_weight", ctypes.c_double), ("total_weight", ctypes.c_double),
+                ("panel_rotations", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class UnswapOpts(ctypes.Structure):
@@ -155,7 +157,7 @@ class MPO:
         s = self.lib.mpo_absorb_gate_pair(self.h, bond, po, pi, ctypes.byref(info))
         self._check(s, "mpo_absorb_gate_pair", ok=(0, 1))
         return dict(k=info.chi_new, sweeps=info.sweeps, discarded=info.discarded_weight,
-                    total=info.total_weight, noconv=(s == 1))
+                    total=info.total_weight, rotations=info.panel_rotations, noconv=(s == 1))
 
     def absorb_batch(self, bonds: Sequence[int], g_outs: Sequence, g_ins: Sequence) -> List[dict]:
         cnt = len(bonds)
@@ -173,8 +175,8 @@ class MPO:
         dp = ctypes.POINTER(ctypes.c_double)
         s = self.lib.mpo_absorb_batch(self.h, cnt, b, go.ctypes.data_as(dp), gi.ctypes.data_as(dp), infos)
         self._check(s, "mpo_absorb_batch", ok=(0, 1))
-        return [dict(k=x.chi_new, sweeps=x.sweeps, discarded=x.discarded_weight, total=x.total_weight)
-                for x in infos]
+        return [dict(k=x.chi_new, sweeps=x.sweeps, discarded=x.discarded_weight, total=x.total_weight,
+                     rotations=x.panel_rotations) for x in infos]
 
     def unswap(self, schedule: str = "parallel", relaxed: bool = False, max_iters: int = 20) -> List[Tuple[str, int]]:
         opts = UnswapOpts(1 if schedule == "parallel" else 0, int(relaxed), max_iters)
