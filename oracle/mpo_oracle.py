@@ -164,10 +164,16 @@ def bond_update(m: OracleMPO, i: int, g_out: Optional[np.ndarray], g_in: Optiona
     lam_left = m.lam[i - 1] if i > 0 else np.ones(1)
     theta = theta_nolam * lam_left[:, None, None, None]
     mat = theta.reshape(chil * 4, 4 * chir)
-    if vectors:
-        _, s, vh = np.linalg.svd(mat, full_matrices=False)
-    else:
-        s = np.linalg.svd(mat, compute_uv=False)
+    try:
+        if vectors:
+            _, s, vh = np.linalg.svd(mat, full_matrices=False)
+        else:
+            s = np.linalg.svd(mat, compute_uv=False)
+    except np.linalg.LinAlgError:
+        # LAPACK's divide-and-conquer driver occasionally fails to converge;
+        # the QR-iteration driver computes the same decomposition
+        import scipy.linalg
+        _, s, vh = scipy.linalg.svd(mat, full_matrices=False, lapack_driver="gesvd")
     k = truncation_rank(s, chi_max, cutoff, mode)
     sq = s * s
     res = UpdateResult(bond=i, k=k, s=s, discarded=float(np.sum(sq[k:])), total=float(np.sum(sq)))
