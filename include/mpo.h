@@ -168,6 +168,26 @@ mpo_status_t mpo_load_state(mpo_handle_t h, const int32_t* dims, const double* s
                             const double* lams);
 mpo_status_t mpo_sync(mpo_handle_t h);
 
+/* ---- groups: one batch of bond updates across several MPOs -------------- *
+ * A group owns workspace and a stream but no MPO.  mpo_group_absorb applies
+ * `count` updates, update p on handles[p] at bonds[p] with gates g_out/g_in
+ * (32 doubles each, all-zero or NULL array = identity), through the same
+ * batched kernels as mpo_absorb_batch; the per-update arithmetic is identical
+ * to a call on the handle alone.  Every handle must have the group's
+ * precision, bonds of one handle must be pairwise non-adjacent, and the
+ * handles' own streams must be idle (true between calls, since calls that
+ * return results synchronise).  Errors leave every MPO unchanged.  This is the
+ * building block of the batched and served forms: updates of many resident
+ * circuits share launches. */
+typedef struct mpo_group_s* mpo_group_t;
+mpo_status_t mpo_group_create(int32_t precision, void* hip_stream, mpo_group_t* out);
+void mpo_group_free(mpo_group_t g);
+mpo_status_t mpo_group_absorb(mpo_group_t g, int32_t count, const mpo_handle_t* handles, const int32_t* bonds,
+                              const double* g_out, const double* g_in, mpo_update_info_t* info);
+/* as mpo_profile, for the group's launches */
+mpo_status_t mpo_group_profile(mpo_group_t g, int32_t on, double* ms_out, int64_t* launches_out);
+const char* mpo_group_last_error(mpo_group_t g);
+
 /* Kernel timing.  While profiling is on, every kernel launch of the handle is
  * bracketed by HIP events on the handle's stream and its device time is added
  * to one of the classes below.  A call synchronises the stream, writes the

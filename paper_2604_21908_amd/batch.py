@@ -1,0 +1,127 @@
+"""Batched and served forms: many resident circuits advanced in lockstep.
+
+Each circuit keeps its own device-resident MPO and follows Alg. 1 exactly as
+alone (driver.Contractor: absorb at least one layer pair, keep absorbing while
+size(M) < tau, unswap, repeat; then read the peak).  What changes is only how
+the bond updates reach the GPU: in every round each circuit that is absorbing
+contributes the ordered updates of its next absorption step; those are split
+into waves of mutually distant bonds per circuit, the waves of all circuits are
+merged, sorted by operand shape (chi_l, chi_r) and issued as group launches
+(mpo_group_absorb, up to 32 updates per launch).  Per-update arithmetic is the
+same as alone, so every circuit's result is identical to its lone run.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import driver as dr
+from . import mpo as _mpo
+
+GROUP_MAX = 32
+
+
+class CircuitTask:
+    """Alg. 1 for one circuit as a resumable state machine."""
+
+    def __init__(self, circuit, cfg: dr.RunConfig, tag=None):
+        self.circuit = circuit
+        self.cfg = cfg
+        self.tag = tag
+        self.c = dr.Contractor(circuit, cfg)
+        self.phase_started = False
+        self.result: Optional[dr.RunResult] = None
+        self.t_start = time.perf_counter()
+        self.t_done: Optional[float] = None
+
+    @property
+    def done(self) -> bool:
+        return self.result is not None
+
+    def next_step(self) -> Optional[List[dr.Update]]:
+        """Updates of the next absorption step; runs the unswap stage and the
+        final readout when Alg. 1 reaches them.  None once finished."""
+        c = self.c
+        while True:
+            if not (c.c_left or c.c_right):
+                if self.phase_started:
+                    c.unswap()
+                self.result = c.finish()
+                self.t_done = time.perf_counter()
+                c.close()
+                return None
+            if not self.phase_started:
+                self.phase_started = True
+                return c.plan_absorb()
+            if c.m.total_elements() < self.cfg.tau:
+                return c.plan_absorb()
+            c.unswap()
+            self.phase_started = False
+
+    def shape(self, bond: int):
+        dims = self.c.m.bond_dims()
+        return (1 if bond == 0 else dims[bond - 1], dims[bond + 1] if bond + 1 < len(dims) else 1)
+
+
+def run_round(tasks: Sequence[CircuitTask], group: Optional[_mpo.Group], per_update: bool = False) -> int:
+    """Advances every unfinished task by one absorption step; returns the
+    number of bond updates issued."""
+    steps = []
+    for t in tasks:
+        if t.done:
+            continue
+        ups = t.next_step()
+        if ups:
+            steps.append((t, ups))
+    issued = 0
+    if per_update:
+        for t, ups in steps:
+            infos = [t.c.m.absorb(u.bond, u.g_out, u.g_in) for u in ups]
+            t.c.record(ups, infos)
+            issued += len(ups)
+        return issued
+    # merge the per-circuit waves, shape-sorted, into group launches
+    results: Dict[int, List[Optional[dict]]] = {id(t): [None] * len(ups) for t, ups in steps}
+    waves: List[list] = []
+    for t, ups in steps:
+        for w, idxs in enumerate(dr.wave_split([u.bond for u in ups])):
+            while len(waves) <= w:
+                waves.append([])
+            dims = t.c.m.bond_dims()
+            for i in idxs:
+                b = ups[i].bond
+                key = (1 if b == 0 else dims[b - 1], dims[b + 1] if b + 1 < len(dims) else 1)
+                waves[w].append((key, t, ups, i))
+    for wave in waves:
+        wave.sort(key=lambda x: x[0])
+        for j in range(0, len(wave), GROUP_MAX):
+            chunk = wave[j:j + GROUP_MAX]
+            infos = group.absorb([x[1].c.m for x in chunk], [x[2][x[3]].bond for x in chunk],
+                                 [x[2][x[3]].g_out for x in chunk], [x[2][x[3]].g_in for x in chunk])
+            for (key, t, ups, i), inf in zip(chunk, infos):
+                results[id(t)][i] = inf
+            issued += len(chunk)
+    for t, ups in steps:
+        t.c.record(ups, results[id(t)])
+    return issued
+
+
+def run_batched(circuits_cfgs, precision: str = "fp32", per_update: bool = False) -> dict:
+    """Contracts (circuit, RunConfig) pairs in lockstep; returns results and
+    aggregate throughput."""
+    group = None if per_update else _mpo.Group(_mpo.PRECISIONS[precision])
+    t0 = time.perf_counter()
+    tasks = [CircuitTask(c, cfg, tag=i) for i, (c, cfg) in enumerate(circuits_cfgs)]
+    updates = 0
+    rounds = 0
+    while not all(t.done for t in tasks):
+        updates += run_round(tasks, group, per_update)
+        rounds += 1
+    secs = time.perf_counter() - t0
+    if group is not None:
+        group.close()
+    return dict(results=[t.result for t in tasks], seconds=secs, bond_updates=updates, rounds=rounds,
+                updates_per_s=updates / secs if secs > 0 else 0.0)

@@ -152,15 +152,14 @@ struct TruncProb {
   double* s_sorted;      // descending
   int* perm;             // column index of each sorted value
   TruncResult* res;
+  double cutoff;
   int ncol, ncol_pad;
   int nval;              // number of singular values: min(rows, columns)
+  int chi_max, mode;
 };
 struct TruncBatch {
   TruncProb p[MAXB];
   int count;
-  int chi_max;
-  int mode;
-  double cutoff;
 };
 
 }  // namespace mpo

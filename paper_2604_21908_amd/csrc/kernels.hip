@@ -315,12 +315,12 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(TruncBatch tb) {
     }
     const double s0 = key[0] > 0.0 ? key[0] : 0.0;
     int k;
-    if (tb.mode == 0) {
+    if (P.mode == 0) {
       k = 0;
       for (int j = 0; j < nvals; ++j)
-        if (key[j] > tb.cutoff * s0) ++k;
+        if (key[j] > P.cutoff * s0) ++k;
     } else {
-      const double thr = tb.cutoff * total;
+      const double thr = P.cutoff * total;
       double tail = 0.0;
       k = 0;
       for (int j = nvals - 1; j >= 0; --j) {
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(TruncBatch tb) {
         }
       }
     }
-    if (k > tb.chi_max) k = tb.chi_max;
+    if (k > P.chi_max) k = P.chi_max;
     if (k > nvals) k = nvals;
     if (k < 1) k = 1;
     double disc = 0.0;

@@ -90,6 +90,7 @@ struct Req {
   int bond;
   const double* gout;   // 32 doubles or NULL
   const double* gin;
+  mpo_ctx* owner;       // MPO the update acts on; NULL = the executing handle
 };
 struct Res {
   int k = 0;
@@ -367,12 +368,14 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   };
   Shape sh[MAXB];
   int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0, maxgch = 1, maxrch = 1;
+  auto O = [&](int p) -> mpo_ctx* { return reqs[p].owner ? reqs[p].owner : h; };
   for (int p = 0; p < count; ++p) {
     Shape& s = sh[p];
+    const mpo_ctx* o = O(p);
     s.i = reqs[p].bond;
-    s.chil = h->chi[s.i];
-    s.chim = h->chi[s.i + 1];
-    s.chir = h->chi[s.i + 2];
+    s.chil = o->chi[s.i];
+    s.chim = o->chi[s.i + 1];
+    s.chir = o->chi[s.i + 2];
     s.m = 4 * s.chil;
     s.n = 4 * s.chir;
     s.r = std::min(s.m, s.n);
@@ -410,7 +413,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   gb.count = count;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
-    gb.p[p] = GemmProb{h->site[s.i], h->site[s.i + 1], h->slots[p].theta0, s.m, s.n, s.chim, s.chim, s.n, s.n, 0};
+    gb.p[p] = GemmProb{O(p)->site[s.i], O(p)->site[s.i + 1], h->slots[p].theta0, s.m, s.n, s.chim, s.chim, s.n, s.n, 0};
   }
   timed(h, MPO_PROF_THETA_GEMM, [&] { launch_gemm<T>(gb, maxM, maxN, st); });
 
@@ -420,7 +423,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
     tb.p[p] = GateProb{h->slots[p].theta0, h->slots[p].thetan, h->slots[p].theta0,
-                       s.i > 0 ? h->lam[s.i - 1] : h->ones, h->d_gates + 64 * p, s.chil, s.chir,
+                       s.i > 0 ? O(p)->lam[s.i - 1] : h->ones, h->d_gates + 64 * p, s.chil, s.chir,
                        reqs[p].gout != nullptr, reqs[p].gin != nullptr};
   }
   timed(h, MPO_PROF_GATE, [&] { launch_gate<T>(tb, maxtot, st); });
@@ -463,7 +466,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     const Shape& s = sh[p];
     Slot& sl = h->slots[p];
     jb.p[p] = JacProb{sl.A, commit ? sl.V : nullptr, h->states + p, sl.norms, (cx<double>*)sl.gpart, sl.dmat,
-                      sl.pflag, tol_for(h, s.m), s.m, s.m, s.r, s.rpad, s.nblk, (int)sl.cap_gch};
+                      sl.pflag, tol_for(O(p), s.m), s.m, s.m, s.r, s.rpad, s.nblk, (int)sl.cap_gch};
   }
   timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
   const bool mixed = (h->prec == MPO_MIXED_SPLITBF16);
@@ -495,7 +498,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     trace_sweeps("fp sweeps");
   } else {
     // split-BF16 sweeps to a loose tolerance ...
-    for (int p = 0; p < count; ++p) jb.p[p].tol = tol_bf16(h, sh[p].m);
+    for (int p = 0; p < count; ++p) jb.p[p].tol = tol_bf16(O(p), sh[p].m);
     sweeps(1, h->max_sweeps);
     trace_sweeps("bf16 sweeps");
     // ... then the FP64 re-orthogonalisation of the accumulated rotations
@@ -509,13 +512,11 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   timed(h, MPO_PROF_FINALIZE, [&] { launch_colnorms<T>(jb, maxrpad, st); });
   TruncBatch trb{};
   trb.count = count;
-  trb.chi_max = h->cfg.chi_max;
-  trb.mode = h->cfg.cutoff_mode;
-  trb.cutoff = h->cfg.cutoff;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
-    trb.p[p] = TruncProb{h->slots[p].norms, h->slots[p].s_sorted, h->slots[p].perm, h->results + p, s.r, s.rpad,
-                         s.r};
+    const mpo_ctx* o = O(p);
+    trb.p[p] = TruncProb{h->slots[p].norms, h->slots[p].s_sorted, h->slots[p].perm, h->results + p,
+                         o->cfg.cutoff, s.r, s.rpad, s.r, o->cfg.chi_max, o->cfg.cutoff_mode};
   }
   timed(h, MPO_PROF_FINALIZE, [&] { launch_sort_trunc(trb, st); });
   hip_check(hipMemcpyAsync(h->h_results, h->results, count * sizeof(TruncResult), hipMemcpyDeviceToHost, st),
@@ -549,10 +550,10 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
     const int k = out[p].k;
-    vb.p[p] = VkProb{h->slots[p].V, h->slots[p].perm, h->slots[p].s_sorted, h->slots[p].Y, h->site[s.i + 1],
-                     h->lam[s.i], s.n, s.r, k, s.rpad};
+    vb.p[p] = VkProb{h->slots[p].V, h->slots[p].perm, h->slots[p].s_sorted, h->slots[p].Y, O(p)->site[s.i + 1],
+                     O(p)->lam[s.i], s.n, s.r, k, s.rpad};
     qa.p[p] = QrApplyProb{h->slots[p].theta0, h->slots[p].Tf, h->slots[p].Y, s.n, s.r, s.n, 0, k};
-    lb.p[p] = GemmProb{h->slots[p].thetan, h->site[s.i + 1], h->site[s.i], s.m, k, s.n, s.n, s.n, k, 1};
+    lb.p[p] = GemmProb{h->slots[p].thetan, O(p)->site[s.i + 1], O(p)->site[s.i], s.m, k, s.n, s.n, s.n, k, 1};
     maxel = std::max(maxel, (size_t)k * s.n);
     maxk = std::max(maxk, k);
   }
@@ -561,7 +562,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     timed(h, MPO_PROF_WRITEBACK, [&] { launch_qr_apply<T>(qa, p0, maxk, st); });
   timed(h, MPO_PROF_WRITEBACK, [&] { launch_vh_rows<T>(vb, maxel, st); });
   timed(h, MPO_PROF_WRITEBACK_GEMM, [&] { launch_gemm<T>(lb, maxM, maxk, st); });
-  for (int p = 0; p < count; ++p) h->chi[sh[p].i + 1] = out[p].k;
+  for (int p = 0; p < count; ++p) O(p)->chi[sh[p].i + 1] = out[p].k;
   return MPO_OK;
 }
 
@@ -600,7 +601,7 @@ const double SWAP_G[32] = {1, 0, 0, 0, 0, 0, 0, 0,  0, 0, 0, 0, 1, 0, 0, 0,
                            0, 0, 1, 0, 0, 0, 0, 0,  0, 0, 0, 0, 0, 0, 1, 0};
 
 Req swap_req(int bond, int side) {
-  return Req{bond, (side == 0 || side == 2) ? SWAP_G : nullptr, (side == 1 || side == 2) ? SWAP_G : nullptr};
+  return Req{bond, (side == 0 || side == 2) ? SWAP_G : nullptr, (side == 1 || side == 2) ? SWAP_G : nullptr, nullptr};
 }
 
 template <typename T>
@@ -665,6 +666,22 @@ int64_t pow4_capped(int e, int64_t cap) {
     if (v >= cap) return cap;
   }
   return std::min(v, cap);
+}
+
+// Batch-execution resources of a handle or group: per-problem workspace
+// slots (grown on demand), Jacobi states, truncation results, gate staging.
+void init_workspace(mpo_ctx* h) {
+  h->ones = (double*)dalloc(sizeof(double));
+  h->slots.assign(MAXB, Slot{});
+  h->states = (JacState*)dalloc(MAXB * sizeof(JacState));
+  h->results = (TruncResult*)dalloc(MAXB * sizeof(TruncResult));
+  h->d_gates = (double*)dalloc(MAXB * 64 * sizeof(double));
+  hip_check(hipHostMalloc((void**)&h->h_states, MAXB * sizeof(JacState), hipHostMallocDefault), "pinned");
+  hip_check(hipHostMalloc((void**)&h->h_results, MAXB * sizeof(TruncResult), hipHostMallocDefault), "pinned");
+  hip_check(hipHostMalloc((void**)&h->h_gates, MAXB * 64 * sizeof(double), hipHostMallocDefault), "pinned");
+  const double one = 1.0;
+  hip_check(hipMemcpyAsync(h->ones, &one, sizeof(double), hipMemcpyHostToDevice, h->stream), "ones");
+  hip_check(hipStreamSynchronize(h->stream), "workspace sync");
 }
 
 void destroy(mpo_ctx* h) {
@@ -749,14 +766,7 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
       h->site[i] = dalloc(h->site_cap[i] * h->esz);
     }
     for (int b = 0; b < n - 1; ++b) h->lam[b] = (double*)dalloc(h->bond_cap[b] * sizeof(double));
-    h->ones = (double*)dalloc(sizeof(double));
-    h->slots.assign(MAXB, Slot{});
-    h->states = (JacState*)dalloc(MAXB * sizeof(JacState));
-    h->results = (TruncResult*)dalloc(MAXB * sizeof(TruncResult));
-    h->d_gates = (double*)dalloc(MAXB * 64 * sizeof(double));
-    hip_check(hipHostMalloc((void**)&h->h_states, MAXB * sizeof(JacState), hipHostMallocDefault), "pinned");
-    hip_check(hipHostMalloc((void**)&h->h_results, MAXB * sizeof(TruncResult), hipHostMallocDefault), "pinned");
-    hip_check(hipHostMalloc((void**)&h->h_gates, MAXB * 64 * sizeof(double), hipHostMallocDefault), "pinned");
+    init_workspace(h);
     const double one = 1.0;
     const double hv = 0.70710678118654752440;
     const double idd[8] = {hv, 0, 0, 0, 0, 0, hv, 0};
@@ -767,7 +777,6 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
                 "identity");
     for (int b = 0; b < n - 1; ++b)
       hip_check(hipMemcpyAsync(h->lam[b], &one, sizeof(double), hipMemcpyHostToDevice, h->stream), "lambda init");
-    hip_check(hipMemcpyAsync(h->ones, &one, sizeof(double), hipMemcpyHostToDevice, h->stream), "ones");
     hip_check(hipStreamSynchronize(h->stream), "init sync");
     return MPO_OK;
   });
@@ -780,6 +789,96 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
 }
 
 void mpo_free(mpo_handle_t h) { destroy(h); }
+
+// ---- groups: batched updates across handles --------------------------------
+struct mpo_group_s {
+  mpo_ctx* x;   // executor: a site-less context that owns the workspace
+};
+
+mpo_status_t mpo_group_create(int32_t precision, void* hip_stream, mpo_group_t* out) {
+  if (!out || precision < MPO_FP64 || precision > MPO_MIXED_SPLITBF16) return MPO_EINVAL;
+  *out = nullptr;
+  mpo_ctx* h = new (std::nothrow) mpo_ctx();
+  if (!h) return MPO_ENOMEM;
+  h->cfg.precision = precision;
+  h->prec = precision;
+  h->esz = (precision == MPO_FP64) ? 16 : 8;
+  h->stream = (hipStream_t)hip_stream;
+  h->n = 0;
+  {
+    const char* t = std::getenv("MPO_TRACE");
+    h->trace = t && t[0] == '1';
+  }
+  mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
+    init_workspace(h);
+    return MPO_OK;
+  });
+  if (s != MPO_OK) {
+    destroy(h);
+    return s;
+  }
+  mpo_group_s* g = new (std::nothrow) mpo_group_s{h};
+  if (!g) {
+    destroy(h);
+    return MPO_ENOMEM;
+  }
+  *out = g;
+  return MPO_OK;
+}
+
+void mpo_group_free(mpo_group_t g) {
+  if (!g) return;
+  destroy(g->x);
+  delete g;
+}
+
+mpo_status_t mpo_group_absorb(mpo_group_t g, int32_t count, const mpo_handle_t* handles, const int32_t* bonds,
+                              const double* g_out, const double* g_in, mpo_update_info_t* info) {
+  if (!g) return MPO_EINVAL;
+  mpo_ctx* x = g->x;
+  if (count < 0 || (count > 0 && (!handles || !bonds))) return fail(x, MPO_EINVAL, "bad count/handles/bonds");
+  std::vector<Req> reqs(count);
+  std::vector<std::pair<mpo_ctx*, int>> used;
+  for (int p = 0; p < count; ++p) {
+    mpo_ctx* o = handles[p];
+    if (!o || o->n == 0) return fail(x, MPO_EINVAL, "null handle");
+    if (o->prec != x->prec) return fail(x, MPO_EINVAL, "handle precision differs from the group's");
+    const int b = bonds[p];
+    if (b < 0 || b > o->n - 2) return fail(x, MPO_EINVAL, "bond out of range");
+    const double* go = g_out ? g_out + 32 * p : nullptr;
+    const double* gi = g_in ? g_in + 32 * p : nullptr;
+    bool zo = go != nullptr, zi = gi != nullptr;
+    for (int j = 0; j < 32 && (zo || zi); ++j) {
+      if (go && go[j] != 0.0) zo = false;
+      if (gi && gi[j] != 0.0) zi = false;
+    }
+    if (zo) go = nullptr;
+    if (zi) gi = nullptr;
+    if (!finite_gate(go) || !finite_gate(gi)) return fail(x, MPO_ENUMERIC, "non-finite gate entry");
+    reqs[p] = Req{b, go, gi, o};
+    used.push_back({o, b});
+  }
+  std::sort(used.begin(), used.end());
+  for (size_t j = 1; j < used.size(); ++j)
+    if (used[j].first == used[j - 1].first && used[j].second - used[j - 1].second < 2)
+      return fail(x, MPO_EINVAL, "bonds of one handle in a group call must be non-adjacent");
+  std::vector<Res> res;
+  mpo_status_t s = guarded(x, [&]() { return updates(x, reqs, res, true); });
+  if (s < 0) return s;
+  bool noconv = false;
+  for (int p = 0; p < count; ++p) {
+    noconv |= res[p].noconv;
+    if (info) info[p] = mpo_update_info_t{res[p].k, res[p].sweeps, res[p].disc, res[p].total, res[p].rotations, 0};
+  }
+  return noconv ? MPO_WARN_NOCONV : MPO_OK;
+}
+
+mpo_status_t mpo_group_profile(mpo_group_t g, int32_t on, double* ms_out, int64_t* launches_out) {
+  if (!g) return MPO_EINVAL;
+  return mpo_profile(g->x, on, ms_out, launches_out);
+}
+
+const char* mpo_group_last_error(mpo_group_t g) { return g ? g->x->err.c_str() : "null group"; }
 
 static mpo_status_t absorb_common(mpo_handle_t h, int32_t count, const int32_t* bonds, const double* g_out,
                                   const double* g_in, mpo_update_info_t* info, bool batch_form) {
@@ -802,7 +901,7 @@ static mpo_status_t absorb_common(mpo_handle_t h, int32_t count, const int32_t* 
       if (zi) gi = nullptr;
     }
     if (!finite_gate(go) || !finite_gate(gi)) return fail(h, MPO_ENUMERIC, "non-finite gate entry");
-    reqs[p] = Req{b, go, gi};
+    reqs[p] = Req{b, go, gi, nullptr};
     sorted.push_back(b);
   }
   std::sort(sorted.begin(), sorted.end());

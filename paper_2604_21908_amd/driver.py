@@ -177,15 +177,30 @@ class Contractor:
         else:
             for i, u in enumerate(ups):
                 infos[i] = self.m.absorb(u.bond, u.g_out, u.g_in)
+        self.record(ups, infos)
+
+    def plan_absorb(self) -> List[Update]:
+        """Pops the innermost layer of each side and returns the ordered
+        updates of that absorption step (layouts change by routing)."""
+        lg = self.c_left.pop(0) if self.c_left else []
+        rg = self.c_right.pop(0) if self.c_right else []
+        return plan_step(lg, rg, self.out_w, self.in_w)
+
+    def record(self, ups: List[Update], infos: List[dict]) -> None:
         for u, r in zip(ups, infos):
             self.trace.append(dict(stage=u.stage, bond=u.bond, k=r["k"], discarded=r["discarded"],
                                    total=r["total"], sweeps=r["sweeps"]))
         self.bond_updates += len(ups)
 
     def absorb_step(self):
-        lg = self.c_left.pop(0) if self.c_left else []
-        rg = self.c_right.pop(0) if self.c_right else []
-        self._execute(plan_step(lg, rg, self.out_w, self.in_w))
+        self._execute(self.plan_absorb())
+
+    def finish(self) -> RunResult:
+        site_bits, p, n2 = self.m.extract_peak()
+        bits = site_bits[self.out_w.site_of]
+        return RunResult(bits.astype(np.uint8), p, n2, site_bits, list(map(int, self.out_w.site_of)),
+                         list(map(int, self.in_w.site_of)), self.trace, 0.0, self.bond_updates,
+                         self.trial_updates)
 
     def unswap(self):
         if self.cfg.unswap == "none":

@@ -23,7 +23,8 @@ SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
 
 EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_batch", "mpo_unswap_sweep",
             "mpo_extract_peak", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
-            "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_profile", "mpo_last_error", "mpo_version"]
+            "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_profile", "mpo_last_error", "mpo_version",
+            "mpo_group_create", "mpo_group_free", "mpo_group_absorb", "mpo_group_profile", "mpo_group_last_error"]
 PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_gram", "finalize", "writeback", "writeback_gemm", "qr",
                 "reorth", "jacobi_evd", "jacobi_rot"]
 
@@ -85,8 +86,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mpo_last_error.restype = ctypes.c_char_p
     lib.mpo_version.argtypes = []
     lib.mpo_version.restype = ctypes.c_char_p
+    lib.mpo_group_create.argtypes = [I32, P, ctypes.POINTER(P)]
+    lib.mpo_group_free.argtypes = [P]
+    lib.mpo_group_free.restype = None
+    lib.mpo_group_absorb.argtypes = [P, I32, ctypes.POINTER(P), ctypes.POINTER(I32), dp, dp,
+                                     ctypes.POINTER(UpdateInfo)]
+    lib.mpo_group_profile.argtypes = [P, I32, dp, ctypes.POINTER(I64)]
+    lib.mpo_group_last_error.argtypes = [P]
+    lib.mpo_group_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("mpo_free", "mpo_last_error", "mpo_version"):
+        if name not in ("mpo_free", "mpo_last_error", "mpo_version", "mpo_group_free", "mpo_group_last_error"):
             getattr(lib, name).restype = ctypes.c_int32
     _lib = lib
     return lib
@@ -245,6 +254,63 @@ class MPO:
         cnt = (ctypes.c_int64 * nc)()
         s = self.lib.mpo_profile(self.h, int(on), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cnt)
         self._check(s, "mpo_profile")
+        return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(PROF_CLASSES)}
+
+
+def _pack_gates(gs, cnt):
+    out = np.zeros((cnt, 32))
+    for j in range(cnt):
+        if gs[j] is not None:
+            out[j] = np.ascontiguousarray(np.asarray(gs[j], np.complex128)).view(np.float64).reshape(32)
+    return out
+
+
+class Group:
+    """Workspace + stream shared by batched updates of several MPOs
+    (mpo_group_*): one call applies updates on many handles at once."""
+
+    def __init__(self, precision: int = FP64, stream=None):
+        self.lib = load_library()
+        g = ctypes.c_void_p()
+        st = stream if stream is not None else _current_stream()
+        s = self.lib.mpo_group_create(precision, st, ctypes.byref(g))
+        if s != 0:
+            raise MpoError(s, "mpo_group_create failed")
+        self.g = g
+
+    def close(self):
+        if getattr(self, "g", None):
+            self.lib.mpo_group_free(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def absorb(self, mpos: Sequence["MPO"], bonds: Sequence[int], g_outs: Sequence, g_ins: Sequence) -> List[dict]:
+        cnt = len(bonds)
+        if cnt == 0:
+            return []
+        hs = (ctypes.c_void_p * cnt)(*[m.h.value for m in mpos])
+        b = (ctypes.c_int32 * cnt)(*bonds)
+        go, gi = _pack_gates(g_outs, cnt), _pack_gates(g_ins, cnt)
+        infos = (UpdateInfo * cnt)()
+        dp = ctypes.POINTER(ctypes.c_double)
+        s = self.lib.mpo_group_absorb(self.g, cnt, hs, b, go.ctypes.data_as(dp), gi.ctypes.data_as(dp), infos)
+        if s not in (0, 1):
+            raise MpoError(s, "mpo_group_absorb: " + self.lib.mpo_group_last_error(self.g).decode())
+        return [dict(k=x.chi_new, sweeps=x.sweeps, discarded=x.discarded_weight, total=x.total_weight,
+                     rotations=x.panel_rotations) for x in infos]
+
+    def profile(self, on: bool) -> dict:
+        nc = len(PROF_CLASSES)
+        ms = np.zeros(nc)
+        cnt = (ctypes.c_int64 * nc)()
+        s = self.lib.mpo_group_profile(self.g, int(on), ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cnt)
+        if s != 0:
+            raise MpoError(s, "mpo_group_profile")
         return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(PROF_CLASSES)}
 
 

@@ -1,0 +1,123 @@
+"""Served form: continuous batching of circuit requests on one GPU.
+
+Requests arrive over time (e.g. Poisson).  A request is admitted when a slot
+is free and its projected MPO memory n * chi_max^2 * 16 B fits in what the
+admitted requests leave of the budget; admitted circuits stay resident on the
+device.  Every scheduling round advances all resident circuits by one
+absorption step through shared group launches (batch.run_round), so requests
+that arrive while others are on the GPU join the running batch at the next
+round and their work overlaps on the device.  A finished circuit releases its
+slot and memory at once.  Time-to-peak is measured from arrival to the end of
+its peak readout.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+
+from . import batch as bt
+from . import circuitgen as cg
+from . import driver as dr
+from . import mpo as _mpo
+
+
+@dataclasses.dataclass
+class Request:
+    t_arrival: float
+    n: int
+    depth: int
+    seed: int
+
+
+@dataclasses.dataclass
+class Served:
+    request: Request
+    t_admit: float
+    t_done: float
+    bits_ok: bool
+    prob: float
+    updates: int
+
+    @property
+    def time_to_peak(self) -> float:
+        return self.t_done - self.request.t_arrival
+
+
+def projected_bytes(n: int, chi_max: int) -> int:
+    return n * chi_max * chi_max * 16
+
+
+def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max_slots: int = 64,
+          reading: str = "A", on_round: Optional[Callable[[int, int], None]] = None) -> dict:
+    reqs = sorted(requests, key=lambda r: r.t_arrival)
+    group = _mpo.Group(_mpo.PRECISIONS[cfg.precision])
+    pending: collections.deque = collections.deque()
+    active: List[tuple] = []
+    done: List[Served] = []
+    used = 0
+    peak_used = 0
+    i = 0
+    rounds = 0
+    t0 = time.perf_counter()
+    while i < len(reqs) or pending or active:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i].t_arrival <= now:
+            pending.append(reqs[i])
+            i += 1
+        while pending and len(active) < max_slots:
+            r = pending[0]
+            need = projected_bytes(r.n, cfg.chi_max)
+            if used + need > budget_bytes and active:
+                break
+            pending.popleft()
+            circ = cg.mirrored_peaked_circuit(r.n, r.depth, r.seed, reading=reading)
+            active.append((r, bt.CircuitTask(circ, cfg), time.perf_counter() - t0, need))
+            used += need
+            peak_used = max(peak_used, used)
+        if not active:
+            if i < len(reqs):
+                time.sleep(max(0.0, min(0.05, reqs[i].t_arrival - (time.perf_counter() - t0))))
+            continue
+        bt.run_round([a[1] for a in active], group)
+        rounds += 1
+        if on_round:
+            on_round(rounds, len(active))
+        still = []
+        for (r, task, t_adm, need) in active:
+            if task.done:
+                res = task.result
+                done.append(Served(r, t_adm, task.t_done - t0, bool((res.bits == task.circuit.peak).all()),
+                                   float(res.prob), res.bond_updates))
+                used -= need
+            else:
+                still.append((r, task, t_adm, need))
+        active = still
+    secs = time.perf_counter() - t0
+    group.close()
+    ttp = np.array([d.time_to_peak for d in done]) if done else np.zeros(1)
+    return dict(served=done, seconds=secs, rounds=rounds, circuits_per_s=len(done) / secs if secs else 0.0,
+                p50=float(np.percentile(ttp, 50)), p99=float(np.percentile(ttp, 99)),
+                all_peaks_ok=all(d.bits_ok for d in done), peak_projected_bytes=peak_used,
+                bond_updates=sum(d.updates for d in done))
+
+
+def poisson_requests(rate: float, duration: float, seed: int = 4000, sizes=(24, 40, 56),
+                     probs=(0.5, 0.3, 0.2)) -> List[Request]:
+    """Arrivals of the serving workload: exponential gaps at `rate`/s over
+    `duration` s; n drawn from `sizes` with `probs`; depth n/4."""
+    rng = np.random.Generator(np.random.PCG64(seed + int(rate * 1000)))
+    t = 0.0
+    out = []
+    k = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        n = int(rng.choice(list(sizes), p=list(probs)))
+        out.append(Request(t, n, max(1, n // 4), seed + 17 * k + 1))
+        k += 1
+    return out

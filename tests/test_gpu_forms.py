@@ -1,0 +1,58 @@
+"""Batched and served forms on the GPU: every circuit's result is the same
+alone and in the mix (bitwise: the batched kernels compute each update
+independently and deterministically)."""
+import numpy as np
+import pytest
+
+from paper_2604_21908_amd import circuitgen as cg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2604_21908_amd import batch as bt, driver as dr, serve as sv
+    return bt, dr, sv
+
+
+def lone(dr, circ, cfg):
+    c = dr.Contractor(circ, cfg)
+    res = c.run()
+    lams = [c.m.singular_values(b) for b in range(circ.n - 1)]
+    c.close()
+    return res, lams
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_equals_alone(mods, prec):
+    bt, dr, sv = mods
+    circs = [cg.mirrored_peaked_circuit(n, d, 50 + n, reading="A") for n, d in ((8, 3), (11, 2), (10, 4))]
+    cfgs = [dr.RunConfig(chi_max=chi, cutoff=1e-10, cutoff_mode="weight", precision=prec, tau=tau)
+            for chi, tau in ((32, 300), (64, 1e9), (16, 200))]
+    out = bt.run_batched(list(zip(circs, cfgs)), precision=prec)
+    for circ, cfg, res in zip(circs, cfgs, out["results"]):
+        ref, _ = lone(dr, circ, cfg)
+        assert np.array_equal(res.bits, ref.bits)
+        assert res.prob == ref.prob
+        assert [t.get("k") for t in res.trace] == [t.get("k") for t in ref.trace]
+    per = bt.run_batched(list(zip(circs, cfgs)), precision=prec, per_update=True)
+    for a, b in zip(out["results"], per["results"]):
+        assert np.array_equal(a.bits, b.bits) and a.prob == b.prob
+
+
+def test_serving_admits_within_budget_and_matches_alone(mods):
+    bt, dr, sv = mods
+    cfg = dr.RunConfig(chi_max=32, cutoff=1e-8, cutoff_mode="weight", precision="mixed", tau=2000)
+    reqs = [sv.Request(0.0, 8, 2, 11), sv.Request(0.0, 12, 3, 12), sv.Request(0.01, 10, 2, 13),
+            sv.Request(0.02, 8, 3, 14)]
+    budget = sv.projected_bytes(12, 32) + sv.projected_bytes(10, 32)      # at most two resident
+    out = sv.serve(reqs, cfg, budget)
+    assert len(out["served"]) == 4 and out["all_peaks_ok"]
+    assert out["peak_projected_bytes"] <= budget
+    for s in out["served"]:
+        circ = cg.mirrored_peaked_circuit(s.request.n, s.request.depth, s.request.seed, reading="A")
+        ref, _ = lone(dr, circ, cfg)
+        assert s.prob == ref.prob
+        assert s.time_to_peak >= 0
