@@ -77,6 +77,19 @@ def algorithmic_flops(chil, chi, chir, k):
                 total=theta + gate + gram + eig + back + wb)
 
 
+def kernel_bytes(cls, chi, sweeps, rotations, esz):
+    """Algorithmic HBM bytes one bond update asks of a memory-bound kernel
+    class: a rotated panel reads and writes its (m + r) x 32 complex entries
+    (theta's rows and V's rows); a Gram step reads m x 32 entries per pair."""
+    m = r = 4 * chi
+    nblk = r // 16
+    if cls == "jacobi_rot":
+        return rotations * (m + r) * 32 * 2 * esz
+    if cls == "jacobi_gram":
+        return sweeps * (nblk - 1) * (nblk // 2) * m * 32 * esz
+    return None
+
+
 def kernel_flops(cls, chi, sweeps, rotations):
     """Algorithmic real flops one bond update asks of a kernel class, at
     (chi_l, chi, chi_r) = (chi, chi, chi): m = r = 4 chi rows/columns, 16-column
@@ -138,25 +151,47 @@ def run_precision(mpolib, torch, prec_name, args, n, sites, lams, bond, gates):
     return dict(secs=t1 - t0, infos=infos, prof=prof, dims_ok=dims0 == dims1)
 
 
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAME = {"jacobi_rot": "k_jac_rot", "jacobi_gram": "k_jac_gram", "jacobi_evd": "k_jac_evd",
+               "qr": "k_qr_panel+k_qr_apply", "theta_gemm": "k_gemm", "writeback_gemm": "k_gemm"}
+
+
 def roofline_of(run, prec_name, chi, steps):
+    """Roofline of the dominant kernel class (largest event-timed device
+    time).  The panel rotation does 32 complex multiply-adds per complex entry
+    it reads and writes: 16 real flops per byte in FP32, 8 in FP64, below the
+    MFMA ridges (157.3 / 8 and 78.6 / 8 flops per byte), so it is priced in
+    bytes against 8 TB/s.  The Gram step reads only (32 flops per byte in
+    FP32): MFMA-bound in FP32/FP64, HBM-bound with split-BF16 products.
+    GEMM-shaped kernels are priced in flops against the MFMA peak of their
+    dtype; the FP64 panel EVD against the FP64 rate."""
     prof = run["prof"]
     dom = max(prof, key=lambda c: prof[c][0])
     ms, launches = prof[dom]
     sweeps = sum(i["sweeps"] for i in run["infos"])
     rots = sum(i["rotations"] for i in run["infos"])
+    esz = 16 if prec_name == "fp64" else 8
+    hbm_bound = dom == "jacobi_rot" or (dom == "jacobi_gram" and prec_name == "mixed")
+    byt = kernel_bytes(dom, chi, sweeps, rots, esz) if hbm_bound else None
+    out = {"kernel": KERNEL_NAME.get(dom, dom), "class": dom, "avg_launch_ms": round(ms / max(launches, 1), 5),
+           "launches_per_update": launches / steps, "traffic": None}
+    if byt:
+        achieved = byt / (ms * 1e-3) / 1e9
+        out.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": byt / max(launches, 1)})
+        f = kernel_flops(dom, chi, sweeps, rots)
+        out["tflops"] = round(f / (ms * 1e-3) / 1e12, 3)
+        return out
     f = kernel_flops(dom, chi, sweeps, rots)
-    if prec_name == "mixed" and dom in ("jacobi_rot", "jacobi_gram"):
-        peak, bound = PEAK_TFLOPS["mixed"], "mfma"        # split-BF16 products: BF16 MFMA peak
-    elif dom == "jacobi_evd":
-        peak, bound = PEAK_TFLOPS["fp64"], "alu"          # FP64 panel EVD, latency bound
+    if dom == "jacobi_evd" or f is None:
+        peak, bound = PEAK_TFLOPS["fp64"], "alu"
     else:
         peak, bound = PEAK_TFLOPS["fp64" if prec_name == "fp64" else "fp32"], "mfma"
     achieved = (f / (ms * 1e-3) / 1e12) if f else None
-    return {"bound": bound, "kernel": dom, "achieved": None if achieved is None else round(achieved, 3),
-            "peak": peak, "unit": "TFLOP/s", "frac": None if achieved is None else round(achieved / peak, 5),
-            "traffic": None, "avg_launch_ms": round(ms / max(launches, 1), 5),
-            "launches_per_update": launches / steps,
-            "algorithmic_flops_per_launch": None if not f else f / max(launches, 1)}
+    out.update({"bound": bound, "achieved": None if achieved is None else round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": None if achieved is None else round(achieved / peak, 5),
+                "algorithmic_flops_per_launch": None if not f else f / max(launches, 1)})
+    return out
 
 
 def main():

@@ -1,0 +1,103 @@
+"""Measurements of the batched and served forms (one JSON line each).
+
+    python -m paper_2604_21908_amd.forms_bench batch --count 16
+    python -m paper_2604_21908_amd.forms_bench serve --rate 1 --duration 10
+
+batch: the first `count` circuits of the batching workload (n ~ U{16..48},
+depth ~ U{4..10}, chi_max ~ U{128, 256, 512}, literal reading, FP32),
+contracted in lockstep with group launches and again with one launch per
+update; aggregate bond updates/s and makespan of both.
+serve: Poisson arrivals at `rate`/s for `duration` s, n in {24, 40, 56}
+(p = 0.5/0.3/0.2), depth n/4, chi_max 512, mixed precision, admission by
+projected n chi^2 16 B within `budget_gb`; p50/p99 time-to-peak from arrival
+and circuits/s.  --max-n and --chi-cap bound both workloads (widest circuit,
+largest chi_max) so a run fits a time budget."""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+from . import batch as bt
+from . import circuitgen as cg
+from . import driver as dr
+from . import serve as sv
+
+
+def _progress(tag):
+    last = [time.perf_counter()]
+
+    def cb(rounds, active):
+        now = time.perf_counter()
+        if now - last[0] > 3.0:
+            print(f"  [{tag}] round {rounds}, resident {active}", flush=True)
+            last[0] = now
+    return cb
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("form", choices=["batch", "serve"])
+    ap.add_argument("--count", type=int, default=16)
+    ap.add_argument("--tau", type=float, default=1e5)
+    ap.add_argument("--rate", type=float, default=1.0)
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--max-n", type=int, default=64, help="skip workload circuits wider than this")
+    ap.add_argument("--chi-cap", type=int, default=1024, help="clip the workload's chi_max to this")
+    a = ap.parse_args(argv)
+    if a.form == "batch":
+        prec = a.precision or "fp32"
+        work = []
+        for circ, chi in cg.batch_workload(128):
+            if len(work) == a.count:
+                break
+            if circ.n > a.max_n:
+                continue
+            circ = cg.mirrored_peaked_circuit(circ.n, circ.meta["depth"], circ.meta["seed"], reading="A")
+            work.append((circ, dr.RunConfig(chi_max=min(chi, a.chi_cap), cutoff=1e-8, cutoff_mode="weight",
+                                            precision=prec, tau=a.tau)))
+        print(f"  batch of {len(work)} circuits, n = {[c.n for c, _ in work]}, "
+              f"chi_max = {[c.chi_max for _, c in work]}", flush=True)
+        orig = bt.run_round
+        rounds = [0]
+
+        def counted(tasks, group, per_update=False):
+            rounds[0] += 1
+            if rounds[0] % 10 == 0:
+                print(f"  round {rounds[0]} ({'per-update' if per_update else 'grouped'})", flush=True)
+            return orig(tasks, group, per_update)
+        bt.run_round = counted
+        g = bt.run_batched(work, precision=prec)
+        rounds[0] = 0
+        p = bt.run_batched(work, precision=prec, per_update=True)
+        ok = all((r.bits == c.peak).all() for r, (c, _) in zip(g["results"], work))
+        same = all((x.bits == y.bits).all() and x.prob == y.prob for x, y in zip(g["results"], p["results"]))
+        print(json.dumps({"form": "batch", "circuits": len(work), "precision": prec, "tau": a.tau,
+                          "n": [c.n for c, _ in work], "chi_max": [c.chi_max for _, c in work],
+                          "grouped": {"seconds": round(g["seconds"], 3), "bond_updates": g["bond_updates"],
+                                      "updates_per_s": round(g["updates_per_s"], 1)},
+                          "per_update_launch": {"seconds": round(p["seconds"], 3), "bond_updates": p["bond_updates"],
+                                                "updates_per_s": round(p["updates_per_s"], 1)},
+                          "speedup": round(p["seconds"] / g["seconds"], 3), "peaks_ok": bool(ok),
+                          "grouped_equals_per_update": bool(same)}), flush=True)
+    else:
+        prec = a.precision or "mixed"
+        cfg = dr.RunConfig(chi_max=min(512, a.chi_cap), cutoff=1e-8, cutoff_mode="weight", precision=prec,
+                           tau=a.tau)
+        reqs = [r for r in sv.poisson_requests(a.rate, a.duration) if r.n <= a.max_n]
+        print(f"  {len(reqs)} requests, n = {[r.n for r in reqs]}", flush=True)
+        out = sv.serve(reqs, cfg, int(a.budget_gb * 2 ** 30), on_round=_progress("serve"))
+        print(json.dumps({"form": "serve", "rate": a.rate, "duration": a.duration, "requests": len(reqs),
+                          "chi_max": cfg.chi_max, "max_n": a.max_n,
+                          "served": len(out["served"]), "precision": prec, "seconds": round(out["seconds"], 3),
+                          "circuits_per_s": round(out["circuits_per_s"], 4), "p50_time_to_peak_s": round(out["p50"], 3),
+                          "p99_time_to_peak_s": round(out["p99"], 3), "all_peaks_ok": out["all_peaks_ok"],
+                          "bond_updates": out["bond_updates"],
+                          "peak_projected_gb": round(out["peak_projected_bytes"] / 2 ** 30, 3)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

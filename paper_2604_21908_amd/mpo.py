@@ -64,6 +64,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libmpo.so is not built ({path}); run `python -m paper_2604_21908_amd.build`")
+    # torch ships its own HIP runtime.  Loaded first, it also serves libmpo's
+    # libamdhip64 dependency, so the process holds one runtime and the streams
+    # torch hands over are valid in libmpo.  Loaded the other way round, the
+    # process would hold two runtimes and torch's streams would be foreign to
+    # libmpo.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     dp = ctypes.POINTER(ctypes.c_double)

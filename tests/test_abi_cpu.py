@@ -114,3 +114,18 @@ def test_wave_split_respects_dependencies():
             for j in range(i):
                 if abs(bonds[i] - bonds[j]) <= 1:
                     assert where[j] < where[i]
+
+
+def test_binding_loads_a_single_hip_runtime():
+    """Loading libmpo before anything else imports torch must still leave one
+    HIP runtime in the process (torch's), so torch streams are valid in libmpo."""
+    import subprocess
+    import sys
+    code = ("from paper_2604_21908_amd import mpo\n"
+            "mpo.load_library()\n"
+            "import torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

@@ -214,3 +214,132 @@ def test_mirror_collapse_on_gpu(lib):
     ks = [t["k"] for t in res.trace if "k" in t]
     assert ks and max(ks) == 1
     assert abs(res.prob - 1.0) < 1e-10 and not res.bits.any()
+
+
+# ---------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_chi_cap_of_one(lib, prec):
+    """chi_max = 1 binds on every update: k = 1 and the leading value agrees."""
+    n = 5
+    rng = np.random.default_rng(4)
+    g = lib.MPO(n, 1, 1e-12, 0, PREC[prec])
+    o = mo.OracleMPO(n)
+    for b in (0, 2, 3, 1):
+        go, gi = cg.haar_su4(rng), cg.haar_su4(rng)
+        info = g.absorb(b, go, gi)
+        r = mo.bond_update(o, b, go, gi, 1, 1e-12, "rel_sv")
+        mo.commit(o, r)
+        assert info["k"] == r.k == 1
+        assert abs(g.singular_values(b)[0] - r.s[0]) <= TOL[prec] * np.linalg.norm(r.s)
+        assert abs(info["discarded"] - r.discarded) <= TOL[prec] * r.total
+    assert g.bond_dims() == [1] * (n - 1)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_odd_chain_end_bonds(lib, prec):
+    """Odd n; updates on both end bonds (chi_l = 1 or chi_r = 1) and a
+    one-sided gate."""
+    n = 7
+    m = random_state(n, 31, 5)
+    rng = np.random.default_rng(6)
+    g = gpu_mpo(lib, m, prec)
+    for b, one_sided in ((0, False), (n - 2, False), (3, True)):
+        go, gi = cg.haar_su4(rng), (None if one_sided else cg.haar_su4(rng))
+        info = g.absorb(b, go, gi)
+        r = mo.bond_update(m, b, go, gi, 256, 1e-12, "rel_sv")
+        mo.commit(m, r)
+        assert info["k"] == r.k
+        assert sv_err(g.singular_values(b), r.s[:r.k]) <= TOL[prec]
+    assert np.max(np.abs(gpu_dense(g, n) - m.dense_operator())) <= TOL[prec] * 10
+    g.close()
+
+
+@pytest.mark.parametrize("schedule", ["sequential", "parallel"])
+def test_gpu_unswap_removes_bare_swap_layer(lib, schedule):
+    """A layer of output SWAPs on even bonds and input SWAPs on odd bonds is
+    undone exactly by the greedy trials, back to bond dimension 1."""
+    n = 7
+    g = lib.MPO(n, 64, 1e-12, 0, 0)
+    o = mo.OracleMPO(n)
+    for b in range(0, n - 1, 2):
+        g.absorb(b, mo.SWAP4, None)
+        mo.commit(o, mo.bond_update(o, b, mo.SWAP4, None, 64, 1e-12, "rel_sv"))
+    for b in range(1, n - 1, 2):
+        g.absorb(b, None, mo.SWAP4)
+        mo.commit(o, mo.bond_update(o, b, None, mo.SWAP4, 64, 1e-12, "rel_sv"))
+    assert g.bond_dims() == o.bond_dims() == [4] * (n - 1)
+    log = g.unswap(schedule)
+    run = mo.unswap_parallel if schedule == "parallel" else mo.unswap_sequential
+    ref = run(o, mo.OracleConfig(chi_max=64, cutoff=1e-12, mode="rel_sv", unswap=schedule))
+    assert g.bond_dims() == o.bond_dims() == [1] * (n - 1)
+    assert sorted(log) == sorted(ref)
+    g.close()
+
+
+def test_peak_readout_of_generic_state(lib):
+    n = 7
+    m = random_state(n, 44, 5)
+    g = gpu_mpo(lib, m, "fp64")
+    bits, p, n2 = g.extract_peak()
+    rb, rp, rn2 = mo.extract_peak(m)
+    assert np.array_equal(bits, rb)
+    assert abs(p - rp) <= 1e-10 * rp and abs(n2 - rn2) <= 1e-12 * rn2
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_chi128_update(lib, prec):
+    """theta 512 x 512: 32 column blocks, 16 pairs per round-robin step."""
+    n = 10
+    m = random_state(n, 5, 9, chi_max=128)
+    b = 4
+    assert m.chi(b - 1) == 128 and m.chi(b + 1) == 128
+    rng = np.random.default_rng(12)
+    go, gi = cg.haar_su4(rng), cg.haar_su4(rng)
+    g = gpu_mpo(lib, m, prec, chi_max=128, cutoff=1e-8, mode=1)
+    info = g.absorb(b, go, gi)
+    r = mo.bond_update(m, b, go, gi, 128, 1e-8, "weight")
+    assert info["k"] == r.k
+    assert sv_err(g.singular_values(b), r.s[:r.k]) <= TOL[prec]
+    right = g.read_site(b + 1).reshape(info["k"], -1)            # V_k^dag: orthonormal rows
+    assert np.max(np.abs(right @ right.conj().T - np.eye(info["k"]))) <= 1e-4
+    assert abs(info["total"] - r.total) <= 1e-4 * r.total
+    g.close()
+
+
+_FULL = {}
+
+
+def _full_size_oracle():
+    """Singular values of the chi = 1024 update (theta 4096 x 4096), once."""
+    if not _FULL:
+        import bench
+        n, sites, lams, bond = bench.micro_state(1024)
+        rng = np.random.default_rng(77)
+        go, gi = bench.haar_su4(rng), bench.haar_su4(rng)
+        m = mo.OracleMPO(n)
+        m.B = [s.copy() for s in sites]
+        m.lam = [l.copy() for l in lams]
+        r = mo.bond_update(m, bond, go, gi, 1024, 1e-8, "weight", vectors=False)
+        _FULL.update(n=n, sites=sites, lams=lams, bond=bond, go=go, gi=gi, r=r)
+    return _FULL
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+def test_full_size_chi1024_update(lib, prec):
+    """The benchmarked update itself (chi_max = 1024 binds) against the
+    oracle's singular values, discarded weight and the orthonormality of
+    the new right tensor."""
+    f = _full_size_oracle()
+    r = f["r"]
+    g = lib.MPO(f["n"], 1024, 1e-8, 1, PREC[prec])
+    g.load_state(f["sites"], f["lams"])
+    info = g.absorb(f["bond"], f["go"], f["gi"])
+    s_gpu = g.singular_values(f["bond"])
+    right = g.read_site(f["bond"] + 1).reshape(info["k"], -1)
+    g.close()
+    assert info["k"] == r.k == 1024
+    assert sv_err(s_gpu, r.s[:r.k]) <= TOL[prec]
+    assert abs(info["discarded"] - r.discarded) <= 1e-4 * r.total
+    assert np.max(np.abs(right @ right.conj().T - np.eye(info["k"]))) <= 1e-4
