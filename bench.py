@@ -152,8 +152,10 @@ def run_precision(mpolib, torch, prec_name, args, n, sites, lams, bond, gates):
 
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAME = {"jacobi_rot": "k_jac_rot", "jacobi_gram": "k_jac_gram", "jacobi_evd": "k_jac_evd",
-               "qr": "k_qr_panel+k_qr_apply", "theta_gemm": "k_gemm", "writeback_gemm": "k_gemm"}
+KERNEL_NAME = {"jacobi_rot": "k_jac_rot", "jacobi_gram": "k_jac_gram",
+               "jacobi_evd": "k_jac_evd", "qr": "k_qr_panel+k_qr_w1+k_qr_w2+k_qr_upd", "theta_gemm": "k_gemm",
+               "writeback_gemm": "k_gemm"}
+KERNEL_NAME_MIXED = {"jacobi_rot": "k_jac_rot_mixed", "jacobi_gram": "k_jac_gram_bf16"}
 
 
 def roofline_of(run, prec_name, chi, steps):
@@ -173,7 +175,8 @@ def roofline_of(run, prec_name, chi, steps):
     esz = 16 if prec_name == "fp64" else 8
     hbm_bound = dom == "jacobi_rot" or (dom == "jacobi_gram" and prec_name == "mixed")
     byt = kernel_bytes(dom, chi, sweeps, rots, esz) if hbm_bound else None
-    out = {"kernel": KERNEL_NAME.get(dom, dom), "class": dom, "avg_launch_ms": round(ms / max(launches, 1), 5),
+    names = dict(KERNEL_NAME, **(KERNEL_NAME_MIXED if prec_name == "mixed" else {}))
+    out = {"kernel": names.get(dom, dom), "class": dom, "avg_launch_ms": round(ms / max(launches, 1), 5),
            "launches_per_update": launches / steps, "traffic": None}
     if byt:
         achieved = byt / (ms * 1e-3) / 1e9
@@ -194,6 +197,19 @@ def roofline_of(run, prec_name, chi, steps):
     return out
 
 
+def calibrate_copy(nbytes=1 << 30, reps=3):
+    """A plain copy of known size for scaling the hardware byte counters."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)      # one elementwise kernel: reads x, writes y
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
+                      "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,12 +219,18 @@ def main():
     ap.add_argument("--compare", default="fp32", help="second precision timed in the same run ('' for none)")
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the path is single-GPU, "
               f"see DESIGN.md for how it would shard", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import torch
     from paper_2604_21908_amd import mpo as mpolib

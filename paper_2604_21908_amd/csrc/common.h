@@ -17,8 +17,11 @@ constexpr int MAXB = 32;
 // panel of 2*JB columns).
 constexpr int JB = 16;
 // Rows per workgroup of the Jacobi Gram and rotation kernels.
-constexpr int GRC = 256;
+constexpr int GRC = 512;
 constexpr int RRC = 256;
+// Panel rotation launch: every row on FP MFMA, or (mixed form) theta's rows
+// on split-BF16 products and V's rows on FP32 MFMA in the same launch.
+constexpr int ROT_FP = 0, ROT_MIXED = 1;
 
 // ---------------------------------------------------------------- GEMM
 // C[M x N] = A[M x K] * op(B), complex, row-major.
@@ -70,9 +73,20 @@ struct JacProb {
   cx<double>* gpart;  // per pair, ngchunk partial 32x32 Gram matrices
   void* dmat;     // per pair, D = W - I (32x32, working precision)
   int* pflag;     // per pair, 1 if the panel is rotated in this step
+  // Skipping of unchanged converged pairs: bmod[b] is the step stamp of the
+  // last rotation of block b, pchk[bi * nblk + bj] the stamp at which the pair
+  // was last found converged.  A pair with pchk > bmod of both blocks would
+  // reproduce the same Gram matrix bit for bit and the same decision, so its
+  // Gram and EVD are skipped.  Valid within one tolerance; k_jac_init clears it.
+  int* bmod;
+  int* pchk;
   double tol;     // off-diagonal tolerance |g_ij| <= tol sqrt(g_ii g_jj)
   int m, lda, ncol, ncol_pad, nblk, ngchunk;
 };
+__device__ __forceinline__ bool pair_unchanged(const JacProb& P, int bi, int bj) {
+  const int c = P.pchk[bi * P.nblk + bj];
+  return c > 0 && c > P.bmod[bi] && c > P.bmod[bj];
+}
 struct JacBatch {
   JacProb p[MAXB];
   int count;
@@ -99,11 +113,18 @@ struct QrBatch {
 // C (n rows, leading dimension ldc, columns [c0, c1)) <- (I - V op(T) V^dag) C
 // for the panel starting at column p0 of M; op(T) = T^dag (Q^dag from the left,
 // used for the trailing matrix) or T (Q from the left, used to form V).
+// The product V^dag C is summed in two levels: k_qr_w1 writes one FP64
+// partial per QRC1-row chunk (wpart: chunks x QNB x ldp), k_qr_w2 adds them in
+// chunk order and multiplies by op(T) (w2: QNB x ldp), k_qr_upd subtracts V w2.
+constexpr int QRC1 = 512;
+constexpr int QRC2 = 256;
 struct QrApplyProb {
   const void* M;
   const void* Tf;
   void* C;
-  int n, r, ldc, c0, c1;
+  void* wpart;    // cx<double>, ceil(n / QRC1) * QNB * ldp
+  void* w2;       // cx<T>, QNB * ldp
+  int n, r, ldc, c0, c1, ldp;   // columns of C index wpart / w2 directly (c1 <= ldp)
 };
 struct QrApplyBatch {
   QrApplyProb p[MAXB];

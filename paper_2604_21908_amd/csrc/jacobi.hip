@@ -15,9 +15,10 @@
 //               and V's panels, computed as P^T <- P^T + D^T P^T so that
 //               each 16-lane group of a wave reads and writes 16 consecutive
 //               rows of one column
-//   k_jac_gram_bf16 / k_jac_rot_bf16  the same with split-BF16 products on
-//               theta's panel (mixed precision; the EVD stays FP64 and the
-//               accumulated rotations V stay FP32)
+//   k_jac_gram_bf16 / k_jac_rot_mixed  the mixed form: Gram matrices with
+//               split-BF16 products, and one rotation launch in which theta's
+//               row chunks use split-BF16 products while the accumulated
+//               rotations V stay on FP32 MFMA (the EVD stays FP64)
 #include "common.h"
 #include "mfma.h"
 
@@ -57,21 +58,29 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacBatch jb, int step) {
   const int r1 = min(P.m, r0 + GRC);
   int bi, bj;
   rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  if (pair_unchanged(P, bi, bj)) return;
   __shared__ cx<T> Pc[64][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int I = wave >> 1, J = wave & 1;
   const cx<T>* A = (const cx<T>*)P.A;
   typedef typename MF<T>::acc acc_t;
   double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
-  for (int s0 = r0; s0 < r1; s0 += 64) {
+  // the next 64-row slab is loaded into registers while this one is multiplied
+  cx<T> nxt[8];
+  auto fetch = [&](int s0) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int c = (tid >> 6) + 4 * u, r = tid & 63;
-      cx<T> v = {0, 0};
-      if (s0 + r < r1) v = A[(size_t)panel_col(bi, bj, c) * P.lda + s0 + r];
-      Pc[r][c] = v;
+      const int c = wave + 4 * u;
+      nxt[u] = cx<T>{0, 0};
+      if (s0 + lane < r1) nxt[u] = A[(size_t)panel_col(bi, bj, c) * P.lda + s0 + lane];
     }
+  };
+  fetch(r0);
+  for (int s0 = r0; s0 < r1; s0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Pc[lane][wave + 4 * u] = nxt[u];
     __syncthreads();
+    if (s0 + 64 < r1) fetch(s0 + 64);
     acc_t are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
 #pragma unroll 4
     for (int kk = 0; kk < 64; kk += 4) {
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacBatch jb, int step) {
 // x columns (p_kc, q_kc) by W_block J_kc: every entry is read and written by
 // exactly one thread, so the update runs in place.
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inner_sweeps) {
+__global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inner_sweeps, int stamp) {
   const int pi = blockIdx.y;
   if (pi >= jb.count) return;
   const JacProb P = jb.p[pi];
@@ -119,6 +128,12 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   const int tid = threadIdx.x;
   const int gi = tid >> 3, gj0 = (tid & 7) * 4;
   int* pflag = P.pflag + blockIdx.x;
+  int bi, bj;
+  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  if (pair_unchanged(P, bi, bj)) {
+    if (tid == 0) *pflag = 0;
+    return;
+  }
   // sum of the partial Gram matrices in chunk order (deterministic)
   const int nch = (P.m + GRC - 1) / GRC;
   const cx<double>* gp = P.gpart + (size_t)blockIdx.x * P.ngchunk * 1024;
@@ -126,9 +141,11 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   for (int u = 0; u < 4; ++u) {
     const int e = gi * 32 + gj0 + u;
     double sr = 0, si = 0;
+#pragma unroll 4
     for (int c = 0; c < nch; ++c) {
-      sr += gp[(size_t)c * 1024 + e].re;
-      si += gp[(size_t)c * 1024 + e].im;
+      const cx<double> v = gp[(size_t)c * 1024 + e];
+      sr += v.re;
+      si += v.im;
     }
     G[gi][gj0 + u] = cx<double>{sr, si};
     W[gi][gj0 + u] = cx<double>{(gi == gj0 + u) ? 1.0 : 0.0, 0.0};
@@ -146,11 +163,16 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   }
   __syncthreads();
   if (!flag) {
-    if (tid == 0) *pflag = 0;
+    if (tid == 0) {
+      *pflag = 0;
+      P.pchk[bi * P.nblk + bj] = stamp;
+    }
     return;
   }
   if (tid == 0) {
     *pflag = 1;
+    P.bmod[bi] = stamp;
+    P.bmod[bj] = stamp;
     atomicAdd(&P.st->rot, 1);
   }
   const int kr = tid >> 4, kc = tid & 15;
@@ -230,26 +252,10 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
 // of V.  out^T = P^T + D^T P^T for 16-row strips; lane (l & 15) owns row
 // strip0 + (l & 15).
 // part 0: all rows; 1: theta's rows [0, m) only; 2: V's rows only.
+// Rows [c0, c1) of the panel's row space, FP MFMA (T = float or double).
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step, int part) {
-  const int pi = blockIdx.z;
-  if (pi >= jb.count) return;
-  const JacProb P = jb.p[pi];
-  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
-  if (P.st->active == 0) return;
-  if (P.pflag[blockIdx.x] == 0) return;
-  const int nv = P.V ? P.ncol : 0;
-  const int rows = (part == 1) ? P.m : P.m + nv;
-  const int c0 = (part == 2 ? P.m : 0) + blockIdx.y * RRC;
-  if (c0 >= rows) return;
-  const int c1 = min(rows, c0 + RRC);
-  int bi, bj;
-  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
-  __shared__ cx<T> Ds[32][33];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const cx<T>* D = (const cx<T>*)P.dmat + (size_t)blockIdx.x * 1024;
-  for (int e = tid; e < 1024; e += 256) Ds[e >> 5][e & 31] = D[e];
-  __syncthreads();
+__device__ __forceinline__ void rot_rows(const JacProb& P, int bi, int bj, int c0, int c1, const cx<T> (*Ds)[33]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   cx<T>* A = (cx<T>*)P.A;
   cx<T>* V = (cx<T>*)P.V;
   typedef typename MF<T>::acc acc_t;
@@ -305,6 +311,28 @@ __global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step, int part
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step, int part) {
+  const int pi = blockIdx.z;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
+  if (P.st->active == 0) return;
+  if (P.pflag[blockIdx.x] == 0) return;
+  const int nv = P.V ? P.ncol : 0;
+  const int rows = (part == 1) ? P.m : P.m + nv;
+  const int c0 = (part == 2 ? P.m : 0) + blockIdx.y * RRC;
+  if (c0 >= rows) return;
+  const int c1 = min(rows, c0 + RRC);
+  int bi, bj;
+  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  __shared__ cx<T> Ds[32][33];
+  const cx<T>* D = (const cx<T>*)P.dmat + (size_t)blockIdx.x * 1024;
+  for (int e = threadIdx.x; e < 1024; e += 256) Ds[e >> 5][e & 31] = D[e];
+  __syncthreads();
+  rot_rows<T>(P, bi, bj, c0, c1, Ds);
+}
+
 // ---------------------------------------------------------------- split-BF16
 // The same Gram and rotation with every real product on three BF16 MFMAs
 // (mfma.h); K = 32 per instruction covers a whole panel width.
@@ -319,20 +347,28 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
   const int r1 = min(P.m, r0 + GRC);
   int bi, bj;
   rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  if (pair_unchanged(P, bi, bj)) return;
   __shared__ cx<float> Pc[64][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int I = wave >> 1, J = wave & 1, g8 = (lane >> 4) * 8;
   const cx<float>* A = (const cx<float>*)P.A;
   double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
-  for (int s0 = r0; s0 < r1; s0 += 64) {
+  // the next 64-row slab is loaded into registers while this one is multiplied
+  cx<float> nxt[8];
+  auto fetch = [&](int s0) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int c = (tid >> 6) + 4 * u, r = tid & 63;
-      cx<float> v = {0, 0};
-      if (s0 + r < r1) v = A[(size_t)panel_col(bi, bj, c) * P.lda + s0 + r];
-      Pc[r][c] = v;
+      const int c = wave + 4 * u;
+      nxt[u] = cx<float>{0, 0};
+      if (s0 + lane < r1) nxt[u] = A[(size_t)panel_col(bi, bj, c) * P.lda + s0 + lane];
     }
+  };
+  fetch(r0);
+  for (int s0 = r0; s0 < r1; s0 += 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Pc[lane][wave + 4 * u] = nxt[u];
     __syncthreads();
+    if (s0 + 64 < r1) fetch(s0 + 64);
     v4f are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < 64; kk += 32) {
@@ -368,26 +404,12 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
   }
 }
 
-// theta's rows only: the accumulated rotations V stay on FP32 MFMA
-// (k_jac_rot, part 2) so that V remains unitary to FP32 accuracy.
-__global__ __launch_bounds__(256) void k_jac_rot_bf16(JacBatch jb, int step) {
-  const int pi = blockIdx.z;
-  if (pi >= jb.count) return;
-  const JacProb P = jb.p[pi];
-  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
-  if (P.st->active == 0) return;
-  if (P.pflag[blockIdx.x] == 0) return;
-  const int rows = P.m;
-  const int c0 = blockIdx.y * RRC;
-  if (c0 >= rows) return;
-  const int c1 = min(rows, c0 + RRC);
-  int bi, bj;
-  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
-  __shared__ cx<float> Ds[32][33];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g8 = (lane >> 4) * 8;
-  const cx<float>* D = (const cx<float>*)P.dmat + (size_t)blockIdx.x * 1024;
-  for (int e = tid; e < 1024; e += 256) Ds[e >> 5][e & 31] = D[e];
-  __syncthreads();
+// theta's rows [c0, c1) (c1 <= m) on split-BF16 products; the accumulated
+// rotations V stay on FP32 MFMA (rot_rows) so that V remains unitary to FP32
+// accuracy.
+__device__ __forceinline__ void rot_rows_bf16(const JacProb& P, int bi, int bj, int c0, int c1,
+                                              const cx<float> (*Ds)[33]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g8 = (lane >> 4) * 8;
   // A operands D^T[c][k] = D[k][c] for the two 16-column halves, split once
   Split8 dr[2], di[2], dn[2];
 #pragma unroll
@@ -400,22 +422,10 @@ __global__ __launch_bounds__(256) void k_jac_rot_bf16(JacBatch jb, int step) {
       split_set(dn[t], e, -d.im);
     }
   cx<float>* A = (cx<float>*)P.A;
-  cx<float>* V = (cx<float>*)P.V;
+  const size_t ld = P.lda;
   for (int s0 = c0 + wave * 16; s0 < c1; s0 += 64) {
-    const int rho = s0 + (lane & 15);
-    const bool valid = rho < c1;
-    cx<float>* base;
-    size_t ld;
-    int row;
-    if (rho < P.m) {
-      base = A;
-      ld = P.lda;
-      row = rho;
-    } else {
-      base = V;
-      ld = P.ncol_pad;
-      row = rho - P.m;
-    }
+    const int row = s0 + (lane & 15);
+    const bool valid = row < c1;
     v4f cre[2], cim[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -423,7 +433,7 @@ __global__ __launch_bounds__(256) void k_jac_rot_bf16(JacBatch jb, int step) {
       for (int r = 0; r < 4; ++r) {
         const int c = t * 16 + MF<float>::row(lane, r);
         cx<float> v = {0, 0};
-        if (valid) v = base[(size_t)panel_col(bi, bj, c) * ld + row];
+        if (valid) v = A[(size_t)panel_col(bi, bj, c) * ld + row];
         cre[t][r] = v.re;
         cim[t][r] = v.im;
       }
@@ -431,7 +441,7 @@ __global__ __launch_bounds__(256) void k_jac_rot_bf16(JacBatch jb, int step) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       cx<float> x = {0, 0};
-      if (valid) x = base[(size_t)panel_col(bi, bj, g8 + e) * ld + row];
+      if (valid) x = A[(size_t)panel_col(bi, bj, g8 + e) * ld + row];
       split_set(xr, e, x.re);
       split_set(xi, e, x.im);
     }
@@ -448,10 +458,42 @@ __global__ __launch_bounds__(256) void k_jac_rot_bf16(JacBatch jb, int step) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int c = t * 16 + MF<float>::row(lane, r);
-          base[(size_t)panel_col(bi, bj, c) * ld + row] = cx<float>{cre[t][r], cim[t][r]};
+          A[(size_t)panel_col(bi, bj, c) * ld + row] = cx<float>{cre[t][r], cim[t][r]};
         }
     }
   }
+}
+
+// One launch for both row sets of the mixed form: row chunks y < ny_theta
+// rotate theta's rows on split-BF16, the others V's rows on FP32, so the
+// memory-bound and the MFMA-bound workgroups share the machine.
+__global__ __launch_bounds__(256) void k_jac_rot_mixed(JacBatch jb, int step, int ny_theta) {
+  const int pi = blockIdx.z;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
+  if (P.st->active == 0) return;
+  if (P.pflag[blockIdx.x] == 0) return;
+  const bool theta = (int)blockIdx.y < ny_theta;
+  int c0, c1;
+  if (theta) {
+    c0 = blockIdx.y * RRC;
+    if (c0 >= P.m) return;
+    c1 = min(P.m, c0 + RRC);
+  } else {
+    const int nv = P.V ? P.ncol : 0;
+    c0 = P.m + (blockIdx.y - ny_theta) * RRC;
+    if (c0 >= P.m + nv) return;
+    c1 = min(P.m + nv, c0 + RRC);
+  }
+  int bi, bj;
+  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
+  __shared__ cx<float> Ds[32][33];
+  const cx<float>* D = (const cx<float>*)P.dmat + (size_t)blockIdx.x * 1024;
+  for (int e = threadIdx.x; e < 1024; e += 256) Ds[e >> 5][e & 31] = D[e];
+  __syncthreads();
+  if (theta) rot_rows_bf16(P, bi, bj, c0, c1, Ds);
+  else rot_rows<float>(P, bi, bj, c0, c1, Ds);
 }
 
 // Newton-Schulz step toward the polar factor in FP64: S <- (3 I - S) / 2.
@@ -478,29 +520,29 @@ void launch_jac_gram(const JacBatch& b, int maxpairs, int maxgch, int step, int 
     hipLaunchKernelGGL(k_jac_gram<T>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
 }
 template <typename T>
-void launch_jac_evd(const JacBatch& b, int maxpairs, int step, int inner_sweeps, hipStream_t s) {
-  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, inner_sweeps);
+void launch_jac_evd(const JacBatch& b, int maxpairs, int step, int inner_sweeps, int stamp, hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, inner_sweeps, stamp);
 }
 template <typename T>
-void launch_jac_rot(const JacBatch& b, int maxpairs, int maxrch, int step, int bf16, hipStream_t s) {
-  if (bf16) {
-    hipLaunchKernelGGL(k_jac_rot_bf16, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step);
-    hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 2);
-  } else {
-    hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 0);
-  }
+void launch_jac_rot(const JacBatch& b, int maxpairs, int maxrch_a, int maxrch_v, int step, int mode, hipStream_t s) {
+  if (mode == ROT_MIXED)
+    hipLaunchKernelGGL(k_jac_rot_mixed, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step,
+                       maxrch_a);
+  else
+    hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step, 0);
 }
 template <>
 void launch_jac_gram<double>(const JacBatch& b, int maxpairs, int maxgch, int step, int, hipStream_t s) {
   hipLaunchKernelGGL(k_jac_gram<double>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
 }
 template <>
-void launch_jac_rot<double>(const JacBatch& b, int maxpairs, int maxrch, int step, int, hipStream_t s) {
-  hipLaunchKernelGGL(k_jac_rot<double>, dim3(maxpairs, maxrch, b.count), dim3(256), 0, s, b, step, 0);
+void launch_jac_rot<double>(const JacBatch& b, int maxpairs, int maxrch_a, int maxrch_v, int step, int,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_rot<double>, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step, 0);
 }
 template void launch_jac_gram<float>(const JacBatch&, int, int, int, int, hipStream_t);
-template void launch_jac_rot<float>(const JacBatch&, int, int, int, int, hipStream_t);
-template void launch_jac_evd<float>(const JacBatch&, int, int, int, hipStream_t);
-template void launch_jac_evd<double>(const JacBatch&, int, int, int, hipStream_t);
+template void launch_jac_rot<float>(const JacBatch&, int, int, int, int, int, hipStream_t);
+template void launch_jac_evd<float>(const JacBatch&, int, int, int, int, hipStream_t);
+template void launch_jac_evd<double>(const JacBatch&, int, int, int, int, hipStream_t);
 
 }  // namespace mpo

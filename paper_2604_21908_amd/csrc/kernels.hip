@@ -218,6 +218,13 @@ __global__ void k_jac_init(JacBatch jb) {
     P.st->sweeps = 0;
     P.st->rot_total = 0;
   }
+  // pair-skip bookkeeping starts empty
+  const size_t nb = (size_t)P.nblk;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb * nb + nb;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if (i < nb * nb) P.pchk[i] = 0;
+    else P.bmod[i - nb * nb] = 0;
+  }
   const size_t npad = (size_t)P.ncol_pad;
   const size_t nv = P.V ? npad * npad : 0;
   const size_t na = (size_t)(P.ncol_pad - P.ncol) * P.lda;

@@ -8,16 +8,30 @@
 // the accumulated Jacobi rotations -- no division by singular values.
 //
 //   k_qr_panel   one workgroup factors a QNB-column panel (complex Householder
-//                reflectors, LAPACK's sign convention) and builds the
-//                upper-triangular T of the compact WY form; FP64 reductions
-//   k_qr_apply   C <- (I - V op(T) V^dag) C on 16-column tiles: the trailing
-//                update (op = dag) and the formation of V (op = identity)
+//                reflectors, LAPACK's sign convention, left-looking) and builds
+//                the upper-triangular T of the compact WY form; FP64 reductions
+//   k_qr_w1/w2/upd  C <- (I - V op(T) V^dag) C: row-chunked partial products
+//                V^dag C, their FP64 sum times op(T), the rank-QNB update; the
+//                trailing update (op = dag) and the formation of V (op = identity)
 //   k_lower_from_r  L = R^dag into the column-major Jacobi operand
 //   k_build_y / k_vh_rows   [W_k; 0] and B_{i+1} <- V_k^dag, lambda_i <- s_<k
 #include "common.h"
 #include "mfma.h"
 
 namespace mpo {
+
+// Left-looking factorisation of the QNB-column panel at p0, one workgroup of
+// 1024 threads (16 waves) per problem, with the current column held in LDS in
+// FP64 (rows p0..n-1, n - p0 <= 4096).  Column j of the panel:
+//  (1) one wave per earlier reflector q < j computes w_q = v_q^dag x and, for
+//      q < j - 1, z_q = v_q^dag v_{j-1}, which completes column j - 1 of T:
+//      T[0:j-1, j-1] = -tau_{j-1} T[0:j-1, 0:j-1] z;  then u = T^dag w and
+//      x <- x - V u  (Q^dag = I - V T^dag V^dag), row-parallel;
+//  (2) the tail norm, and thread 0 forms the reflector (LAPACK's complex
+//      Householder: beta = -sign(Re alpha) |x|, tau = (beta - alpha) / beta,
+//      v = [1; x_tail / (alpha - beta)]).
+// The last column of T is completed after the loop.
+constexpr int QPN = 4096;   // largest panel height: n <= 4 chi_max
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -32,31 +46,120 @@ __global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
   if (p0 >= P.r) return;
   const int nb = min(QNB, P.r - p0);
   const int n = P.n;
+  const int N = n - p0;                    // rows of the panel
   cx<T>* M = (cx<T>*)P.M;
   cx<T>* tau = (cx<T>*)P.tau;
   cx<T>* Tf = (cx<T>*)P.Tf + (size_t)(p0 / QNB) * QNB * QNB;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  __shared__ double red[16][2 * QNB];
-  __shared__ double res[2 * QNB];
+  __shared__ cx<double> xs[QPN];           // the current column
+  __shared__ double red[16];
+  __shared__ cx<double> Wd[QNB], Zd[QNB], U[QNB], Tl[QNB][QNB + 1];
   __shared__ double bc[8];
-  __shared__ cx<double> Tl[QNB][QNB];
+
+  // v_q at panel row r (absolute row p0 + r): 1 on its diagonal, the stored
+  // tail below it, 0 above
+  auto vq = [&](int q, int r) -> cx<double> {
+    if (r == q) return cx<double>{1.0, 0.0};
+    if (r < q) return cx<double>{0.0, 0.0};
+    const cx<T> t = M[(size_t)(p0 + q) * n + p0 + r];
+    return cx<double>{(double)t.re, (double)t.im};
+  };
+  // T[0:c, c] = -tau_c T[0:c, 0:c] Zd[0:c]  (threads < c; Tl[c][c] = tau_c is set
+  // when reflector c is formed)
+  auto t_column = [&](int c) {
+    if (tid < c) {
+      const cx<double> tc = Tl[c][c];
+      double sr = 0, si = 0;
+      for (int b = tid; b < c; ++b) {
+        const cx<double> t = Tl[tid][b], z = Zd[b];
+        sr += t.re * z.re - t.im * z.im;
+        si += t.re * z.im + t.im * z.re;
+      }
+      Tl[tid][c] = cx<double>{-(tc.re * sr - tc.im * si), -(tc.re * si + tc.im * sr)};
+    }
+  };
 
   for (int jj = 0; jj < nb; ++jj) {
-    const int j = p0 + jj;
-    cx<T>* colj = M + (size_t)j * n;
-    // |x[j+1:n]|^2
-    double s = 0;
-    for (int i = j + 1 + tid; i < n; i += 1024) {
-      const double a = colj[i].re, b = colj[i].im;
-      s += a * a + b * b;
+    cx<T>* colj = M + (size_t)(p0 + jj) * n + p0;
+    for (int r = tid; r < N; r += 1024) xs[r] = cx<double>{(double)colj[r].re, (double)colj[r].im};
+    __syncthreads();
+    if (jj > 0) {
+      if (wv < jj) {
+        // w_q over rows r >= q (v_q[q] = 1 taken by lane 0), z_q over rows
+        // r >= j - 1 (v_{j-1}[j-1] = 1); branch-free unrolled loops so the
+        // loads of a lane are in flight together
+        const int q = wv;
+        const cx<T>* vc = M + (size_t)(p0 + q) * n + p0;
+        double sr = 0, si = 0, zr = 0, zi = 0;
+        if (lane == 0) {
+          sr = xs[q].re;
+          si = xs[q].im;
+        }
+#pragma unroll 8
+        for (int r = q + 1 + lane; r < N; r += 64) {
+          const cx<T> v = vc[r];
+          const cx<double> x = xs[r];
+          sr += (double)v.re * x.re + (double)v.im * x.im;
+          si += (double)v.re * x.im - (double)v.im * x.re;
+        }
+        if (q < jj - 1) {
+          const cx<T>* yc = M + (size_t)(p0 + jj - 1) * n + p0;
+          if (lane == 0) {
+            zr = (double)vc[jj - 1].re;
+            zi = -(double)vc[jj - 1].im;
+          }
+#pragma unroll 8
+          for (int r = jj + lane; r < N; r += 64) {
+            const cx<T> v = vc[r], y = yc[r];
+            zr += (double)v.re * (double)y.re + (double)v.im * (double)y.im;
+            zi += (double)v.re * (double)y.im - (double)v.im * (double)y.re;
+          }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        zr = wave_sum(zr);
+        zi = wave_sum(zi);
+        if (lane == 0) {
+          Wd[wv] = cx<double>{sr, si};
+          Zd[wv] = cx<double>{zr, zi};
+        }
+      }
+      __syncthreads();
+      t_column(jj - 1);
+      __syncthreads();
+      if (tid < jj) {   // u_a = sum_{b <= a} conj(T[b][a]) w_b
+        double ur = 0, ui = 0;
+        for (int b = 0; b <= tid; ++b) {
+          const cx<double> t = Tl[b][tid], w = Wd[b];
+          ur += t.re * w.re + t.im * w.im;
+          ui += t.re * w.im - t.im * w.re;
+        }
+        U[tid] = cx<double>{ur, ui};
+      }
+      __syncthreads();
+      for (int r = tid; r < N; r += 1024) {
+        cx<double> x = xs[r];
+#pragma unroll
+        for (int q = 0; q < QNB - 1; ++q) {
+          if (q < jj && q <= r) {
+            const cx<double> v = vq(q, r), u = U[q];
+            x.re -= v.re * u.re - v.im * u.im;
+            x.im -= v.re * u.im + v.im * u.re;
+          }
+        }
+        xs[r] = x;
+      }
+      __syncthreads();
     }
+    double s = 0;
+    for (int r = jj + 1 + tid; r < N; r += 1024) s += xs[r].re * xs[r].re + xs[r].im * xs[r].im;
     s = wave_sum(s);
-    if (lane == 0) red[wv][0] = s;
+    if (lane == 0) red[wv] = s;
     __syncthreads();
     if (tid == 0) {
       double xn2 = 0;
-      for (int w = 0; w < 16; ++w) xn2 += red[w][0];
-      const double ar = colj[j].re, ai = colj[j].im;
+      for (int w = 0; w < 16; ++w) xn2 += red[w];
+      const double ar = xs[jj].re, ai = xs[jj].im;
       double tr = 0, ti = 0, scr = 0, sci = 0, beta = ar;
       if (xn2 > 0 || ai != 0) {
         const double nrm = sqrt(ar * ar + ai * ai + xn2);
@@ -66,96 +169,51 @@ __global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
         const double dr = ar - beta, di = ai, d2 = dr * dr + di * di;
         scr = dr / d2;
         sci = -di / d2;
-      } else {
-        beta = ar;
       }
       bc[0] = beta;
       bc[1] = tr;
       bc[2] = ti;
       bc[3] = scr;
       bc[4] = sci;
-    }
-    __syncthreads();
-    const double beta = bc[0], tr = bc[1], ti = bc[2], scr = bc[3], sci = bc[4];
-    const bool trivial = (tr == 0.0 && ti == 0.0);
-    if (!trivial)
-      for (int i = j + 1 + tid; i < n; i += 1024) {
-        const double a = colj[i].re, b = colj[i].im;
-        colj[i] = cx<T>{(T)(a * scr - b * sci), (T)(a * sci + b * scr)};
-      }
-    __syncthreads();
-    if (tid == 0) {
-      colj[j] = cx<T>{(T)beta, (T)0};
-      tau[j] = cx<T>{(T)tr, (T)ti};
-    }
-    // dots over rows >= j: slot q < jj -> z_q = v_q^dag v_j (for T);
-    //                      slot q >= jj -> w = v_j^dag M[:, p0+q+1] (update)
-    const int nd = nb - 1;
-    double acc[2 * (QNB - 1)];
-#pragma unroll
-    for (int q = 0; q < 2 * (QNB - 1); ++q) acc[q] = 0;
-    for (int i = j + tid; i < n; i += 1024) {
-      const cx<T> vt = colj[i];
-      const double vr = (i == j) ? 1.0 : (double)vt.re, vi = (i == j) ? 0.0 : (double)vt.im;
-#pragma unroll
-      for (int q = 0; q < QNB - 1; ++q) {
-        if (q < nd) {
-          if (q < jj) {
-            const cx<T> y = M[(size_t)(p0 + q) * n + i];
-            acc[2 * q] += (double)y.re * vr + (double)y.im * vi;
-            acc[2 * q + 1] += (double)y.re * vi - (double)y.im * vr;
-          } else {
-            const cx<T> y = M[(size_t)(p0 + q + 1) * n + i];
-            acc[2 * q] += vr * (double)y.re + vi * (double)y.im;
-            acc[2 * q + 1] += vr * (double)y.im - vi * (double)y.re;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 2 * (QNB - 1); ++q) {
-      const double v = wave_sum(acc[q]);
-      if (lane == 0) red[wv][q] = v;
-    }
-    __syncthreads();
-    if (tid < 2 * (QNB - 1)) {
-      double v = 0;
-      for (int w = 0; w < 16; ++w) v += red[w][tid];
-      res[tid] = v;
-    }
-    __syncthreads();
-    // later columns: M[i][c] -= conj(tau) v_i w_c, rows i >= j
-    if (!trivial) {
-      const double ctr = tr, cti = -ti;
-      for (int q = jj; q < nd; ++q) {
-        const int c = p0 + q + 1;
-        const double wr = res[2 * q], wi = res[2 * q + 1];
-        const double fr = ctr * wr - cti * wi, fi = ctr * wi + cti * wr;
-        cx<T>* colc = M + (size_t)c * n;
-        for (int i = j + tid; i < n; i += 1024) {
-          const cx<T> vt = colj[i];
-          const double vr = (i == j) ? 1.0 : (double)vt.re, vi = (i == j) ? 0.0 : (double)vt.im;
-          const double ur = vr * fr - vi * fi, ui = vr * fi + vi * fr;
-          const cx<T> x = colc[i];
-          colc[i] = cx<T>{(T)((double)x.re - ur), (T)((double)x.im - ui)};
-        }
-      }
-    }
-    // T[0:jj, jj] = -tau_j T[0:jj, 0:jj] z,  T[jj][jj] = tau_j
-    if (tid == 0) {
-      for (int a = 0; a < jj; ++a) {
-        double sr = 0, si = 0;
-        for (int b = a; b < jj; ++b) {
-          const cx<double> t = Tl[a][b];
-          const double zr = res[2 * b], zi = res[2 * b + 1];
-          sr += t.re * zr - t.im * zi;
-          si += t.re * zi + t.im * zr;
-        }
-        Tl[a][jj] = cx<double>{-(tr * sr - ti * si), -(tr * si + ti * sr)};
-      }
       Tl[jj][jj] = cx<double>{tr, ti};
-      for (int a = jj + 1; a < QNB; ++a) Tl[a][jj] = cx<double>{0, 0};
+      tau[p0 + jj] = cx<T>{(T)tr, (T)ti};
     }
+    __syncthreads();
+    {
+      const double beta = bc[0], scr = bc[3], sci = bc[4];
+      const bool trivial = (bc[1] == 0.0 && bc[2] == 0.0);
+      for (int r = tid; r < N; r += 1024) {
+        cx<double> y = xs[r];
+        if (r == jj) y = cx<double>{beta, 0.0};
+        else if (r > jj && !trivial) y = cx<double>{xs[r].re * scr - xs[r].im * sci, xs[r].re * sci + xs[r].im * scr};
+        colj[r] = cx<T>{(T)y.re, (T)y.im};
+      }
+    }
+    __syncthreads();
+  }
+  // last column of T: z_q = v_q^dag v_{nb-1}
+  if (nb > 1) {
+    const int c = nb - 1;
+    if (wv < c) {
+      const cx<T>* vc = M + (size_t)(p0 + wv) * n + p0;
+      const cx<T>* yc = M + (size_t)(p0 + c) * n + p0;
+      double zr = 0, zi = 0;
+      if (lane == 0) {
+        zr = (double)vc[c].re;
+        zi = -(double)vc[c].im;
+      }
+#pragma unroll 8
+      for (int r = c + 1 + lane; r < N; r += 64) {
+        const cx<T> v = vc[r], y = yc[r];
+        zr += (double)v.re * (double)y.re + (double)v.im * (double)y.im;
+        zi += (double)v.re * (double)y.im - (double)v.im * (double)y.re;
+      }
+      zr = wave_sum(zr);
+      zi = wave_sum(zi);
+      if (lane == 0) Zd[wv] = cx<double>{zr, zi};
+    }
+    __syncthreads();
+    t_column(c);
     __syncthreads();
   }
   if (tid < QNB * QNB) {
@@ -165,64 +223,57 @@ __global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
   }
 }
 
-// 16-column tile of C per workgroup (4 waves).  Phase 1: W1 = V^dag C over
-// rows [p0, n) on MFMA from LDS-staged 64-row slabs, one K range per wave,
-// then a cross-wave sum.  Phase 2: W2 = op(T) W1 (16 x 16, FP64), then
-// C^T <- C^T - W2^T V^T on MFMA with each 16-lane group on 16 consecutive
-// rows of one column of C.
+// V (rows [p0, n), nb columns) at row i, column a of the panel at p0.
 template <typename T>
-__global__ __launch_bounds__(256) void k_qr_apply(QrApplyBatch ab, int p0) {
-  const int pi = blockIdx.y;
+__device__ __forceinline__ cx<T> v_entry(const cx<T>* M, int n, int p0, int nb, int i, int a) {
+  if (a >= nb || i >= n) return cx<T>{0, 0};
+  if (i == p0 + a) return cx<T>{1, 0};
+  if (i > p0 + a) return M[(size_t)(p0 + a) * n + i];
+  return cx<T>{0, 0};
+}
+
+// Partial products V^dag C over the QRC1 rows of chunk blockIdx.y, for the
+// QAT columns of tile blockIdx.x: 128-row slabs staged in LDS (coalesced),
+// each wave multiplies 32 rows per slab on MFMA; the four wave sums are added
+// in FP64 and stored to wpart[chunk].
+template <typename T>
+__global__ __launch_bounds__(256) void k_qr_w1(QrApplyBatch ab, int p0) {
+  const int pi = blockIdx.z;
   if (pi >= ab.count) return;
   const QrApplyProb P = ab.p[pi];
   if (p0 >= P.r) return;
   const int cbeg = P.c0 + blockIdx.x * QAT;
   if (cbeg >= P.c1) return;
+  const int n = P.n;
+  const int rbeg = p0 + blockIdx.y * QRC1;
+  if (rbeg >= n) return;
+  const int rend = min(n, rbeg + QRC1);
   const int nb = min(QNB, P.r - p0);
   const int ncols = min(QAT, P.c1 - cbeg);
-  const int n = P.n;
   const cx<T>* M = (const cx<T>*)P.M;
-  cx<T>* C = (cx<T>*)P.C;
-  const cx<T>* Tf = (const cx<T>*)P.Tf + (size_t)(p0 / QNB) * QNB * QNB;
+  const cx<T>* C = (const cx<T>*)P.C;
   typedef typename MF<T>::acc acc_t;
-  __shared__ cx<T> Vs[64][QNB + 1];
-  __shared__ cx<T> Cs[64][QAT + 1];
+  __shared__ cx<T> Vs[128][QNB + 1];
+  __shared__ cx<T> Cs[128][QAT + 1];
   __shared__ double Wp[4][QNB][QAT][2];
-  __shared__ cx<double> W1[QNB][QAT + 1];
-  __shared__ cx<T> W2[QNB][QAT + 1];
-  __shared__ cx<double> Tl[QNB][QNB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  {
-    const int a = tid / QNB, b = tid % QNB;
-    if (ab.conj_t) {
-      const cx<T> u = Tf[b * QNB + a];
-      Tl[a][b] = cx<double>{(double)u.re, -(double)u.im};
-    } else {
-      const cx<T> t = Tf[a * QNB + b];
-      Tl[a][b] = cx<double>{(double)t.re, (double)t.im};
-    }
-  }
-  // ---- phase 1: W1[a][c] = sum_i conj(V[i][a]) C[i][c]
   acc_t wre = {0, 0, 0, 0}, wim = {0, 0, 0, 0};
-  for (int r0 = p0; r0 < n; r0 += 64) {
-    for (int e = tid; e < 64 * QNB; e += 256) {
-      const int rr = e % 64, a = e / 64, i = r0 + rr;
-      cx<T> v = {0, 0};
-      if (i < n && a < nb) {
-        if (i == p0 + a) v = cx<T>{1, 0};
-        else if (i > p0 + a) v = M[(size_t)(p0 + a) * n + i];
-      }
-      Vs[rr][a] = v;
+  for (int r0 = rbeg; r0 < rend; r0 += 128) {
+#pragma unroll
+    for (int e = tid; e < 128 * QNB; e += 256) {
+      const int rr = e % 128, a = e / 128, i = r0 + rr;
+      Vs[rr][a] = (i < rend) ? v_entry(M, n, p0, nb, i, a) : cx<T>{0, 0};
     }
-    for (int e = tid; e < 64 * QAT; e += 256) {
-      const int rr = e % 64, c = e / 64, i = r0 + rr;
+#pragma unroll
+    for (int e = tid; e < 128 * QAT; e += 256) {
+      const int rr = e % 128, c = e / 128, i = r0 + rr;
       cx<T> v = {0, 0};
-      if (i < n && c < ncols) v = C[(size_t)(cbeg + c) * P.ldc + i];
+      if (i < rend && c < ncols) v = C[(size_t)(cbeg + c) * P.ldc + i];
       Cs[rr][c] = v;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = wave * 16; kk < wave * 16 + 16; kk += 4) {
+    for (int kk = wave * 32; kk < wave * 32 + 32; kk += 4) {
       const cx<T> x = Vs[kk + (lane >> 4)][lane & 15];   // A[a][k] = conj(V[k][a])
       const cx<T> y = Cs[kk + (lane >> 4)][lane & 15];   // B[k][c] = C[k][c]
       wre = MF<T>::mma(x.re, y.re, wre);
@@ -239,27 +290,91 @@ __global__ __launch_bounds__(256) void k_qr_apply(QrApplyBatch ab, int p0) {
     Wp[wave][a][c][1] = (double)wim[r];
   }
   __syncthreads();
-  {
-    const int a = tid / QAT, c = tid % QAT;
-    W1[a][c] = cx<double>{Wp[0][a][c][0] + Wp[1][a][c][0] + Wp[2][a][c][0] + Wp[3][a][c][0],
-                          Wp[0][a][c][1] + Wp[1][a][c][1] + Wp[2][a][c][1] + Wp[3][a][c][1]};
+  const int a = tid / QAT, c = tid % QAT;
+  if (c < ncols) {
+    cx<double>* out = (cx<double>*)P.wpart + ((size_t)blockIdx.y * QNB + a) * P.ldp + cbeg + c;
+    *out = cx<double>{Wp[0][a][c][0] + Wp[1][a][c][0] + Wp[2][a][c][0] + Wp[3][a][c][0],
+                      Wp[0][a][c][1] + Wp[1][a][c][1] + Wp[2][a][c][1] + Wp[3][a][c][1]};
   }
+}
+
+// w2 = op(T) * (sum of the chunk partials, in chunk order), one 16 x QAT tile
+// per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qr_w2(QrApplyBatch ab, int p0) {
+  const int pi = blockIdx.y;
+  if (pi >= ab.count) return;
+  const QrApplyProb P = ab.p[pi];
+  if (p0 >= P.r) return;
+  const int cbeg = P.c0 + blockIdx.x * QAT;
+  if (cbeg >= P.c1) return;
+  const int ncols = min(QAT, P.c1 - cbeg);
+  const int nch = (P.n - p0 + QRC1 - 1) / QRC1;
+  const cx<T>* Tf = (const cx<T>*)P.Tf + (size_t)(p0 / QNB) * QNB * QNB;
+  __shared__ cx<double> Tl[QNB][QNB];
+  __shared__ cx<double> W1[QNB][QAT + 1];
+  const int tid = threadIdx.x;
+  const int a = tid / QAT, c = tid % QAT;
+  if (ab.conj_t) {
+    const cx<T> u = Tf[c * QNB + a];
+    Tl[a][c] = cx<double>{(double)u.re, -(double)u.im};
+  } else {
+    const cx<T> t = Tf[a * QNB + c];
+    Tl[a][c] = cx<double>{(double)t.re, (double)t.im};
+  }
+  double sr = 0, si = 0;
+  if (c < ncols) {
+    const cx<double>* wp = (const cx<double>*)P.wpart + (size_t)a * P.ldp + cbeg + c;
+    for (int ch = 0; ch < nch; ++ch) {
+      const cx<double> v = wp[(size_t)ch * QNB * P.ldp];
+      sr += v.re;
+      si += v.im;
+    }
+  }
+  W1[a][c] = cx<double>{sr, si};
   __syncthreads();
-  {
-    const int a = tid / QAT, c = tid % QAT;
+  if (c < ncols) {
     double yr = 0, yi = 0;
     for (int b = 0; b < QNB; ++b) {
       const cx<double> t = Tl[a][b], u = W1[b][c];
       yr += t.re * u.re - t.im * u.im;
       yi += t.re * u.im + t.im * u.re;
     }
-    W2[a][c] = cx<T>{(T)yr, (T)yi};
+    ((cx<T>*)P.w2)[(size_t)a * P.ldp + cbeg + c] = cx<T>{(T)yr, (T)yi};
+  }
+}
+
+// C <- C - V w2 on QRC2 rows (chunk blockIdx.y) x QAT columns (tile
+// blockIdx.x), on MFMA in the transposed orientation C^T -= w2^T V^T: each
+// 16-lane group covers 16 consecutive rows of one column of C; each wave
+// takes 64 rows as four 16-row strips.
+template <typename T>
+__global__ __launch_bounds__(256) void k_qr_upd(QrApplyBatch ab, int p0) {
+  const int pi = blockIdx.z;
+  if (pi >= ab.count) return;
+  const QrApplyProb P = ab.p[pi];
+  if (p0 >= P.r) return;
+  const int cbeg = P.c0 + blockIdx.x * QAT;
+  if (cbeg >= P.c1) return;
+  const int n = P.n;
+  const int rbeg = p0 + blockIdx.y * QRC2;
+  if (rbeg >= n) return;
+  const int nb = min(QNB, P.r - p0);
+  const int ncols = min(QAT, P.c1 - cbeg);
+  const cx<T>* M = (const cx<T>*)P.M;
+  cx<T>* C = (cx<T>*)P.C;
+  typedef typename MF<T>::acc acc_t;
+  __shared__ cx<T> W2[QNB][QAT + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    const int a = tid / QAT, c = tid % QAT;
+    W2[a][c] = (c < ncols) ? ((const cx<T>*)P.w2)[(size_t)a * P.ldp + cbeg + c] : cx<T>{0, 0};
   }
   __syncthreads();
-  // ---- phase 2: C^T[c][i] -= sum_a W2[a][c] V[i][a], 16-row strips per wave
-  for (int s0 = p0 + wave * 16; s0 < n; s0 += 64) {
-    const int i = s0 + (lane & 15);
-    const bool valid = i < n;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int i = rbeg + wave * 64 + st * 16 + (lane & 15);
+    const bool valid = i < n && i < rbeg + QRC2;
     acc_t cre, cim;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -272,12 +387,8 @@ __global__ __launch_bounds__(256) void k_qr_apply(QrApplyBatch ab, int p0) {
 #pragma unroll
     for (int k0 = 0; k0 < QNB; k0 += 4) {
       const int a = k0 + (lane >> 4);
-      cx<T> v = {0, 0};
-      if (valid && a < nb) {
-        if (i == p0 + a) v = cx<T>{1, 0};
-        else if (i > p0 + a) v = M[(size_t)(p0 + a) * n + i];
-      }
-      const cx<T> w = W2[a][lane & 15];   // A[c][a] = W2[a][c], negated for the subtraction
+      const cx<T> v = valid ? v_entry(M, n, p0, nb, i, a) : cx<T>{0, 0};
+      const cx<T> w = W2[a][lane & 15];   // A[c][a] = w2[a][c], negated for the subtraction
       cre = MF<T>::mma(-w.re, v.re, cre);
       cre = MF<T>::mma(w.im, v.im, cre);
       cim = MF<T>::mma(-w.re, v.im, cim);
@@ -358,8 +469,13 @@ void launch_qr_panel(const QrBatch& b, int p0, hipStream_t s) {
 template <typename T>
 void launch_qr_apply(const QrApplyBatch& b, int p0, int maxcols, hipStream_t s) {
   const int gx = (maxcols + QAT - 1) / QAT;
-  if (gx < 1) return;
-  hipLaunchKernelGGL(k_qr_apply<T>, dim3(gx, b.count), dim3(256), 0, s, b, p0);
+  int maxrows = 0;
+  for (int p = 0; p < b.count; ++p)
+    if (p0 < b.p[p].r && b.p[p].c0 < b.p[p].c1 && b.p[p].n - p0 > maxrows) maxrows = b.p[p].n - p0;
+  if (gx < 1 || maxrows < 1) return;
+  hipLaunchKernelGGL(k_qr_w1<T>, dim3(gx, (maxrows + QRC1 - 1) / QRC1, b.count), dim3(256), 0, s, b, p0);
+  hipLaunchKernelGGL(k_qr_w2<T>, dim3(gx, b.count), dim3(256), 0, s, b, p0);
+  hipLaunchKernelGGL(k_qr_upd<T>, dim3(gx, (maxrows + QRC2 - 1) / QRC2, b.count), dim3(256), 0, s, b, p0);
 }
 template <typename T>
 void launch_lower_from_r(const LowerBatch& b, int maxm, int maxrpad, hipStream_t s) {

@@ -19,8 +19,8 @@ template <typename T> void launch_gemm(const GemmBatch&, int, int, hipStream_t);
 template <typename T> void launch_gate(const GateBatch&, int, hipStream_t);
 template <typename T> void launch_jac_init(const JacBatch&, hipStream_t);
 template <typename T> void launch_jac_gram(const JacBatch&, int, int, int, int, hipStream_t);
-template <typename T> void launch_jac_evd(const JacBatch&, int, int, int, hipStream_t);
-template <typename T> void launch_jac_rot(const JacBatch&, int, int, int, int, hipStream_t);
+template <typename T> void launch_jac_evd(const JacBatch&, int, int, int, int, hipStream_t);
+template <typename T> void launch_jac_rot(const JacBatch&, int, int, int, int, int, hipStream_t);
 void launch_ns_coef(cx<double>*, int, hipStream_t);
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
@@ -65,10 +65,15 @@ struct Slot {
   int* perm = nullptr;
   void* tau = nullptr;
   void* Tf = nullptr;
+  void* qwp = nullptr;   // QR apply: FP64 chunk partials
+  void* qw2 = nullptr;   // QR apply: op(T) V^dag C
+  size_t cap_qwp = 0, cap_qw2 = 0;
   void* Y = nullptr;
   void* gpart = nullptr;
   void* dmat = nullptr;
   int* pflag = nullptr;
+  int* bmod = nullptr;   // pair-skip bookkeeping (JacProb)
+  int* pchk = nullptr;
   size_t cap_mn = 0, cap_A = 0, cap_V = 0, cap_n = 0, cap_r = 0, cap_Y = 0;
   size_t cap_pairs = 0, cap_gch = 0;
 };
@@ -241,7 +246,7 @@ void ensure_slot(mpo_ctx* h, Slot& s, size_t mn, size_t nA, size_t nV, size_t nn
   }
 }
 
-void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY) {
+void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY, size_t nwp, size_t nw2) {
   const size_t e = h->esz;
   if (s.cap_r < r) {
     dfree(s.tau);
@@ -251,6 +256,20 @@ void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY) {
     s.tau = dalloc(r * e);
     s.Tf = dalloc(((r + QNB - 1) / QNB) * QNB * QNB * e);
     s.cap_r = r;
+  }
+  if (s.cap_qwp < nwp) {
+    dfree(s.qwp);
+    s.qwp = nullptr;
+    s.cap_qwp = 0;
+    s.qwp = dalloc(nwp * sizeof(cx<double>));
+    s.cap_qwp = nwp;
+  }
+  if (s.cap_qw2 < nw2) {
+    dfree(s.qw2);
+    s.qw2 = nullptr;
+    s.cap_qw2 = 0;
+    s.qw2 = dalloc(nw2 * e);
+    s.cap_qw2 = nw2;
   }
   if (nY && s.cap_Y < nY) {
     dfree(s.Y);
@@ -267,12 +286,16 @@ void ensure_jac(mpo_ctx* h, Slot& s, size_t pairs, size_t gch) {
     dfree(s.gpart);
     dfree(s.dmat);
     dfree(s.pflag);
+    dfree(s.bmod);
+    dfree(s.pchk);
     s.gpart = s.dmat = nullptr;
-    s.pflag = nullptr;
+    s.pflag = s.bmod = s.pchk = nullptr;
     s.cap_pairs = s.cap_gch = 0;
     s.gpart = dalloc(np * ng * 1024 * sizeof(cx<double>));
     s.dmat = dalloc(np * 1024 * h->esz);
     s.pflag = (int*)dalloc(np * sizeof(int));
+    s.bmod = (int*)dalloc(2 * np * sizeof(int));
+    s.pchk = (int*)dalloc(4 * np * np * sizeof(int));
     s.cap_pairs = np;
     s.cap_gch = ng;
   }
@@ -367,7 +390,8 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     int i, chil, chim, chir, m, n, r, rpad, nblk;
   };
   Shape sh[MAXB];
-  int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0, maxgch = 1, maxrch = 1;
+  int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0, maxgch = 1;
+  int maxrch_a = 1, maxrch_v = 1;   // row chunks of theta's rows, of V's rows
   auto O = [&](int p) -> mpo_ctx* { return reqs[p].owner ? reqs[p].owner : h; };
   for (int p = 0; p < count; ++p) {
     Shape& s = sh[p];
@@ -391,10 +415,12 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     Slot& sl = h->slots[p];
     ensure_slot(h, sl, (size_t)s.m * s.n, (size_t)s.m * s.rpad, commit ? (size_t)s.rpad * s.rpad : 0,
                 (size_t)s.rpad);
-    ensure_qr(h, sl, (size_t)s.r, commit ? (size_t)s.n * s.r : 0);
+    ensure_qr(h, sl, (size_t)s.r, commit ? (size_t)s.n * s.r : 0,
+              (size_t)((s.n + QRC1 - 1) / QRC1) * QNB * s.m, (size_t)QNB * s.m);
     ensure_jac(h, sl, (size_t)(s.nblk / 2), (size_t)((s.m + GRC - 1) / GRC));
     maxgch = std::max(maxgch, (s.m + GRC - 1) / GRC);
-    maxrch = std::max(maxrch, (s.m + (commit ? s.r : 0) + RRC - 1) / RRC);
+    maxrch_a = std::max(maxrch_a, (s.m + RRC - 1) / RRC);
+    if (commit) maxrch_v = std::max(maxrch_v, (s.r + RRC - 1) / RRC);
   }
   // gates -> pinned staging -> device (the staging buffer is free: every
   // call ends with a stream synchronisation)
@@ -443,7 +469,8 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     for (int p = 0; p < count; ++p) {
       const Shape& s = sh[p];
       const int c0 = std::min(p0 + QNB, s.r), c1 = s.m;
-      tr.p[p] = QrApplyProb{h->slots[p].theta0, h->slots[p].Tf, h->slots[p].theta0, s.n, s.r, s.n, c0, c1};
+      tr.p[p] = QrApplyProb{h->slots[p].theta0, h->slots[p].Tf, h->slots[p].theta0, h->slots[p].qwp,
+                            h->slots[p].qw2, s.n, s.r, s.n, c0, c1, s.m};
       if (p0 < s.r) maxtrail = std::max(maxtrail, c1 - c0);
     }
     timed(h, MPO_PROF_QR, [&] {
@@ -465,18 +492,23 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
     Slot& sl = h->slots[p];
-    jb.p[p] = JacProb{sl.A, commit ? sl.V : nullptr, h->states + p, sl.norms, (cx<double>*)sl.gpart, sl.dmat,
-                      sl.pflag, tol_for(O(p), s.m), s.m, s.m, s.r, s.rpad, s.nblk, (int)sl.cap_gch};
+    jb.p[p] = JacProb{sl.A,      commit ? sl.V : nullptr, h->states + p, sl.norms, (cx<double>*)sl.gpart, sl.dmat,
+                      sl.pflag,  sl.bmod, sl.pchk, tol_for(O(p), s.m), s.m, s.m, s.r, s.rpad, s.nblk,
+                      (int)sl.cap_gch};
   }
   timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
   const bool mixed = (h->prec == MPO_MIXED_SPLITBF16);
+  int stamp = 0;   // step stamps of the pair-skip bookkeeping (cleared by k_jac_init)
   auto sweeps = [&](int bf16, int budget) {
     bool active_left = true;
     for (int sw = 0; sw < budget && active_left; ++sw) {
       for (int step = 0; step < maxblk - 1; ++step) {
         timed(h, MPO_PROF_JACOBI_GRAM, [&] { launch_jac_gram<T>(jb, maxpairs, maxgch, step, bf16, st); });
-        timed(h, MPO_PROF_JACOBI_EVD, [&] { launch_jac_evd<T>(jb, maxpairs, step, bf16 ? 1 : 2, st); });
-        timed(h, MPO_PROF_JACOBI_ROT, [&] { launch_jac_rot<T>(jb, maxpairs, maxrch, step, bf16, st); });
+        ++stamp;
+        timed(h, MPO_PROF_JACOBI_EVD, [&] { launch_jac_evd<T>(jb, maxpairs, step, bf16 ? 1 : 2, stamp, st); });
+        timed(h, MPO_PROF_JACOBI_ROT, [&] {
+          launch_jac_rot<T>(jb, maxpairs, maxrch_a, commit ? maxrch_v : 0, step, bf16 ? ROT_MIXED : ROT_FP, st);
+        });
       }
       launch_jac_sweep_end(jb, st);
       hip_check(hipMemcpyAsync(h->h_states, h->states, count * sizeof(JacState), hipMemcpyDeviceToHost, st),
@@ -552,7 +584,8 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     const int k = out[p].k;
     vb.p[p] = VkProb{h->slots[p].V, h->slots[p].perm, h->slots[p].s_sorted, h->slots[p].Y, O(p)->site[s.i + 1],
                      O(p)->lam[s.i], s.n, s.r, k, s.rpad};
-    qa.p[p] = QrApplyProb{h->slots[p].theta0, h->slots[p].Tf, h->slots[p].Y, s.n, s.r, s.n, 0, k};
+    qa.p[p] = QrApplyProb{h->slots[p].theta0, h->slots[p].Tf, h->slots[p].Y, h->slots[p].qwp, h->slots[p].qw2,
+                          s.n, s.r, s.n, 0, k, s.m};
     lb.p[p] = GemmProb{h->slots[p].thetan, O(p)->site[s.i + 1], O(p)->site[s.i], s.m, k, s.n, s.n, s.n, k, 1};
     maxel = std::max(maxel, (size_t)k * s.n);
     maxk = std::max(maxk, k);
@@ -699,10 +732,14 @@ void destroy(mpo_ctx* h) {
     dfree(s.perm);
     dfree(s.tau);
     dfree(s.Tf);
+    dfree(s.qwp);
+    dfree(s.qw2);
     dfree(s.Y);
     dfree(s.gpart);
     dfree(s.dmat);
     dfree(s.pflag);
+    dfree(s.bmod);
+    dfree(s.pchk);
   }
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);
