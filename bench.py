@@ -129,16 +129,17 @@ def cpu_baseline(n, sites, lams, bond, chi, samples=1):
     return {"value": samples / dt, "unit": "bond updates/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{samples} oracle bond update(s) at (chi_l, chi, chi_r) = ({chi}, {chi}, {chi}), "
                       f"theta {4 * chi}x{4 * chi} complex128, numpy.linalg.svd (LAPACK gesdd); "
-                      f"{dt:.1f} s on {os.cpu_count()} host cores", "seconds": dt, "k": int(r.k)}
+                      f"with vectors and write-back tensors; {dt:.1f} s with {int(cores)} BLAS threads",
+            "seconds": dt, "k": int(r.k)}
 
 
-def run_precision(mpolib, torch, prec_name, args, n, sites, lams, bond, gates):
+def run_precision(mpolib, torch, prec_name, args, n, sites, lams, bond, gates, events=True):
     h = mpolib.MPO(n, args.chi, 1e-8, mpolib.CUT_WEIGHT, mpolib.PRECISIONS[prec_name])
     h.load_state(sites, lams)
     dims0 = h.bond_dims()
     for w in range(args.warmup):
         h.absorb(bond, *gates[w])
-    h.profile(True)
+    h.profile(events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = [h.absorb(bond, *gates[args.warmup + s]) for s in range(args.steps)]
@@ -156,6 +157,31 @@ KERNEL_NAME = {"jacobi_rot": "k_jac_rot", "jacobi_gram": "k_jac_gram",
                "jacobi_evd": "k_jac_evd", "qr": "k_qr_panel+k_qr_w1+k_qr_w2+k_qr_upd", "theta_gemm": "k_gemm",
                "writeback_gemm": "k_gemm"}
 KERNEL_NAME_MIXED = {"jacobi_rot": "k_jac_rot_mixed", "jacobi_gram": "k_jac_gram_bf16"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/*_traffic.md, two rocprofv3 --pmc passes scaled by the copy
+    calibration), or None when there is none or the kernel's source file has
+    changed since the counters were taken."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    for path in glob.glob(os.path.join(here, "profiles", "*_traffic.md")):
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", " ", "`")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        if fields.get("kernel") != kernel or "traffic_bytes_per_launch" not in fields:
+            continue
+        src = os.path.join(here, fields.get("source", ""))
+        if not os.path.isfile(src):
+            return None
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    return None
 
 
 def roofline_of(run, prec_name, chi, steps):
@@ -177,7 +203,7 @@ def roofline_of(run, prec_name, chi, steps):
     byt = kernel_bytes(dom, chi, sweeps, rots, esz) if hbm_bound else None
     names = dict(KERNEL_NAME, **(KERNEL_NAME_MIXED if prec_name == "mixed" else {}))
     out = {"kernel": names.get(dom, dom), "class": dom, "avg_launch_ms": round(ms / max(launches, 1), 5),
-           "launches_per_update": launches / steps, "traffic": None}
+           "launches_per_update": launches / steps, "traffic": measured_traffic(names.get(dom, dom))}
     if byt:
         achieved = byt / (ms * 1e-3) / 1e9
         out.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -240,7 +266,12 @@ def main():
     rng = np.random.default_rng(1234)
     gates = [(haar_su4(rng), haar_su4(rng)) for _ in range(args.warmup + args.steps)]
     chi = args.chi
-    run = run_precision(mpolib, torch, args.precision, args, n, sites, lams, bond, gates)
+    # the headline pass has no per-launch events in its timed region (recorded
+    # around every launch they cost about a tenth of the step); the same warmup
+    # and steps are then run again with HIP events on the library's stream
+    # around every launch, for the per-kernel times and the roofline
+    run = run_precision(mpolib, torch, args.precision, args, n, sites, lams, bond, gates, events=False)
+    prof_run = run_precision(mpolib, torch, args.precision, args, n, sites, lams, bond, gates, events=True)
     secs = run["secs"]
     value = args.steps / secs
     flops = algorithmic_flops(chi, chi, chi, chi)
@@ -253,16 +284,20 @@ def main():
                       "precision": args.precision, "kept_rank": [i["k"] for i in run["infos"]],
                       "jacobi_sweeps": [i["sweeps"] for i in run["infos"]],
                       "bond_dims_unchanged": run["dims_ok"]},
-           "roofline": roofline_of(run, args.precision, chi, args.steps),
+           "roofline": roofline_of(prof_run, args.precision, chi, args.steps),
+           "roofline_pass_ms_per_step": round(1e3 * prof_run["secs"] / args.steps, 3),
            "update_roofline_frac": round(flops["total"] / (secs / args.steps) / 1e12 /
                                          PEAK_TFLOPS["fp32" if args.precision != "fp64" else "fp64"], 5),
-           "kernels_ms_per_update": {c: round(v[0] / args.steps, 3) for c, v in run["prof"].items() if v[1]}}
+           "kernels_ms_per_update": {c: round(v[0] / args.steps, 3) for c, v in prof_run["prof"].items() if v[1]}}
     if args.compare and args.compare != args.precision:
-        cmp_run = run_precision(mpolib, torch, args.compare, args, n, sites, lams, bond, gates)
+        cmp_run = run_precision(mpolib, torch, args.compare, args, n, sites, lams, bond, gates, events=False)
+        cmp_prof = run_precision(mpolib, torch, args.compare, args, n, sites, lams, bond, gates, events=True)
         out["compare"] = {"precision": args.compare, "value": round(args.steps / cmp_run["secs"], 4),
                           "ms_per_step": round(1e3 * cmp_run["secs"] / args.steps, 3),
                           "jacobi_sweeps": [i["sweeps"] for i in cmp_run["infos"]],
-                          "roofline": roofline_of(cmp_run, args.compare, chi, args.steps),
+                          "roofline": roofline_of(cmp_prof, args.compare, chi, args.steps),
+                          "kernels_ms_per_update": {c: round(v[0] / args.steps, 3)
+                                                    for c, v in cmp_prof["prof"].items() if v[1]},
                           "speedup_of_headline": round(cmp_run["secs"] / secs, 3)}
     if rank == 0 and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, sites, lams, bond, chi)

@@ -21,17 +21,24 @@
 namespace mpo {
 
 // Left-looking factorisation of the QNB-column panel at p0, one workgroup of
-// 1024 threads (16 waves) per problem, with the current column held in LDS in
+// 512 threads (8 waves) per problem, with the current column held in LDS in
 // FP64 (rows p0..n-1, n - p0 <= 4096).  Column j of the panel:
-//  (1) one wave per earlier reflector q < j computes w_q = v_q^dag x and, for
-//      q < j - 1, z_q = v_q^dag v_{j-1}, which completes column j - 1 of T:
-//      T[0:j-1, j-1] = -tau_{j-1} T[0:j-1, 0:j-1] z;  then u = T^dag w and
-//      x <- x - V u  (Q^dag = I - V T^dag V^dag), row-parallel;
+//  (1) wave w serves the earlier reflectors q = w and q = w + 8 (q < j):
+//      w_q = v_q^dag x and, for q < j - 1, z_q = v_q^dag v_{j-1}, which
+//      completes column j - 1 of T: T[0:j-1, j-1] = -tau_{j-1} T[0:j-1, 0:j-1] z;
+//      then u = T^dag w and x <- x - V u  (Q^dag = I - V T^dag V^dag);
 //  (2) the tail norm, and thread 0 forms the reflector (LAPACK's complex
 //      Householder: beta = -sign(Re alpha) |x|, tau = (beta - alpha) / beta,
 //      v = [1; x_tail / (alpha - beta)]).
-// The last column of T is completed after the loop.
+// The panel's columns come from HBM (the previous launch wrote them), so every
+// loop is unrolled far enough that a thread's loads are in flight together;
+// 512 threads leave room for that in registers.  The last column of T is
+// completed after the loop.
 constexpr int QPN = 4096;   // largest panel height: n <= 4 chi_max
+constexpr int QPT = 512;    // threads of the panel workgroup
+constexpr int QRT = QPN / QPT;
+constexpr int QDU = 8;      // rows per lane whose loads a dot loop keeps in flight
+constexpr int QUG = 1;      // rows per thread updated together
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -39,7 +46,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
+__global__ __launch_bounds__(QPT) void k_qr_panel(QrBatch qb, int p0) {
   const int pi = blockIdx.x;
   if (pi >= qb.count) return;
   const QrProb P = qb.p[pi];
@@ -52,7 +59,7 @@ __global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
   cx<T>* Tf = (cx<T>*)P.Tf + (size_t)(p0 / QNB) * QNB * QNB;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   __shared__ cx<double> xs[QPN];           // the current column
-  __shared__ double red[16];
+  __shared__ double red[QPT / 64];
   __shared__ cx<double> Wd[QNB], Zd[QNB], U[QNB], Tl[QNB][QNB + 1];
   __shared__ double bc[8];
 
@@ -78,50 +85,124 @@ __global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
       Tl[tid][c] = cx<double>{-(tc.re * sr - tc.im * si), -(tc.re * si + tc.im * sr)};
     }
   };
+  // z_q = v_q^dag v_c for q = wv and q = wv + 8 below c (one wave)
+  auto z_dots = [&](int c) {
+    const int qa = wv, qb2 = wv + 8;
+    const bool hb = qb2 < c;
+    const cx<T>* va = M + (size_t)(p0 + qa) * n + p0;
+    const cx<T>* vb = M + (size_t)(p0 + (hb ? qb2 : qa)) * n + p0;
+    const cx<T>* yc = M + (size_t)(p0 + c) * n + p0;
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    if (lane == 0) {     // row c: v_c[c] = 1
+      ar = (double)va[c].re;
+      ai = -(double)va[c].im;
+      if (hb) {
+        br = (double)vb[c].re;
+        bi = -(double)vb[c].im;
+      }
+    }
+    for (int r0 = c + 1; r0 < N; r0 += 64 * QDU) {
+#pragma unroll
+      for (int k = 0; k < QDU; ++k) {
+        const int r = r0 + lane + 64 * k;
+        const int rc = min(r, N - 1);
+        const cx<T> y = yc[rc], v = va[rc], w = vb[rc];
+        const double mk = (r < N) ? 1.0 : 0.0;
+        ar += mk * ((double)v.re * (double)y.re + (double)v.im * (double)y.im);
+        ai += mk * ((double)v.re * (double)y.im - (double)v.im * (double)y.re);
+        br += mk * ((double)w.re * (double)y.re + (double)w.im * (double)y.im);
+        bi += mk * ((double)w.re * (double)y.im - (double)w.im * (double)y.re);
+      }
+    }
+    ar = wave_sum(ar);
+    ai = wave_sum(ai);
+    br = wave_sum(br);
+    bi = wave_sum(bi);
+    if (lane == 0) {
+      Zd[qa] = cx<double>{ar, ai};
+      if (hb) Zd[qb2] = cx<double>{br, bi};
+    }
+  };
 
   for (int jj = 0; jj < nb; ++jj) {
     cx<T>* colj = M + (size_t)(p0 + jj) * n + p0;
-    for (int r = tid; r < N; r += 1024) xs[r] = cx<double>{(double)colj[r].re, (double)colj[r].im};
+    {
+      cx<T> t[QRT];
+#pragma unroll
+      for (int u = 0; u < QRT; ++u) t[u] = colj[min(tid + QPT * u, N - 1)];   // clamped: no branch
+#pragma unroll
+      for (int u = 0; u < QRT; ++u) {
+        const int r = tid + QPT * u;
+        if (r < N) xs[r] = cx<double>{(double)t[u].re, (double)t[u].im};
+      }
+    }
     __syncthreads();
     if (jj > 0) {
       if (wv < jj) {
-        // w_q over rows r >= q (v_q[q] = 1 taken by lane 0), z_q over rows
-        // r >= j - 1 (v_{j-1}[j-1] = 1); branch-free unrolled loops so the
-        // loads of a lane are in flight together
-        const int q = wv;
-        const cx<T>* vc = M + (size_t)(p0 + q) * n + p0;
-        double sr = 0, si = 0, zr = 0, zi = 0;
+        // w_q for q = wv (rows > wv) and q = wv + 8 (rows > wv + 8); the
+        // diagonal terms v_q[q] = 1 are taken by lane 0
+        const int qa = wv, qb2 = wv + 8;
+        const bool hb = qb2 < jj;
+        const cx<T>* va = M + (size_t)(p0 + qa) * n + p0;
+        const cx<T>* vb = M + (size_t)(p0 + (hb ? qb2 : qa)) * n + p0;
+        double ar = 0, ai = 0, br = 0, bi = 0;
         if (lane == 0) {
-          sr = xs[q].re;
-          si = xs[q].im;
-        }
-#pragma unroll 8
-        for (int r = q + 1 + lane; r < N; r += 64) {
-          const cx<T> v = vc[r];
-          const cx<double> x = xs[r];
-          sr += (double)v.re * x.re + (double)v.im * x.im;
-          si += (double)v.re * x.im - (double)v.im * x.re;
-        }
-        if (q < jj - 1) {
-          const cx<T>* yc = M + (size_t)(p0 + jj - 1) * n + p0;
-          if (lane == 0) {
-            zr = (double)vc[jj - 1].re;
-            zi = -(double)vc[jj - 1].im;
-          }
-#pragma unroll 8
-          for (int r = jj + lane; r < N; r += 64) {
-            const cx<T> v = vc[r], y = yc[r];
-            zr += (double)v.re * (double)y.re + (double)v.im * (double)y.im;
-            zi += (double)v.re * (double)y.im - (double)v.im * (double)y.re;
+          ar = xs[qa].re;
+          ai = xs[qa].im;
+          if (hb) {
+            br = xs[qb2].re;
+            bi = xs[qb2].im;
           }
         }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        zr = wave_sum(zr);
-        zi = wave_sum(zi);
+        // z_q = v_q^dag v_{j-1} for q < j - 1 rides along: row j - 1 of
+        // v_{j-1} is 1 (lane 0 adds conj(v_q[j-1])), rows >= j are stored
+        const bool za = qa < jj - 1, zb = hb && qb2 < jj - 1;
+        const cx<T>* yc = M + (size_t)(p0 + max(jj - 1, 0)) * n + p0;
+        double zar = 0, zai = 0, zbr = 0, zbi = 0;
+        if (lane == 0 && za) {
+          zar = (double)va[jj - 1].re;
+          zai = -(double)va[jj - 1].im;
+          if (zb) {
+            zbr = (double)vb[jj - 1].re;
+            zbi = -(double)vb[jj - 1].im;
+          }
+        }
+        // blocks of QDU rows per lane: clamped addresses and masks instead of
+        // bounds branches, so a block's loads are in flight together
+        for (int r0 = qa + 1; r0 < N; r0 += 64 * QDU) {
+#pragma unroll
+          for (int k = 0; k < QDU; ++k) {
+            const int r = r0 + lane + 64 * k;
+            const int rc = min(r, N - 1);
+            const cx<double> x = xs[rc];
+            const cx<T> v = va[rc], w = vb[rc], y = yc[rc];
+            const double ma = (r < N) ? 1.0 : 0.0;
+            const double mb = (hb && r > qb2 && r < N) ? 1.0 : 0.0;
+            const double mz = (za && r >= jj && r < N) ? 1.0 : 0.0;
+            const double mzb = (zb && r >= jj && r < N) ? 1.0 : 0.0;
+            ar += ma * ((double)v.re * x.re + (double)v.im * x.im);
+            ai += ma * ((double)v.re * x.im - (double)v.im * x.re);
+            br += mb * ((double)w.re * x.re + (double)w.im * x.im);
+            bi += mb * ((double)w.re * x.im - (double)w.im * x.re);
+            zar += mz * ((double)v.re * (double)y.re + (double)v.im * (double)y.im);
+            zai += mz * ((double)v.re * (double)y.im - (double)v.im * (double)y.re);
+            zbr += mzb * ((double)w.re * (double)y.re + (double)w.im * (double)y.im);
+            zbi += mzb * ((double)w.re * (double)y.im - (double)w.im * (double)y.re);
+          }
+        }
+        ar = wave_sum(ar);
+        ai = wave_sum(ai);
+        br = wave_sum(br);
+        bi = wave_sum(bi);
+        zar = wave_sum(zar);
+        zai = wave_sum(zai);
+        zbr = wave_sum(zbr);
+        zbi = wave_sum(zbi);
         if (lane == 0) {
-          Wd[wv] = cx<double>{sr, si};
-          Zd[wv] = cx<double>{zr, zi};
+          Wd[qa] = cx<double>{ar, ai};
+          if (hb) Wd[qb2] = cx<double>{br, bi};
+          if (za) Zd[qa] = cx<double>{zar, zai};
+          if (zb) Zd[qb2] = cx<double>{zbr, zbi};
         }
       }
       __syncthreads();
@@ -137,28 +218,47 @@ __global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
         U[tid] = cx<double>{ur, ui};
       }
       __syncthreads();
-      for (int r = tid; r < N; r += 1024) {
-        cx<double> x = xs[r];
+      // every load from a valid address (row and column clamped), the value
+      // masked afterwards, so the loads of a row group are in flight together
+      for (int g = 0; g < QRT; g += QUG) {
+        cx<double> xg[QUG];
 #pragma unroll
-        for (int q = 0; q < QNB - 1; ++q) {
-          if (q < jj && q <= r) {
-            const cx<double> v = vq(q, r), u = U[q];
-            x.re -= v.re * u.re - v.im * u.im;
-            x.im -= v.re * u.im + v.im * u.re;
+        for (int u = 0; u < QUG; ++u) {
+          const int rc = min(tid + QPT * (g + u), N - 1);
+          cx<double> x = xs[rc];
+#pragma unroll
+          for (int q = 0; q < QNB - 1; ++q) {
+            // the loaded value is always used (times a 0/1 mask), so the
+            // compiler cannot sink the load behind a branch on q < j
+            const int cq = min(q, jj - 1);
+            const cx<T> t = M[(size_t)(p0 + cq) * n + p0 + rc];
+            const double live = (q < jj) ? 1.0 : 0.0;
+            const double below = (rc > q) ? live : 0.0;
+            const double diag = (rc == q) ? live : 0.0;
+            const double vr = below * (double)t.re + diag;
+            const double vi = below * (double)t.im;
+            const cx<double> uq = U[cq];
+            x.re -= vr * uq.re - vi * uq.im;
+            x.im -= vr * uq.im + vi * uq.re;
           }
+          xg[u] = x;
         }
-        xs[r] = x;
+#pragma unroll
+        for (int u = 0; u < QUG; ++u) {
+          const int r = tid + QPT * (g + u);
+          if (r < N) xs[r] = xg[u];
+        }
       }
       __syncthreads();
     }
     double s = 0;
-    for (int r = jj + 1 + tid; r < N; r += 1024) s += xs[r].re * xs[r].re + xs[r].im * xs[r].im;
+    for (int r = jj + 1 + tid; r < N; r += QPT) s += xs[r].re * xs[r].re + xs[r].im * xs[r].im;
     s = wave_sum(s);
     if (lane == 0) red[wv] = s;
     __syncthreads();
     if (tid == 0) {
       double xn2 = 0;
-      for (int w = 0; w < 16; ++w) xn2 += red[w];
+      for (int w = 0; w < QPT / 64; ++w) xn2 += red[w];
       const double ar = xs[jj].re, ai = xs[jj].im;
       double tr = 0, ti = 0, scr = 0, sci = 0, beta = ar;
       if (xn2 > 0 || ai != 0) {
@@ -182,38 +282,24 @@ __global__ __launch_bounds__(1024) void k_qr_panel(QrBatch qb, int p0) {
     {
       const double beta = bc[0], scr = bc[3], sci = bc[4];
       const bool trivial = (bc[1] == 0.0 && bc[2] == 0.0);
-      for (int r = tid; r < N; r += 1024) {
-        cx<double> y = xs[r];
-        if (r == jj) y = cx<double>{beta, 0.0};
-        else if (r > jj && !trivial) y = cx<double>{xs[r].re * scr - xs[r].im * sci, xs[r].re * sci + xs[r].im * scr};
-        colj[r] = cx<T>{(T)y.re, (T)y.im};
+#pragma unroll
+      for (int u = 0; u < QRT; ++u) {
+        const int r = tid + QPT * u;
+        if (r < N) {
+          cx<double> y = xs[r];
+          if (r == jj) y = cx<double>{beta, 0.0};
+          else if (r > jj && !trivial) y = cx<double>{xs[r].re * scr - xs[r].im * sci, xs[r].re * sci + xs[r].im * scr};
+          colj[r] = cx<T>{(T)y.re, (T)y.im};
+        }
       }
     }
     __syncthreads();
   }
   // last column of T: z_q = v_q^dag v_{nb-1}
   if (nb > 1) {
-    const int c = nb - 1;
-    if (wv < c) {
-      const cx<T>* vc = M + (size_t)(p0 + wv) * n + p0;
-      const cx<T>* yc = M + (size_t)(p0 + c) * n + p0;
-      double zr = 0, zi = 0;
-      if (lane == 0) {
-        zr = (double)vc[c].re;
-        zi = -(double)vc[c].im;
-      }
-#pragma unroll 8
-      for (int r = c + 1 + lane; r < N; r += 64) {
-        const cx<T> v = vc[r], y = yc[r];
-        zr += (double)v.re * (double)y.re + (double)v.im * (double)y.im;
-        zi += (double)v.re * (double)y.im - (double)v.im * (double)y.re;
-      }
-      zr = wave_sum(zr);
-      zi = wave_sum(zi);
-      if (lane == 0) Zd[wv] = cx<double>{zr, zi};
-    }
+    if (wv < nb - 1) z_dots(nb - 1);
     __syncthreads();
-    t_column(c);
+    t_column(nb - 1);
     __syncthreads();
   }
   if (tid < QNB * QNB) {
@@ -464,7 +550,7 @@ __global__ __launch_bounds__(256) void k_vh_rows(VkBatch vb) {
 // ---------------------------------------------------------------- launchers
 template <typename T>
 void launch_qr_panel(const QrBatch& b, int p0, hipStream_t s) {
-  hipLaunchKernelGGL(k_qr_panel<T>, dim3(b.count), dim3(1024), 0, s, b, p0);
+  hipLaunchKernelGGL(k_qr_panel<T>, dim3(b.count), dim3(QPT), 0, s, b, p0);
 }
 template <typename T>
 void launch_qr_apply(const QrApplyBatch& b, int p0, int maxcols, hipStream_t s) {

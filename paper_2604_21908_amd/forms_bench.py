@@ -2,6 +2,7 @@
 
     python -m paper_2604_21908_amd.forms_bench batch --count 16
     python -m paper_2604_21908_amd.forms_bench serve --rate 1 --duration 10
+    python -m paper_2604_21908_amd.forms_bench peak --config 1 --precisions fp32,mixed
 
 batch: the first `count` circuits of the batching workload (n ~ U{16..48},
 depth ~ U{4..10}, chi_max ~ U{128, 256, 512}, literal reading, FP32),
@@ -10,7 +11,11 @@ update; aggregate bond updates/s and makespan of both.
 serve: Poisson arrivals at `rate`/s for `duration` s, n in {24, 40, 56}
 (p = 0.5/0.3/0.2), depth n/4, chi_max 512, mixed precision, admission by
 projected n chi^2 16 B within `budget_gb`; p50/p99 time-to-peak from arrival
-and circuits/s.  --max-n and --chi-cap bound both workloads (widest circuit,
+and circuits/s, beside the same arrivals served one at a time in FP32.
+peak: time-to-peak of one seeded circuit of a configuration (literal reading;
+config 1: n = 32, depth 8, chi_max 256, discarded-weight cutoff 1e-8, parallel
+unswapping at size tau) in each precision, with the planted peak checked.
+--max-n and --chi-cap bound the batch and serve workloads (widest circuit,
 largest chi_max) so a run fits a time budget."""
 from __future__ import annotations
 
@@ -38,7 +43,10 @@ def _progress(tag):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("form", choices=["batch", "serve"])
+    ap.add_argument("form", choices=["batch", "serve", "peak"])
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--chi", type=int, default=256)
+    ap.add_argument("--precisions", default="fp32,mixed")
     ap.add_argument("--count", type=int, default=16)
     ap.add_argument("--tau", type=float, default=1e5)
     ap.add_argument("--rate", type=float, default=1.0)
@@ -48,6 +56,35 @@ def main(argv=None):
     ap.add_argument("--max-n", type=int, default=64, help="skip workload circuits wider than this")
     ap.add_argument("--chi-cap", type=int, default=1024, help="clip the workload's chi_max to this")
     a = ap.parse_args(argv)
+    if a.form == "peak":
+        import time as _t
+        circ = cg.config_circuit(a.config, reading="A")
+        tau = a.tau if a.tau != 1e5 else 2e4
+        out = {"form": "peak", "config": a.config, "n": circ.n, "chi_max": a.chi, "tau": tau, "runs": []}
+        for prec in a.precisions.split(","):
+            c = dr.Contractor(circ, dr.RunConfig(chi_max=a.chi, cutoff=1e-8, cutoff_mode="weight", precision=prec,
+                                                 tau=tau, unswap="parallel"))
+            steps = [0]
+            t0 = _t.perf_counter()
+            orig = c.absorb_step
+
+            def step(orig=orig):
+                orig()
+                steps[0] += 1
+                if steps[0] % 5 == 0:
+                    print(f"  [{prec}] step {steps[0]}, max chi {max(c.m.bond_dims())}, "
+                          f"t = {_t.perf_counter() - t0:.1f} s", flush=True)
+            c.absorb_step = step
+            res = c.run()
+            c.close()
+            ks = [x["k"] for x in res.trace if "k" in x]
+            out["runs"].append({"precision": prec, "time_to_peak_s": round(res.seconds, 3),
+                                "bond_updates": res.bond_updates, "max_chi": max(ks),
+                                "peak_ok": bool((res.bits == circ.peak).all()), "p_peak": res.prob,
+                                "updates_per_s": round(res.bond_updates / res.seconds, 1)})
+            print(json.dumps(out["runs"][-1]), flush=True)
+        print(json.dumps(out), flush=True)
+        return
     if a.form == "batch":
         prec = a.precision or "fp32"
         work = []
@@ -90,13 +127,22 @@ def main(argv=None):
         reqs = [r for r in sv.poisson_requests(a.rate, a.duration) if r.n <= a.max_n]
         print(f"  {len(reqs)} requests, n = {[r.n for r in reqs]}", flush=True)
         out = sv.serve(reqs, cfg, int(a.budget_gb * 2 ** 30), on_round=_progress("serve"))
+        print("  sequential FP32 baseline", flush=True)
+        base_cfg = dr.RunConfig(chi_max=cfg.chi_max, cutoff=cfg.cutoff, cutoff_mode=cfg.cutoff_mode,
+                                precision="fp32", tau=cfg.tau)
+        seq = sv.serve_sequential(reqs, base_cfg)
         print(json.dumps({"form": "serve", "rate": a.rate, "duration": a.duration, "requests": len(reqs),
                           "chi_max": cfg.chi_max, "max_n": a.max_n,
                           "served": len(out["served"]), "precision": prec, "seconds": round(out["seconds"], 3),
                           "circuits_per_s": round(out["circuits_per_s"], 4), "p50_time_to_peak_s": round(out["p50"], 3),
                           "p99_time_to_peak_s": round(out["p99"], 3), "all_peaks_ok": out["all_peaks_ok"],
                           "bond_updates": out["bond_updates"],
-                          "peak_projected_gb": round(out["peak_projected_bytes"] / 2 ** 30, 3)}), flush=True)
+                          "peak_projected_gb": round(out["peak_projected_bytes"] / 2 ** 30, 3),
+                          "sequential_fp32": {"seconds": round(seq["seconds"], 3),
+                                              "circuits_per_s": round(seq["circuits_per_s"], 4),
+                                              "p50_time_to_peak_s": round(seq["p50"], 3),
+                                              "p99_time_to_peak_s": round(seq["p99"], 3),
+                                              "all_peaks_ok": seq["all_peaks_ok"]}}), flush=True)
 
 
 if __name__ == "__main__":

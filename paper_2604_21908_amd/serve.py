@@ -121,3 +121,33 @@ def poisson_requests(rate: float, duration: float, seed: int = 4000, sizes=(24, 
         out.append(Request(t, n, max(1, n // 4), seed + 17 * k + 1))
         k += 1
     return out
+
+
+def serve_sequential(requests: Sequence[Request], cfg: dr.RunConfig, reading: str = "A") -> dict:
+    """Baseline for the served form: the same arrivals handled one circuit at
+    a time, first come first served, each contracted alone with one launch per
+    update wave.  The solo service time of every circuit is measured; the
+    queue is then exact for a single server: a request starts when it has
+    arrived and the previous one has finished."""
+    reqs = sorted(requests, key=lambda r: r.t_arrival)
+    service = []
+    ok = []
+    updates = 0
+    for r in reqs:
+        circ = cg.mirrored_peaked_circuit(r.n, r.depth, r.seed, reading=reading)
+        t0 = time.perf_counter()
+        res = dr.contract(circ, cfg)
+        service.append(time.perf_counter() - t0)
+        ok.append(bool((res.bits == circ.peak).all()))
+        updates += res.bond_updates
+    done = []
+    t_free = 0.0
+    for r, s in zip(reqs, service):
+        start = max(r.t_arrival, t_free)
+        t_free = start + s
+        done.append(t_free - r.t_arrival)
+    makespan = t_free if reqs else 0.0
+    ttp = np.array(done) if done else np.zeros(1)
+    return dict(seconds=makespan, circuits_per_s=len(reqs) / makespan if makespan else 0.0,
+                p50=float(np.percentile(ttp, 50)), p99=float(np.percentile(ttp, 99)),
+                all_peaks_ok=all(ok), bond_updates=updates, service_s=service)
