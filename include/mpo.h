@@ -184,6 +184,19 @@ mpo_status_t mpo_group_create(int32_t precision, void* hip_stream, mpo_group_t* 
 void mpo_group_free(mpo_group_t g);
 mpo_status_t mpo_group_absorb(mpo_group_t g, int32_t count, const mpo_handle_t* handles, const int32_t* bonds,
                               const double* g_out, const double* g_in, mpo_update_info_t* info);
+/* The parallel unswap schedule (App. A.1; schedule must be 1 in opts) run on
+ * `count` handles in lockstep: in each (cycle, side, parity) batch the SWAP
+ * trials of every handle still in the loop share launches, and so do the
+ * accepted commits.  A handle leaves after a cycle without a reduction (or
+ * after opts->max_iters cycles), exactly as in mpo_unswap_sweep, and its log,
+ * decisions and resulting MPO are those of mpo_unswap_sweep on it alone.
+ * logs: count x log_cap_each entries, row p for handles[p]; n_accepted[p]
+ * receives the number of accepted swaps of handle p.  Returns MPO_EOVERFLOW
+ * when a row was truncated, MPO_WARN_NOCONV when a Jacobi SVD hit its sweep
+ * cap.  Handles must be distinct and have the group's precision. */
+mpo_status_t mpo_group_unswap(mpo_group_t g, int32_t count, const mpo_handle_t* handles,
+                              const mpo_unswap_opts_t* opts, mpo_swap_t* logs, int32_t log_cap_each,
+                              int32_t* n_accepted);
 /* as mpo_profile, for the group's launches */
 mpo_status_t mpo_group_profile(mpo_group_t g, int32_t on, double* ms_out, int64_t* launches_out);
 const char* mpo_group_last_error(mpo_group_t g);

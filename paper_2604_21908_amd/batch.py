@@ -7,8 +7,11 @@ the bond updates reach the GPU: in every round each circuit that is absorbing
 contributes the ordered updates of its next absorption step; those are split
 into waves of mutually distant bonds per circuit, the waves of all circuits are
 merged, sorted by operand shape (chi_l, chi_r) and issued as group launches
-(mpo_group_absorb, up to 32 updates per launch).  Per-update arithmetic is the
-same as alone, so every circuit's result is identical to its lone run.
+(mpo_group_absorb, up to 32 updates per launch).  Circuits that reach their
+unswapping stage in the same round run the parallel schedule together
+(mpo_group_unswap: the trial and commit updates of one (side, parity) batch of
+all of them share launches).  Per-update arithmetic is the same as alone, so
+every circuit's result is identical to its lone run.
 """
 from __future__ import annotations
 
@@ -22,15 +25,17 @@ from . import driver as dr
 from . import mpo as _mpo
 
 GROUP_MAX = 32
+UNSWAP = object()      # next_step(): the circuit waits for its unswapping stage
 
 
 class CircuitTask:
     """Alg. 1 for one circuit as a resumable state machine."""
 
-    def __init__(self, circuit, cfg: dr.RunConfig, tag=None):
+    def __init__(self, circuit, cfg: dr.RunConfig, tag=None, group_unswap: bool = False):
         self.circuit = circuit
         self.cfg = cfg
         self.tag = tag
+        self.group_unswap = group_unswap and cfg.unswap == "parallel"
         self.c = dr.Contractor(circuit, cfg)
         self.phase_started = False
         self.result: Optional[dr.RunResult] = None
@@ -41,14 +46,18 @@ class CircuitTask:
     def done(self) -> bool:
         return self.result is not None
 
-    def next_step(self) -> Optional[List[dr.Update]]:
-        """Updates of the next absorption step; runs the unswap stage and the
+    def next_step(self):
+        """Updates of the next absorption step; runs the unswap stage (or, with
+        group unswapping, returns UNSWAP and waits for unswap_done) and the
         final readout when Alg. 1 reaches them.  None once finished."""
         c = self.c
         while True:
             if not (c.c_left or c.c_right):
                 if self.phase_started:
+                    if self.group_unswap:
+                        return UNSWAP
                     c.unswap()
+                    self.phase_started = False
                 self.result = c.finish()
                 self.t_done = time.perf_counter()
                 c.close()
@@ -58,8 +67,14 @@ class CircuitTask:
                 return c.plan_absorb()
             if c.m.total_elements() < self.cfg.tau:
                 return c.plan_absorb()
+            if self.group_unswap:
+                return UNSWAP
             c.unswap()
             self.phase_started = False
+
+    def unswap_done(self, log, before: int) -> None:
+        self.c.record_unswap(log, before)
+        self.phase_started = False
 
     def shape(self, bond: int):
         dims = self.c.m.bond_dims()
@@ -70,12 +85,24 @@ def run_round(tasks: Sequence[CircuitTask], group: Optional[_mpo.Group], per_upd
     """Advances every unfinished task by one absorption step; returns the
     number of bond updates issued."""
     steps = []
+    pend = []
     for t in tasks:
         if t.done:
             continue
         ups = t.next_step()
-        if ups:
+        if ups is UNSWAP:
+            pend.append(t)
+        elif ups:
             steps.append((t, ups))
+    if pend:
+        by_opts: Dict[tuple, list] = {}
+        for t in pend:
+            by_opts.setdefault((t.cfg.relaxed, t.cfg.max_unswap_iters), []).append(t)
+        for (relaxed, iters), ts in by_opts.items():
+            before = [t.c.m.total_elements() for t in ts]
+            logs = group.unswap([t.c.m for t in ts], relaxed, iters)
+            for t, log, b0 in zip(ts, logs, before):
+                t.unswap_done(log, b0)
     issued = 0
     if per_update:
         for t, ups in steps:
@@ -114,7 +141,7 @@ def run_batched(circuits_cfgs, precision: str = "fp32", per_update: bool = False
     aggregate throughput."""
     group = None if per_update else _mpo.Group(_mpo.PRECISIONS[precision])
     t0 = time.perf_counter()
-    tasks = [CircuitTask(c, cfg, tag=i) for i, (c, cfg) in enumerate(circuits_cfgs)]
+    tasks = [CircuitTask(c, cfg, tag=i, group_unswap=not per_update) for i, (c, cfg) in enumerate(circuits_cfgs)]
     updates = 0
     rounds = 0
     while not all(t.done for t in tasks):

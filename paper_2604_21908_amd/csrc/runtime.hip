@@ -915,6 +915,87 @@ mpo_status_t mpo_group_profile(mpo_group_t g, int32_t on, double* ms_out, int64_
   return mpo_profile(g->x, on, ms_out, launches_out);
 }
 
+mpo_status_t mpo_group_unswap(mpo_group_t g, int32_t count, const mpo_handle_t* handles,
+                              const mpo_unswap_opts_t* opts, mpo_swap_t* logs, int32_t log_cap_each,
+                              int32_t* n_accepted) {
+  if (!g) return MPO_EINVAL;
+  mpo_ctx* x = g->x;
+  if (!opts || count < 0 || (count > 0 && !handles) || log_cap_each < 0 || (log_cap_each > 0 && count > 0 && !logs))
+    return fail(x, MPO_EINVAL, "bad arguments");
+  if (opts->schedule != 1) return fail(x, MPO_EINVAL, "group unswapping runs the parallel schedule (1)");
+  for (int p = 0; p < count; ++p) {
+    mpo_ctx* o = handles[p];
+    if (!o || o->n == 0) return fail(x, MPO_EINVAL, "null handle");
+    if (o->prec != x->prec) return fail(x, MPO_EINVAL, "handle precision differs from the group's");
+    for (int q = 0; q < p; ++q)
+      if (handles[q] == o) return fail(x, MPO_EINVAL, "handles must be distinct");
+  }
+  const int max_iters = opts->max_iters > 0 ? opts->max_iters : 20;
+  const bool relaxed = opts->relaxed != 0;
+  std::vector<std::vector<mpo_swap_t>> acc(count);
+  std::vector<char> active(count, 1), reduced(count, 0);
+  bool noconv = false;
+  mpo_status_t s = guarded(x, [&]() -> mpo_status_t {
+    static const int order[6][2] = {{2, 0}, {2, 1}, {0, 0}, {0, 1}, {1, 0}, {1, 1}};
+    for (int cyc = 0; cyc < max_iters; ++cyc) {
+      bool any = false;
+      for (int p = 0; p < count; ++p) {
+        reduced[p] = 0;
+        any |= active[p] != 0;
+      }
+      if (!any) break;
+      for (int c = 0; c < 6; ++c) {
+        const int side = order[c][0], parity = order[c][1];
+        std::vector<Req> trials;
+        std::vector<int> who;
+        for (int p = 0; p < count; ++p) {
+          if (!active[p]) continue;
+          for (int b = parity; b <= handles[p]->n - 2; b += 2) {
+            Req q = swap_req(b, side);
+            q.owner = handles[p];
+            trials.push_back(q);
+            who.push_back(p);
+          }
+        }
+        if (trials.empty()) continue;
+        std::vector<Res> tr;
+        mpo_status_t r = updates(x, trials, tr, false);
+        if (r != MPO_OK) return r;
+        std::vector<Req> commits;
+        for (size_t t = 0; t < trials.size(); ++t) {
+          noconv |= tr[t].noconv;
+          const int p = who[t], b = trials[t].bond;
+          const int chi_b = handles[p]->chi[b + 1];
+          if (tr[t].k < chi_b || (relaxed && tr[t].k == chi_b)) {
+            commits.push_back(trials[t]);
+            acc[p].push_back(mpo_swap_t{side, b});
+            if (tr[t].k < chi_b) reduced[p] = 1;
+          }
+        }
+        if (!commits.empty()) {
+          std::vector<Res> cr;
+          r = updates(x, commits, cr, true);
+          if (r != MPO_OK) return r;
+          for (auto& y : cr) noconv |= y.noconv;
+        }
+      }
+      for (int p = 0; p < count; ++p)
+        if (!reduced[p]) active[p] = 0;
+    }
+    return MPO_OK;
+  });
+  if (s < 0) return s;
+  bool over = false;
+  for (int p = 0; p < count; ++p) {
+    const int nacc = (int)acc[p].size();
+    for (int j = 0; j < nacc && j < log_cap_each; ++j) logs[(size_t)p * log_cap_each + j] = acc[p][j];
+    if (n_accepted) n_accepted[p] = nacc;
+    over |= nacc > log_cap_each;
+  }
+  if (over) return fail(x, MPO_EOVERFLOW, "accepted-swap log truncated");
+  return noconv ? MPO_WARN_NOCONV : MPO_OK;
+}
+
 const char* mpo_group_last_error(mpo_group_t g) { return g ? g->x->err.c_str() : "null group"; }
 
 static mpo_status_t absorb_common(mpo_handle_t h, int32_t count, const int32_t* bonds, const double* g_out,

@@ -207,6 +207,11 @@ class Contractor:
             return []
         before = self.m.total_elements()
         log = self.m.unswap(self.cfg.unswap, self.cfg.relaxed, self.cfg.max_unswap_iters)
+        self.record_unswap(log, before)
+        return log
+
+    def record_unswap(self, log, before: int) -> None:
+        """Rewiring (Sec. II.B.2): fold the accepted swaps into the layouts."""
         for side, b in log:
             if side in ("L", "B"):
                 self.out_w.exchange(b)
@@ -214,7 +219,6 @@ class Contractor:
                 self.in_w.exchange(b)
         self.trace.append(dict(stage="unswap", accepted=len(log), size_before=before,
                                size=self.m.total_elements(), log=list(log)))
-        return log
 
     def run(self) -> RunResult:
         t0 = time.perf_counter()

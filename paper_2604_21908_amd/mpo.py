@@ -24,7 +24,8 @@ SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
 EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_batch", "mpo_unswap_sweep",
             "mpo_extract_peak", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
             "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_profile", "mpo_last_error", "mpo_version",
-            "mpo_group_create", "mpo_group_free", "mpo_group_absorb", "mpo_group_profile", "mpo_group_last_error"]
+            "mpo_group_create", "mpo_group_free", "mpo_group_absorb", "mpo_group_unswap", "mpo_group_profile",
+            "mpo_group_last_error"]
 PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_gram", "finalize", "writeback", "writeback_gemm", "qr",
                 "reorth", "jacobi_evd", "jacobi_rot"]
 
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mpo_group_free.restype = None
     lib.mpo_group_absorb.argtypes = [P, I32, ctypes.POINTER(P), ctypes.POINTER(I32), dp, dp,
                                      ctypes.POINTER(UpdateInfo)]
+    lib.mpo_group_unswap.argtypes = [P, I32, ctypes.POINTER(P), ctypes.POINTER(UnswapOpts), ctypes.POINTER(SwapEntry),
+                                     I32, ctypes.POINTER(I32)]
     lib.mpo_group_profile.argtypes = [P, I32, dp, ctypes.POINTER(I64)]
     lib.mpo_group_last_error.argtypes = [P]
     lib.mpo_group_last_error.restype = ctypes.c_char_p
@@ -309,6 +312,23 @@ class Group:
             raise MpoError(s, "mpo_group_absorb: " + self.lib.mpo_group_last_error(self.g).decode())
         return [dict(k=x.chi_new, sweeps=x.sweeps, discarded=x.discarded_weight, total=x.total_weight,
                      rotations=x.panel_rotations) for x in infos]
+
+    def unswap(self, mpos: Sequence["MPO"], relaxed: bool = False, max_iters: int = 20) -> List[List[Tuple[str, int]]]:
+        """Parallel unswapping of several MPOs in lockstep (mpo_group_unswap);
+        one accepted-swap log per MPO, equal to its lone mpo_unswap_sweep log."""
+        cnt = len(mpos)
+        if cnt == 0:
+            return []
+        hs = (ctypes.c_void_p * cnt)(*[m.h.value for m in mpos])
+        opts = UnswapOpts(1, int(relaxed), max_iters)
+        cap = max(64, 4 * max_iters * max(m.n for m in mpos))
+        logs = (SwapEntry * (cap * cnt))()
+        nacc = (ctypes.c_int32 * cnt)()
+        s = self.lib.mpo_group_unswap(self.g, cnt, hs, ctypes.byref(opts), logs, cap, nacc)
+        if s not in (0, 1):
+            raise MpoError(s, "mpo_group_unswap: " + self.lib.mpo_group_last_error(self.g).decode())
+        return [[(SIDE_NAMES[logs[p * cap + j].side], int(logs[p * cap + j].bond)) for j in range(nacc[p])]
+                for p in range(cnt)]
 
     def profile(self, on: bool) -> dict:
         nc = len(PROF_CLASSES)

@@ -75,7 +75,7 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
                 break
             pending.popleft()
             circ = cg.mirrored_peaked_circuit(r.n, r.depth, r.seed, reading=reading)
-            active.append((r, bt.CircuitTask(circ, cfg), time.perf_counter() - t0, need))
+            active.append((r, bt.CircuitTask(circ, cfg, group_unswap=True), time.perf_counter() - t0, need))
             used += need
             peak_used = max(peak_used, used)
         if not active:

@@ -56,3 +56,43 @@ def test_serving_admits_within_budget_and_matches_alone(mods):
         ref, _ = lone(dr, circ, cfg)
         assert s.prob == ref.prob
         assert s.time_to_peak >= 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_group_unswap_equals_per_mpo(mods, prec):
+    """mpo_group_unswap on three MPOs of different widths gives each the log
+    and tensors of its own mpo_unswap_sweep, bit for bit."""
+    from oracle import mpo_oracle as mo
+    from paper_2604_21908_amd import mpo as mpolib
+    code = {"fp64": 0, "fp32": 1}[prec]
+    states = []
+    for n, seed in ((7, 3), (9, 4), (6, 5)):
+        rng = np.random.default_rng(seed)
+        m = mo.OracleMPO(n)
+        for b in range(0, n - 1, 2):           # output SWAPs on even bonds, input SWAPs on odd
+            mo.commit(m, mo.bond_update(m, b, mo.SWAP4, None, 64, 1e-12, "rel_sv"))
+        for b in range(1, n - 1, 2):
+            mo.commit(m, mo.bond_update(m, b, None, mo.SWAP4, 64, 1e-12, "rel_sv"))
+        b0 = int(rng.integers(0, n - 1))       # one gate that no swap removes
+        mo.commit(m, mo.bond_update(m, b0, cg.haar_su4(rng), None, 64, 1e-12, "rel_sv"))
+        states.append(m)
+
+    def load():
+        hs = []
+        for m in states:
+            h = mpolib.MPO(m.n, 64, 1e-12, 0, code)
+            h.load_state(m.B, m.lam)
+            hs.append(h)
+        return hs
+    a, b = load(), load()
+    g = mpolib.Group(code)
+    logs = g.unswap(a)
+    g.close()
+    assert sum(len(x) for x in logs) > 0
+    for ha, hb, log in zip(a, b, logs):
+        assert log == hb.unswap("parallel")
+        assert ha.bond_dims() == hb.bond_dims()
+        for i in range(ha.n):
+            assert np.array_equal(ha.read_site(i), hb.read_site(i))
+        ha.close()
+        hb.close()
