@@ -386,7 +386,10 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
   int bi, bj;
   rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
   if (pair_unchanged(P, bi, bj)) return;
-  __shared__ cx<float> Pc[64][33];
+  // A 64-row slab, split once as it is staged: Sh[part][column][row] with
+  // parts re_hi, re_lo, im_hi, im_lo, transposed so that a lane's 8
+  // consecutive rows of one column (its MFMA operand) are one 16-byte read.
+  __shared__ __attribute__((aligned(16))) __bf16 Sh[4][32][72];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int I = wave >> 1, J = wave & 1, g8 = (lane >> 4) * 8;
   const cx<float>* A = (const cx<float>*)P.A;
@@ -401,26 +404,27 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
       if (s0 + lane < r1) nxt[u] = A[(size_t)panel_col(bi, bj, c) * P.lda + s0 + lane];
     }
   };
+  auto op = [&](int part, int c, int k) -> v8bf { return *(const v8bf*)&Sh[part][c][k]; };
   fetch(r0);
   for (int s0 = r0; s0 < r1; s0 += 64) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) Pc[lane][wave + 4 * u] = nxt[u];
+    for (int u = 0; u < 8; ++u) {
+      const int c = wave + 4 * u;
+      const __bf16 rh = (__bf16)nxt[u].re, ih = (__bf16)nxt[u].im;
+      Sh[0][c][lane] = rh;
+      Sh[1][c][lane] = (__bf16)(nxt[u].re - (float)rh);
+      Sh[2][c][lane] = ih;
+      Sh[3][c][lane] = (__bf16)(nxt[u].im - (float)ih);
+    }
     __syncthreads();
     if (s0 + 64 < r1) fetch(s0 + 64);
     v4f are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < 64; kk += 32) {
-      Split8 xr, xi, xn, yr, yi;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const cx<float> x = Pc[kk + g8 + e][I * 16 + (lane & 15)];
-        const cx<float> y = Pc[kk + g8 + e][J * 16 + (lane & 15)];
-        split_set(xr, e, x.re);
-        split_set(xi, e, x.im);
-        split_set(xn, e, -x.im);
-        split_set(yr, e, y.re);
-        split_set(yi, e, y.im);
-      }
+      const int cx_ = I * 16 + (lane & 15), cy = J * 16 + (lane & 15), k = kk + g8;
+      const Split8 xr{op(0, cx_, k), op(1, cx_, k)}, xi{op(2, cx_, k), op(3, cx_, k)};
+      const Split8 xn{-xi.hi, -xi.lo};
+      const Split8 yr{op(0, cy, k), op(1, cy, k)}, yi{op(2, cy, k), op(3, cy, k)};
       // conj(x) y
       are = mma3_bf16(xr, yr, are);
       are = mma3_bf16(xi, yi, are);
