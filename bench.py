@@ -162,8 +162,9 @@ KERNEL_NAME_MIXED = {"jacobi_rot": "k_jac_rot_mixed", "jacobi_gram": "k_jac_gram
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/*_traffic.md, two rocprofv3 --pmc passes scaled by the copy
-    calibration), or None when there is none or the kernel's source file has
-    changed since the counters were taken."""
+    calibration), or None when there is none or the kernel's sources (the
+    comma-separated `source` files, hashed in that order) have changed since
+    the counters were taken."""
     import glob
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
@@ -175,10 +176,13 @@ def measured_traffic(kernel):
                 fields[k.strip()] = v.strip()
         if fields.get("kernel") != kernel or "traffic_bytes_per_launch" not in fields:
             continue
-        src = os.path.join(here, fields.get("source", ""))
-        if not os.path.isfile(src):
-            return None
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields.get("source_sha256"):
+        digest = hashlib.sha256()
+        for name in fields.get("source", "").split(","):
+            src = os.path.join(here, name.strip())
+            if not name.strip() or not os.path.isfile(src):
+                return None
+            digest.update(open(src, "rb").read())
+        if digest.hexdigest() != fields.get("source_sha256"):
             return None
         return float(fields["traffic_bytes_per_launch"])
     return None

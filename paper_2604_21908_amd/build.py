@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["kernels.hip", "qr.hip", "jacobi.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "qr.hip", "jacobi.hip", "rotation.hip", "runtime.hip"]
 LIB = os.path.join(HERE, "libmpo.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -24,9 +24,13 @@ constexpr int RRC = 256;
 constexpr int ROT_FP = 0, ROT_MIXED = 1;
 
 // ---------------------------------------------------------------- GEMM
-// C[M x N] = A[M x K] * op(B), complex, row-major.
+// C[M x N] = C0 + A[M x K] * op(B), complex, row-major (C0 = 0 when null;
+// C0 has C's leading dimension and must not alias A or B).
 //   bmode 0: B is K x N row-major (ldb)
 //   bmode 1: op(B) = conj(W)^T with W an N x K row-major matrix (ldb)
+//   herm: the result is Hermitian; tiles of GEMM_TILE x GEMM_TILE entirely
+//         below the diagonal are not computed (their entries are left as is)
+constexpr int GEMM_TILE = 64;
 struct GemmProb {
   const void* A;
   const void* B;
@@ -34,6 +38,8 @@ struct GemmProb {
   int M, N, K;
   int lda, ldb, ldc;
   int bmode;
+  int herm;
+  const void* C0;
 };
 struct GemmBatch {
   GemmProb p[MAXB];
@@ -83,6 +89,27 @@ struct JacProb {
   double tol;     // off-diagonal tolerance |g_ij| <= tol sqrt(g_ii g_jj)
   int m, lda, ncol, ncol_pad, nblk, ngchunk;
 };
+// Round-robin pairing of N (even) indices: in step `step` (0 <= step < N - 1)
+// pair t (0 <= t < N / 2) is (a, b), a < b; every index appears once per step
+// and every pair once per N - 1 steps.
+__device__ __forceinline__ void rr_pair2(int N, int step, int t, int& a, int& b) {
+  if (t == 0) {
+    a = step;
+    b = N - 1;
+  } else {
+    a = (step + t) % (N - 1);
+    b = (step - t + (N - 1)) % (N - 1);
+  }
+  if (a > b) {
+    const int x = a;
+    a = b;
+    b = x;
+  }
+}
+
+// Operand column of panel column c (0 <= c < 2 JB): block bi, then block bj.
+__device__ __forceinline__ int panel_col(int bi, int bj, int c) { return c < JB ? bi * JB + c : bj * JB + c - JB; }
+
 __device__ __forceinline__ bool pair_unchanged(const JacProb& P, int bi, int bj) {
   const int c = P.pchk[bi * P.nblk + bj];
   return c > 0 && c > P.bmod[bi] && c > P.bmod[bj];

@@ -11,14 +11,10 @@
 //               at most one or two sweeps of cyclic Jacobi on G with FP64
 //               angles (the outer iteration finishes what they leave), and
 //               D = W - I rounded to the working precision
-//   k_jac_rot   P <- P + P D on MFMA over row chunks of RRC rows of theta's
-//               and V's panels, computed as P^T <- P^T + D^T P^T so that
-//               each 16-lane group of a wave reads and writes 16 consecutive
-//               rows of one column
-//   k_jac_gram_bf16 / k_jac_rot_mixed  the mixed form: Gram matrices with
-//               split-BF16 products, and one rotation launch in which theta's
-//               row chunks use split-BF16 products while the accumulated
-//               rotations V stay on FP32 MFMA (the EVD stays FP64)
+//   k_jac_rot   P <- P + P D (rotation.hip)
+//   k_jac_gram_bf16  the mixed form's Gram matrices with split-BF16 products
+//               (the EVD stays FP64)
+//   k_ns_corr   the Newton-Schulz correction of the mixed form's rotations
 #include "common.h"
 #include "mfma.h"
 
@@ -27,23 +23,6 @@ namespace mpo {
 // Inner cyclic-Jacobi sweeps per panel EVD (a kernel argument): two already
 // give the outer iteration its full convergence rate, more only add latency;
 // one costs about one extra outer sweep but halves the EVD.
-
-__device__ __forceinline__ void rr_pair2(int N, int step, int t, int& a, int& b) {
-  if (t == 0) {
-    a = step;
-    b = N - 1;
-  } else {
-    a = (step + t) % (N - 1);
-    b = (step - t + (N - 1)) % (N - 1);
-  }
-  if (a > b) {
-    const int x = a;
-    a = b;
-    b = x;
-  }
-}
-
-__device__ __forceinline__ int panel_col(int bi, int bj, int c) { return c < JB ? bi * JB + c : bj * JB + c - JB; }
 
 // ---------------------------------------------------------------- Gram
 template <typename T>
@@ -107,12 +86,61 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacBatch jb, int step) {
 }
 
 // ---------------------------------------------------------------- EVD
+// Refined hardware reciprocal and reciprocal square root (FP64, positive
+// normal arguments): the hardware estimate (about 2^-23 relative) followed by
+// two Newton steps, which square the relative error each, leaving a few ulp.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// Complex Jacobi rotation of pair (p, q) of the Hermitian G:
+// J = [[c, z], [-conj(z), c]] with z = s g_pq / |g_pq|, t = s / c the smaller
+// root of t^2 + 2 zeta t - 1 = 0, zeta = (g_qq - g_pp) / (2 |g_pq|); it zeroes
+// the (p, q) entry of J^dag G J.  Returns false (c = 1, z = 0) when |g_pq| is
+// below tol sqrt(g_pp g_qq).  Branch-free: the formula is evaluated for every
+// lane and the identity selected where no rotation applies.
+__device__ __forceinline__ bool jac_angle(double app, double aqq, cx<double> g, double tol, double& c, double& zr,
+                                          double& zi) {
+  const double g2 = g.re * g.re + g.im * g.im;
+  const bool rot = (g2 > 0.0) & (g2 > tol * tol * fmax(app * aqq, 0.0));
+  const double rm = rsq_nr(rot ? g2 : 1.0);            // 1 / |g_pq|
+  const double zeta = 0.5 * (aqq - app) * rm;
+  const double az = fabs(zeta);
+  // 1 / (|zeta| + sqrt(1 + zeta^2)); for |zeta| > 2^60 the root is |zeta| to
+  // working precision and zeta^2 could overflow
+  const bool big = az > 0x1p60;
+  const double z1 = big ? 1.0 : 1.0 + zeta * zeta;
+  const double h = z1 * rsq_nr(z1);
+  const double ta = rcp_nr(big ? az : az + h) * (big ? 0.5 : 1.0);
+  const double t = zeta >= 0.0 ? ta : -ta;
+  const double cv = rsq_nr(1.0 + t * t);
+  const double sm = t * cv * rm;
+  c = rot ? cv : 1.0;
+  zr = rot ? sm * g.re : 0.0;
+  zi = rot ? sm * g.im : 0.0;
+  return rot;
+}
+
 // In a round-robin step the 32 indices form 16 disjoint pairs; the rotation
-// J = [[c, z], [-conj(z), c]] of pair k acts on columns (p_k, q_k).  Thread
-// (kr, kc) owns the 2x2 block of G at rows (p_kr, q_kr) x columns (p_kc, q_kc)
-// and replaces it by J_kr^dag G_block J_kc, and likewise W's rows (p_kr, q_kr)
-// x columns (p_kc, q_kc) by W_block J_kc: every entry is read and written by
-// exactly one thread, so the update runs in place.
+// J_k of pair k acts on columns (p_k, q_k).  Thread (kr, kc) owns the 2x2
+// block of G at rows (p_kr, q_kr) x columns (p_kc, q_kc) and replaces it by
+// J_kr^dag G_block J_kc, and likewise W's rows (p_kr, q_kr) x columns
+// (p_kc, q_kc) by W_block J_kc: every entry is written by exactly one thread.
+// Every lane computes the angle of its own column pair kc from the round's G;
+// the row pair's angle comes from the lane of the same wave whose kc equals kr.
+// G is double-buffered (read one copy, write the other), so a round needs a
+// single barrier; W is updated in place (each thread touches only its block).
 template <typename T>
 __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inner_sweeps, int stamp) {
   const int pi = blockIdx.y;
@@ -121,9 +149,8 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
   if (P.st->active == 0) return;
   const double tol = P.tol;
-  __shared__ cx<double> G[32][33];
+  __shared__ cx<double> G[2][32][33];
   __shared__ cx<double> W[32][33];
-  __shared__ double rc[16], rzr[16], rzi[16];
   __shared__ int flag, anyrot;
   const int tid = threadIdx.x;
   const int gi = tid >> 3, gj0 = (tid & 7) * 4;
@@ -147,17 +174,20 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
       sr += v.re;
       si += v.im;
     }
-    G[gi][gj0 + u] = cx<double>{sr, si};
+    G[0][gi][gj0 + u] = cx<double>{sr, si};
     W[gi][gj0 + u] = cx<double>{(gi == gj0 + u) ? 1.0 : 0.0, 0.0};
   }
-  if (tid == 0) flag = 0;
+  if (tid == 0) {
+    flag = 0;
+    anyrot = 0;
+  }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int j = gj0 + u;
     if (j > gi) {
-      const cx<double> g = G[gi][j];
-      const double d = G[gi][gi].re * G[j][j].re;
+      const cx<double> g = G[0][gi][j];
+      const double d = G[0][gi][gi].re * G[0][j][j].re;
       if (d > 0 && g.re * g.re + g.im * g.im > tol * tol * d) flag = 1;
     }
   }
@@ -176,57 +206,36 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
     atomicAdd(&P.st->rot, 1);
   }
   const int kr = tid >> 4, kc = tid & 15;
+  const int src = (tid & 48) | kr;   // lane of this wave with kc == kr
+  int cur = 0;
   for (int isw = 0; isw < inner_sweeps; ++isw) {
-    if (tid == 0) anyrot = 0;
-    __syncthreads();
-    for (int st = 0; st < 31; ++st) {
-      if (tid < 16) {
-        int p, q;
-        rr_pair2(32, st, tid, p, q);
-        const double app = G[p][p].re, aqq = G[q][q].re;
-        const cx<double> g = G[p][q];
-        const double mag = sqrt(g.re * g.re + g.im * g.im);
-        double c = 1.0, zr = 0.0, zi = 0.0;
-        if (mag > 0.0 && mag > tol * sqrt(fmax(app * aqq, 0.0))) {
-          const double zeta = (aqq - app) / (2.0 * mag);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          const double s = t * c;
-          zr = s * g.re / mag;
-          zi = s * g.im / mag;
-          anyrot = 1;
-        }
-        rc[tid] = c;
-        rzr[tid] = zr;
-        rzi[tid] = zi;
-      }
-      __syncthreads();
+    for (int st = 0; st < 31; ++st, cur ^= 1) {
+      const cx<double>(*Gc)[33] = G[cur];
+      cx<double>(*Gn)[33] = G[cur ^ 1];
       int pr, qr, pc, qc;
       rr_pair2(32, st, kr, pr, qr);
       rr_pair2(32, st, kc, pc, qc);
-      const double cr = rc[kr], zrr = rzr[kr], zri = rzi[kr];
-      const double cc = rc[kc], zcr = rzr[kc], zci = rzi[kc];
-      if (!(zrr == 0.0 && zri == 0.0 && zcr == 0.0 && zci == 0.0)) {
-        // H = G_block J_c, J_c = [[cc, zc], [-conj(zc), cc]]
-        const cx<double> a00 = G[pr][pc], a01 = G[pr][qc], a10 = G[qr][pc], a11 = G[qr][qc];
-        // x * (-conj(zc)) = -(x.re zcr + x.im zci) + i (x.re zci - x.im zcr)
-        const double h00r = a00.re * cc - (a01.re * zcr + a01.im * zci);
-        const double h00i = a00.im * cc + (a01.re * zci - a01.im * zcr);
-        const double h01r = a00.re * zcr - a00.im * zci + a01.re * cc;
-        const double h01i = a00.re * zci + a00.im * zcr + a01.im * cc;
-        const double h10r = a10.re * cc - (a11.re * zcr + a11.im * zci);
-        const double h10i = a10.im * cc + (a11.re * zci - a11.im * zcr);
-        const double h11r = a10.re * zcr - a10.im * zci + a11.re * cc;
-        const double h11i = a10.re * zci + a10.im * zcr + a11.im * cc;
-        // G' = J_r^dag H, J_r^dag = [[cr, -zr], [conj(zr), cr]]
-        G[pr][pc] = cx<double>{cr * h00r - (zrr * h10r - zri * h10i), cr * h00i - (zrr * h10i + zri * h10r)};
-        G[pr][qc] = cx<double>{cr * h01r - (zrr * h11r - zri * h11i), cr * h01i - (zrr * h11i + zri * h11r)};
-        G[qr][pc] = cx<double>{zrr * h00r + zri * h00i + cr * h10r, zrr * h00i - zri * h00r + cr * h10i};
-        G[qr][qc] = cx<double>{zrr * h01r + zri * h01i + cr * h11r, zrr * h01i - zri * h01r + cr * h11i};
-      }
+      const cx<double> a00 = Gc[pr][pc], a01 = Gc[pr][qc], a10 = Gc[qr][pc], a11 = Gc[qr][qc];
+      const cx<double> w00 = W[pr][pc], w01 = W[pr][qc], w10 = W[qr][pc], w11 = W[qr][qc];
+      double cc, zcr, zci;
+      if (jac_angle(Gc[pc][pc].re, Gc[qc][qc].re, Gc[pc][qc], tol, cc, zcr, zci)) anyrot = isw + 1;
+      const double cr = __shfl(cc, src, 64), zrr = __shfl(zcr, src, 64), zri = __shfl(zci, src, 64);
+      // H = G_block J_c; x * (-conj(zc)) = -(x.re zcr + x.im zci) + i (x.re zci - x.im zcr)
+      const double h00r = a00.re * cc - (a01.re * zcr + a01.im * zci);
+      const double h00i = a00.im * cc + (a01.re * zci - a01.im * zcr);
+      const double h01r = a00.re * zcr - a00.im * zci + a01.re * cc;
+      const double h01i = a00.re * zci + a00.im * zcr + a01.im * cc;
+      const double h10r = a10.re * cc - (a11.re * zcr + a11.im * zci);
+      const double h10i = a10.im * cc + (a11.re * zci - a11.im * zcr);
+      const double h11r = a10.re * zcr - a10.im * zci + a11.re * cc;
+      const double h11i = a10.re * zci + a10.im * zcr + a11.im * cc;
+      // G' = J_r^dag H, J_r^dag = [[cr, -zr], [conj(zr), cr]]
+      Gn[pr][pc] = cx<double>{cr * h00r - (zrr * h10r - zri * h10i), cr * h00i - (zrr * h10i + zri * h10r)};
+      Gn[pr][qc] = cx<double>{cr * h01r - (zrr * h11r - zri * h11i), cr * h01i - (zrr * h11i + zri * h11r)};
+      Gn[qr][pc] = cx<double>{zrr * h00r + zri * h00i + cr * h10r, zrr * h00i - zri * h00r + cr * h10i};
+      Gn[qr][qc] = cx<double>{zrr * h01r + zri * h01i + cr * h11r, zrr * h01i - zri * h01r + cr * h11i};
       if (!(zcr == 0.0 && zci == 0.0)) {
         // W' = W_block J_c on rows (pr, qr)
-        const cx<double> w00 = W[pr][pc], w01 = W[pr][qc], w10 = W[qr][pc], w11 = W[qr][qc];
         W[pr][pc] = cx<double>{w00.re * cc - (w01.re * zcr + w01.im * zci), w00.im * cc + (w01.re * zci - w01.im * zcr)};
         W[pr][qc] = cx<double>{w00.re * zcr - w00.im * zci + w01.re * cc, w00.re * zci + w00.im * zcr + w01.im * cc};
         W[qr][pc] = cx<double>{w10.re * cc - (w11.re * zcr + w11.im * zci), w10.im * cc + (w11.re * zci - w11.im * zcr)};
@@ -234,9 +243,9 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
       }
       __syncthreads();
     }
-    const int any = anyrot;
-    __syncthreads();
-    if (!any) break;
+    // anyrot only grows and is isw + 1 or more iff some pair rotated in this
+    // sweep; every thread reads it after the sweep's last barrier
+    if (anyrot <= isw) break;
   }
   // D = W - I, rounded entry by entry (see k_jac_rot)
   cx<T>* D = (cx<T>*)P.dmat + (size_t)blockIdx.x * 1024;
@@ -245,130 +254,6 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
     const int r = gi, c = gj0 + u;
     D[r * 32 + c] = cx<T>{(T)(W[r][c].re - (r == c ? 1.0 : 0.0)), (T)W[r][c].im};
   }
-}
-
-// ---------------------------------------------------------------- rotation
-// Row space of a panel: rows [0, m) of theta's operand A, then rows [0, nv)
-// of V.  out^T = P^T + D^T P^T for 16-row strips; lane (l & 15) owns row
-// strip0 + (l & 15).
-// part 0: all rows; 1: theta's rows [0, m) only; 2: V's rows only.
-// Element (row rho, panel column c) of the panel's row space: rows [0, m) of
-// theta's operand A, then V's rows.
-template <typename T>
-__device__ __forceinline__ cx<T>* panel_ptr(const JacProb& P, int bi, int bj, int rho, int c) {
-  if (rho < P.m) return (cx<T>*)P.A + (size_t)panel_col(bi, bj, c) * P.lda + rho;
-  return (cx<T>*)P.V + (size_t)panel_col(bi, bj, c) * P.ncol_pad + (rho - P.m);
-}
-
-// A wave's 16-row strip is loaded once, element (row lane & 15, column
-// (lane >> 4) + 4 u) into slot u -- the MFMA B-operand layout, 16 consecutive
-// rows of a column per 16-lane group -- with rows past c1 clamped to a valid
-// row (never stored).  The accumulator layout is read back through the wave's
-// own LDS tile.  DS instructions of one wave execute in order, so the tile
-// needs no barrier; the wave_barrier only keeps the compiler from reordering.
-template <typename T>
-struct StripBase {
-  cx<T>* base;   // A or V
-  int ld;
-  int row;       // clamped row within base
-};
-template <typename T>
-__device__ __forceinline__ StripBase<T> strip_base(const JacProb& P, int rho) {
-  if (rho < P.m) return StripBase<T>{(cx<T>*)P.A, P.lda, rho};
-  return StripBase<T>{(cx<T>*)P.V, P.ncol_pad, rho - P.m};
-}
-// colB[u]: panel column of load slot u; colA[4 t + r]: of accumulator entry
-template <typename T>
-__device__ __forceinline__ void strip_load(const StripBase<T>& sb, const int (&colB)[8], cx<T> (&v)[8]) {
-#pragma unroll
-  for (int u = 0; u < 8; ++u) v[u] = sb.base[colB[u] * sb.ld + sb.row];   // < 2^24 elements: int offsets
-}
-
-// Rows [c0, c1) of the panel's row space, FP MFMA (T = float or double).
-// Software-pipelined: a wave issues the loads of its next strip before it
-// multiplies and stores the current one.
-template <typename T>
-__device__ __forceinline__ void rot_rows(const JacProb& P, int bi, int bj, int c0, int c1, const cx<T> (*Ds)[33],
-                                         cx<T> (*Sw)[33]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  typedef typename MF<T>::acc acc_t;
-  int colB[8], colA[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) colB[u] = panel_col(bi, bj, (lane >> 4) + 4 * u);
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) colA[4 * t + r] = panel_col(bi, bj, t * 16 + MF<T>::row(lane, r));
-  int s0 = c0 + wave * 16;
-  if (s0 >= c1) return;
-  cx<T> v[8];
-  strip_load<T>(strip_base<T>(P, min(s0 + (lane & 15), c1 - 1)), colB, v);
-  for (; s0 < c1; s0 += 64) {
-    const bool more = s0 + 64 < c1;
-    cx<T> nv[8];
-    if (more) strip_load<T>(strip_base<T>(P, min(s0 + 64 + (lane & 15), c1 - 1)), colB, nv);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) Sw[lane & 15][(lane >> 4) + 4 * u] = v[u];
-    __builtin_amdgcn_wave_barrier();
-    acc_t cre[2], cim[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const cx<T> a = Sw[lane & 15][t * 16 + MF<T>::row(lane, r)];
-        cre[t][r] = a.re;
-        cim[t][r] = a.im;
-      }
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int k = 4 * kk + (lane >> 4);
-      const cx<T> x = v[kk];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const cx<T> d = Ds[k][t * 16 + (lane & 15)];   // A[c][k] = D[k][c]
-        cre[t] = MF<T>::mma(d.re, x.re, cre[t]);
-        cre[t] = MF<T>::mma(-d.im, x.im, cre[t]);
-        cim[t] = MF<T>::mma(d.re, x.im, cim[t]);
-        cim[t] = MF<T>::mma(d.im, x.re, cim[t]);
-      }
-    }
-    const int rho = s0 + (lane & 15);
-    if (rho < c1) {
-      const StripBase<T> sb = strip_base<T>(P, rho);
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sb.base[colA[4 * t + r] * sb.ld + sb.row] = cx<T>{cre[t][r], cim[t][r]};
-    }
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = nv[u];
-    }
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step, int part) {
-  const int pi = blockIdx.z;
-  if (pi >= jb.count) return;
-  const JacProb P = jb.p[pi];
-  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
-  if (P.st->active == 0) return;
-  if (P.pflag[blockIdx.x] == 0) return;
-  const int nv = P.V ? P.ncol : 0;
-  const int rows = (part == 1) ? P.m : P.m + nv;
-  const int c0 = (part == 2 ? P.m : 0) + blockIdx.y * RRC;
-  if (c0 >= rows) return;
-  const int c1 = min(rows, c0 + RRC);
-  int bi, bj;
-  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
-  __shared__ cx<T> Ds[32][33];
-  __shared__ cx<T> Sw[4][16][33];   // one strip tile per wave
-  const cx<T>* D = (const cx<T>*)P.dmat + (size_t)blockIdx.x * 1024;
-  for (int e = threadIdx.x; e < 1024; e += 256) Ds[e >> 5][e & 31] = D[e];
-  __syncthreads();
-  rot_rows<T>(P, bi, bj, c0, c1, Ds, Sw[threadIdx.x >> 6]);
 }
 
 // ---------------------------------------------------------------- split-BF16
@@ -446,136 +331,30 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
   }
 }
 
-// theta's rows [c0, c1) (c1 <= m) on split-BF16 products; the accumulated
-// rotations V stay on FP32 MFMA (rot_rows) so that V remains unitary to FP32
-// accuracy.
-__device__ __forceinline__ void rot_rows_bf16(const JacProb& P, int bi, int bj, int c0, int c1,
-                                              const cx<float> (*Ds)[33], cx<float> (*Sw)[33]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g8 = (lane >> 4) * 8;
-  // A operands D^T[c][k] = D[k][c] for the two 16-column halves, split once
-  Split8 dr[2], di[2], dn[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const cx<float> d = Ds[g8 + e][t * 16 + (lane & 15)];
-      split_set(dr[t], e, d.re);
-      split_set(di[t], e, d.im);
-      split_set(dn[t], e, -d.im);
-    }
-  int colB[8], colA[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) colB[u] = panel_col(bi, bj, (lane >> 4) + 4 * u) * P.lda;
-#pragma unroll
-  for (int t = 0; t < 2; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) colA[4 * t + r] = panel_col(bi, bj, t * 16 + MF<float>::row(lane, r)) * P.lda;
-  const cx<float>* A = (const cx<float>*)P.A;
-  cx<float>* Aw = (cx<float>*)P.A;
-  int s0 = c0 + wave * 16;
-  if (s0 >= c1) return;
-  cx<float> v[8];
-  {
-    const int row = min(s0 + (lane & 15), c1 - 1);
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = A[colB[u] + row];
-  }
-  for (; s0 < c1; s0 += 64) {
-    const bool more = s0 + 64 < c1;
-    cx<float> nv[8];
-    if (more) {
-      const int row = min(s0 + 64 + (lane & 15), c1 - 1);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) nv[u] = A[colB[u] + row];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) Sw[lane & 15][(lane >> 4) + 4 * u] = v[u];
-    __builtin_amdgcn_wave_barrier();
-    v4f cre[2], cim[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const cx<float> a = Sw[lane & 15][t * 16 + MF<float>::row(lane, r)];
-        cre[t][r] = a.re;
-        cim[t][r] = a.im;
-      }
-    Split8 xr, xi;   // B operand: this lane's columns g8 .. g8 + 7
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const cx<float> x = Sw[lane & 15][g8 + e];
-      split_set(xr, e, x.re);
-      split_set(xi, e, x.im);
-    }
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      cre[t] = mma3_bf16(dr[t], xr, cre[t]);
-      cre[t] = mma3_bf16(dn[t], xi, cre[t]);
-      cim[t] = mma3_bf16(dr[t], xi, cim[t]);
-      cim[t] = mma3_bf16(di[t], xr, cim[t]);
-    }
-    const int row = s0 + (lane & 15);
-    if (row < c1) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Aw[colA[4 * t + r] + row] = cx<float>{cre[t][r], cim[t][r]};
-    }
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = nv[u];
-    }
-  }
-}
-
-// One launch for both row sets of the mixed form: row chunks y < ny_theta
-// rotate theta's rows on split-BF16, the others V's rows on FP32, so the
-// memory-bound and the MFMA-bound workgroups share the machine.
-__global__ __launch_bounds__(256) void k_jac_rot_mixed(JacBatch jb, int step, int ny_theta) {
-  const int pi = blockIdx.z;
-  if (pi >= jb.count) return;
-  const JacProb P = jb.p[pi];
-  if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
-  if (P.st->active == 0) return;
-  if (P.pflag[blockIdx.x] == 0) return;
-  const bool theta = (int)blockIdx.y < ny_theta;
-  int c0, c1;
-  if (theta) {
-    c0 = blockIdx.y * RRC;
-    if (c0 >= P.m) return;
-    c1 = min(P.m, c0 + RRC);
-  } else {
-    const int nv = P.V ? P.ncol : 0;
-    c0 = P.m + (blockIdx.y - ny_theta) * RRC;
-    if (c0 >= P.m + nv) return;
-    c1 = min(P.m + nv, c0 + RRC);
-  }
-  int bi, bj;
-  rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
-  __shared__ cx<float> Ds[32][33];
-  __shared__ cx<float> Sw[4][16][33];   // one strip tile per wave
-  const cx<float>* D = (const cx<float>*)P.dmat + (size_t)blockIdx.x * 1024;
-  for (int e = threadIdx.x; e < 1024; e += 256) Ds[e >> 5][e & 31] = D[e];
-  __syncthreads();
-  if (theta) rot_rows_bf16(P, bi, bj, c0, c1, Ds, Sw[threadIdx.x >> 6]);
-  else rot_rows<float>(P, bi, bj, c0, c1, Ds, Sw[threadIdx.x >> 6]);
-}
-
-// Newton-Schulz step toward the polar factor in FP64: S <- (3 I - S) / 2.
-__global__ void k_ns_coef(cx<double>* S, int n) {
+// Newton-Schulz step toward the polar factor, W <- W + W (I - W^dag W) / 2
+// in the transposed row-major storage X = W^T: X <- X + E X with
+// E = (I - S) / 2, S = X X^dag (FP64, only its upper tiles computed; the
+// lower ones are the conjugates).  E, of the size of the drift from
+// unitarity, is rounded to the working precision T.
+template <typename T>
+__global__ void k_ns_corr(const cx<double>* S, cx<T>* E, int n) {
   const size_t tot = (size_t)n * n;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
-    const size_t i = e / n, j = e - i * n;
-    const cx<double> v = S[e];
-    S[e] = cx<double>{((i == j) ? 1.5 : 0.0) - 0.5 * v.re, -0.5 * v.im};
+    const int i = (int)(e / n), j = (int)(e - (size_t)i * n);
+    cx<double> v = S[e];
+    if (i / GEMM_TILE > j / GEMM_TILE) {
+      const cx<double> u = S[(size_t)j * n + i];
+      v = cx<double>{u.re, -u.im};
+    }
+    E[e] = cx<T>{(T)(0.5 * ((i == j ? 1.0 : 0.0) - v.re)), (T)(-0.5 * v.im)};
   }
 }
 
-void launch_ns_coef(cx<double>* S, int n, hipStream_t s) {
+template <typename T>
+void launch_ns_corr(const cx<double>* S, cx<T>* E, int n, hipStream_t s) {
   size_t g = ((size_t)n * n + 255) / 256;
   g = g < 1 ? 1 : (g > 2048 ? 2048 : g);
-  hipLaunchKernelGGL(k_ns_coef, dim3((unsigned)g), dim3(256), 0, s, S, n);
+  hipLaunchKernelGGL(k_ns_corr<T>, dim3((unsigned)g), dim3(256), 0, s, S, E, n);
 }
 
 template <typename T>
@@ -589,26 +368,14 @@ template <typename T>
 void launch_jac_evd(const JacBatch& b, int maxpairs, int step, int inner_sweeps, int stamp, hipStream_t s) {
   hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, inner_sweeps, stamp);
 }
-template <typename T>
-void launch_jac_rot(const JacBatch& b, int maxpairs, int maxrch_a, int maxrch_v, int step, int mode, hipStream_t s) {
-  if (mode == ROT_MIXED)
-    hipLaunchKernelGGL(k_jac_rot_mixed, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step,
-                       maxrch_a);
-  else
-    hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step, 0);
-}
 template <>
 void launch_jac_gram<double>(const JacBatch& b, int maxpairs, int maxgch, int step, int, hipStream_t s) {
   hipLaunchKernelGGL(k_jac_gram<double>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
 }
-template <>
-void launch_jac_rot<double>(const JacBatch& b, int maxpairs, int maxrch_a, int maxrch_v, int step, int,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_jac_rot<double>, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step, 0);
-}
 template void launch_jac_gram<float>(const JacBatch&, int, int, int, int, hipStream_t);
-template void launch_jac_rot<float>(const JacBatch&, int, int, int, int, int, hipStream_t);
 template void launch_jac_evd<float>(const JacBatch&, int, int, int, int, hipStream_t);
 template void launch_jac_evd<double>(const JacBatch&, int, int, int, int, hipStream_t);
+template void launch_ns_corr<float>(const cx<double>*, cx<float>*, int, hipStream_t);
+template void launch_ns_corr<double>(const cx<double>*, cx<double>*, int, hipStream_t);
 
 }  // namespace mpo

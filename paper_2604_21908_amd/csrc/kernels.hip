@@ -31,7 +31,7 @@ __device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
 // A[i][k] from lane i + 16k and B[k][j] from lane j + 16k.  Element r of the
 // result holds D[4*(lane>>4) + r][lane & 15] for the f32 instruction and
 // D[(lane>>4) + 4*r][lane & 15] for the f64 one (measured on gfx950).
-constexpr int GT = 64;
+constexpr int GT = GEMM_TILE;
 constexpr int GK = 16;
 
 template <typename T> __device__ __forceinline__ int mfma_row(int lane, int r);
@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmBatch gb) {
   const GemmProb P = gb.p[pi];
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
   if (m0 >= P.M || n0 >= P.N) return;
+  if (P.herm && m0 >= n0 + GT) return;
   __shared__ cx<T> As[GT][GK + 1];
   __shared__ cx<T> Bs[GK][GT + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmBatch gb) {
     __syncthreads();
   }
   cx<T>* C = (cx<T>*)P.C;
+  const cx<T>* C0 = (const cx<T>*)P.C0;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -119,7 +121,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmBatch gb) {
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + i * 16 + mfma_row<T>(lane, r);
         const int col = n0 + wn + j * 16 + (lane & 15);
-        if (row < P.M && col < P.N) C[(size_t)row * P.ldc + col] = cx<T>{accr[i][j][r], acci[i][j][r]};
+        if (row < P.M && col < P.N) {
+          cx<T> v{accr[i][j][r], acci[i][j][r]};
+          if (C0) {
+            const cx<T> c0 = C0[(size_t)row * P.ldc + col];
+            v.re += c0.re;
+            v.im += c0.im;
+          }
+          C[(size_t)row * P.ldc + col] = v;
+        }
       }
 }
 

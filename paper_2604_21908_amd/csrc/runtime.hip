@@ -21,7 +21,7 @@ template <typename T> void launch_jac_init(const JacBatch&, hipStream_t);
 template <typename T> void launch_jac_gram(const JacBatch&, int, int, int, int, hipStream_t);
 template <typename T> void launch_jac_evd(const JacBatch&, int, int, int, int, hipStream_t);
 template <typename T> void launch_jac_rot(const JacBatch&, int, int, int, int, int, hipStream_t);
-void launch_ns_coef(cx<double>*, int, hipStream_t);
+template <typename T> void launch_ns_corr(const cx<double>*, cx<T>*, int, hipStream_t);
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
 void launch_sort_trunc(const TruncBatch&, hipStream_t);
@@ -324,12 +324,14 @@ RShapes sh_r(const S* sh, int count) {
 }
 
 // Mixed form, after the split-BF16 sweeps: W (the accumulated rotations,
-// r x r, rotated on FP32 MFMA) is replaced by its polar factor with one FP64
-// Newton-Schulz step W <- (3 I - W W^dag) W / 2 (its drift from unitarity is
-// at FP32 rounding level, so one step lands below FP32 resolution), and the
-// Jacobi operand, whose split-BF16 rotations drifted, is recomputed as A = L W
-// from L = R^dag, so that its columns are an exact unitary transform of L
-// again before the FP32 polish.
+// r x r, rotated on FP32 MFMA) is replaced by its polar factor with one
+// Newton-Schulz step W <- W + W (I - W^dag W) / 2.  Its drift from unitarity
+// is at FP32 rounding level, so one step lands below FP32 resolution; the
+// Gram W^dag W is formed in FP64 (only its upper tiles: it is Hermitian), and
+// the correction, of the size of the drift, is applied with an FP32 product.
+// Then the Jacobi operand, whose split-BF16 rotations drifted, is recomputed
+// as A = L W from L = R^dag, so that its columns are an exact unitary
+// transform of L again.
 template <typename T>
 void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStream_t st) {
   for (int p = 0; p < rs.count; ++p) {
@@ -343,7 +345,7 @@ void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStrea
       h->cap_ns = 0;
       h->ns_x = dalloc(nn * sizeof(cx<double>));
       h->ns_s = dalloc(nn * sizeof(cx<double>));
-      h->ns_y = dalloc(nn * sizeof(cx<double>));
+      h->ns_y = dalloc(2 * nn * h->esz);   // E and the new W, working precision
       h->cap_ns = nn;
     }
     const size_t nl = (size_t)s.m * s.rpad;
@@ -357,18 +359,19 @@ void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStrea
     Slot& sl = h->slots[p];
     cx<double>* X = (cx<double>*)h->ns_x;
     cx<double>* S = (cx<double>*)h->ns_s;
-    cx<double>* Y = (cx<double>*)h->ns_y;
+    cx<T>* E = (cx<T>*)h->ns_y;            // correction, then (after E) the new W
+    cx<T>* Wn = E + nn;
     launch_convert<double, T>(X, (const cx<T>*)sl.V, nn, st);
     GemmBatch g1{};
     g1.count = 1;
-    g1.p[0] = GemmProb{X, X, S, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, 1};
+    g1.p[0] = GemmProb{X, X, S, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, 1, 1, nullptr};
     launch_gemm<double>(g1, s.rpad, s.rpad, st);
-    launch_ns_coef(S, s.rpad, st);
+    launch_ns_corr<T>(S, E, s.rpad, st);
     GemmBatch g2{};
     g2.count = 1;
-    g2.p[0] = GemmProb{S, X, Y, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, 0};
-    launch_gemm<double>(g2, s.rpad, s.rpad, st);
-    launch_convert<T, double>((cx<T>*)sl.V, Y, nn, st);
+    g2.p[0] = GemmProb{E, sl.V, Wn, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, s.rpad, 0, 0, sl.V};
+    launch_gemm<T>(g2, s.rpad, s.rpad, st);
+    hip_check(hipMemcpyAsync(sl.V, Wn, nn * sizeof(cx<T>), hipMemcpyDeviceToDevice, st), "polar copy");
     LowerBatch lw{};
     lw.count = 1;
     lw.p[0] = LowerProb{sl.theta0, h->lbuf, s.n, s.m, s.r, s.rpad, s.m};
