@@ -86,49 +86,55 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacBatch jb, int step) {
 }
 
 // ---------------------------------------------------------------- EVD
-// Refined hardware reciprocal and reciprocal square root (FP64, positive
-// normal arguments): the hardware estimate (about 2^-23 relative) followed by
-// two Newton steps, which square the relative error each, leaving a few ulp.
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
+// Hardware reciprocal and reciprocal square root estimates (FP64, positive
+// normal arguments, about 2^-23 relative) refined by Newton steps, each of
+// which squares the relative error: one step leaves about 2^-45, two a few
+// ulp.
+__device__ __forceinline__ double rcp_nr1(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
 }
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double e = fma(-x * y, y, 1.0);
-  y = fma(0.5 * y, e, y);
-  e = fma(-x * y, y, 1.0);
-  return fma(0.5 * y, e, y);
+__device__ __forceinline__ double rsq_nr1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+__device__ __forceinline__ double rsq_nr2(double x) {
+  const double y = rsq_nr1(x);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
 }
 
 // Complex Jacobi rotation of pair (p, q) of the Hermitian G:
-// J = [[c, z], [-conj(z), c]] with z = s g_pq / |g_pq|, t = s / c the smaller
-// root of t^2 + 2 zeta t - 1 = 0, zeta = (g_qq - g_pp) / (2 |g_pq|); it zeroes
-// the (p, q) entry of J^dag G J.  Returns false (c = 1, z = 0) when |g_pq| is
-// below tol sqrt(g_pp g_qq).  Branch-free: the formula is evaluated for every
-// lane and the identity selected where no rotation applies.
+// J = [[c, z], [-conj(z), c]], z = tau c, c = 1 / sqrt(1 + |tau|^2), with the
+// complex tangent tau = t g_pq / |g_pq| and t the smaller root of
+// t^2 + 2 zeta t - 1 = 0, zeta = (g_qq - g_pp) / (2 |g_pq|); it zeroes the
+// (p, q) entry of J^dag G J.  Only c needs full accuracy: c^2 + |z|^2 = 1
+// holds for whatever tau is used, so tau (which only sets how well the entry
+// is zeroed) comes from once-refined estimates.  Returns false (c = 1, z = 0)
+// when |g_pq| is below tol sqrt(g_pp g_qq).  Branch-free: evaluated for every
+// lane, the identity selected where no rotation applies.
 __device__ __forceinline__ bool jac_angle(double app, double aqq, cx<double> g, double tol, double& c, double& zr,
                                           double& zi) {
   const double g2 = g.re * g.re + g.im * g.im;
   const bool rot = (g2 > 0.0) & (g2 > tol * tol * fmax(app * aqq, 0.0));
-  const double rm = rsq_nr(rot ? g2 : 1.0);            // 1 / |g_pq|
+  const double g2s = rot ? g2 : 1.0;
+  const double rm = rsq_nr1(g2s);                      // ~ 1 / |g_pq|
   const double zeta = 0.5 * (aqq - app) * rm;
   const double az = fabs(zeta);
   // 1 / (|zeta| + sqrt(1 + zeta^2)); for |zeta| > 2^60 the root is |zeta| to
   // working precision and zeta^2 could overflow
   const bool big = az > 0x1p60;
   const double z1 = big ? 1.0 : 1.0 + zeta * zeta;
-  const double h = z1 * rsq_nr(z1);
-  const double ta = rcp_nr(big ? az : az + h) * (big ? 0.5 : 1.0);
+  const double h = z1 * rsq_nr1(z1);
+  const double ta = rcp_nr1(big ? az : az + h) * (big ? 0.5 : 1.0);
   const double t = zeta >= 0.0 ? ta : -ta;
-  const double cv = rsq_nr(1.0 + t * t);
-  const double sm = t * cv * rm;
+  // the phase g_pq / |g_pq| first (|g_pq| may be near the underflow limit,
+  // its reciprocal near overflow), then tau = t e and |tau|^2 = t^2 |e|^2
+  const double er = g.re * rm, ei = g.im * rm;
+  const double cv = rsq_nr2(fma(t * t, er * er + ei * ei, 1.0));
+  const double sv = t * cv;
   c = rot ? cv : 1.0;
-  zr = rot ? sm * g.re : 0.0;
-  zi = rot ? sm * g.im : 0.0;
+  zr = rot ? sv * er : 0.0;
+  zi = rot ? sv * ei : 0.0;
   return rot;
 }
 
@@ -141,41 +147,67 @@ __device__ __forceinline__ bool jac_angle(double app, double aqq, cx<double> g, 
 // the row pair's angle comes from the lane of the same wave whose kc equals kr.
 // G is double-buffered (read one copy, write the other), so a round needs a
 // single barrier; W is updated in place (each thread touches only its block).
+// The pairs of the 31 rounds are tabulated once as LDS byte offsets.
+constexpr int EVD_LD = 33;                       // row stride of G and W (entries)
+constexpr int EVD_ROWB = EVD_LD * 16;            // ... in bytes (cx<double>)
 template <typename T>
 __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inner_sweeps, int stamp) {
   const int pi = blockIdx.y;
   if (pi >= jb.count) return;
   const JacProb P = jb.p[pi];
   if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
-  if (P.st->active == 0) return;
   const double tol = P.tol;
-  __shared__ cx<double> G[2][32][33];
-  __shared__ cx<double> W[32][33];
+  __shared__ cx<double> G[2][32][EVD_LD];
+  __shared__ cx<double> W[32][EVD_LD];
+  __shared__ ushort4 ptab[31][16];   // pair k of round st: (p, q) row and column byte offsets
   __shared__ int flag, anyrot;
   const int tid = threadIdx.x;
   const int gi = tid >> 3, gj0 = (tid & 7) * 4;
   int* pflag = P.pflag + blockIdx.x;
   int bi, bj;
   rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
-  if (pair_unchanged(P, bi, bj)) {
-    if (tid == 0) *pflag = 0;
-    return;
-  }
-  // sum of the partial Gram matrices in chunk order (deterministic)
+  // Every load of the set-up is issued before any of them is tested: the
+  // state flag, the pair-skip stamps and all partial Gram matrices (read even
+  // for a pair that turns out skipped; their sum is then discarded).
+  const int active = P.st->active;
+  const int chk = P.pchk[bi * P.nblk + bj], mod_i = P.bmod[bi], mod_j = P.bmod[bj];
   const int nch = (P.m + GRC - 1) / GRC;
-  const cx<double>* gp = P.gpart + (size_t)blockIdx.x * P.ngchunk * 1024;
+  const cx<double>* gp = P.gpart + (size_t)blockIdx.x * P.ngchunk * 1024 + gi * 32 + gj0;
+  double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+  for (int c0 = 0; c0 < nch; c0 += 8) {
+    cx<double> v[8][4];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const size_t off = (size_t)min(c0 + c, nch - 1) * 1024;   // clamped, masked below
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[c][u] = gp[off + u];
+    }
+    // in chunk order (deterministic); a clamped duplicate adds zero
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double w = (c0 + c < nch) ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sr[u] += w * v[c][u].re;
+        si[u] += w * v[c][u].im;
+      }
+    }
+  }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int e = gi * 32 + gj0 + u;
-    double sr = 0, si = 0;
-#pragma unroll 4
-    for (int c = 0; c < nch; ++c) {
-      const cx<double> v = gp[(size_t)c * 1024 + e];
-      sr += v.re;
-      si += v.im;
-    }
-    G[0][gi][gj0 + u] = cx<double>{sr, si};
+    G[0][gi][gj0 + u] = cx<double>{sr[u], si[u]};
     W[gi][gj0 + u] = cx<double>{(gi == gj0 + u) ? 1.0 : 0.0, 0.0};
+  }
+  for (int e = tid; e < 31 * 16; e += 256) {
+    int p, q;
+    rr_pair2(32, e >> 4, e & 15, p, q);
+    ptab[e >> 4][e & 15] = ushort4{(unsigned short)(p * EVD_ROWB), (unsigned short)(q * EVD_ROWB),
+                                   (unsigned short)(p * 16), (unsigned short)(q * 16)};
+  }
+  if (active == 0) return;
+  if (chk > 0 && chk > mod_i && chk > mod_j) {   // unchanged converged pair
+    if (tid == 0) *pflag = 0;
+    return;
   }
   if (tid == 0) {
     flag = 0;
@@ -207,18 +239,24 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   }
   const int kr = tid >> 4, kc = tid & 15;
   const int src = (tid & 48) | kr;   // lane of this wave with kc == kr
+  char* const g0 = (char*)&G[0][0][0];
+  char* const wb = (char*)&W[0][0];
   int cur = 0;
   for (int isw = 0; isw < inner_sweeps; ++isw) {
     for (int st = 0; st < 31; ++st, cur ^= 1) {
-      const cx<double>(*Gc)[33] = G[cur];
-      cx<double>(*Gn)[33] = G[cur ^ 1];
-      int pr, qr, pc, qc;
-      rr_pair2(32, st, kr, pr, qr);
-      rr_pair2(32, st, kc, pc, qc);
-      const cx<double> a00 = Gc[pr][pc], a01 = Gc[pr][qc], a10 = Gc[qr][pc], a11 = Gc[qr][qc];
-      const cx<double> w00 = W[pr][pc], w01 = W[pr][qc], w10 = W[qr][pc], w11 = W[qr][qc];
+      char* const gc = g0 + cur * (32 * EVD_ROWB);
+      char* const gn = g0 + (cur ^ 1) * (32 * EVD_ROWB);
+      const ushort4 R = ptab[st][kr], C = ptab[st][kc];
+      auto at = [](char* base, int off) -> cx<double>& { return *(cx<double>*)(base + off); };
+      const cx<double> a00 = at(gc, R.x + C.z), a01 = at(gc, R.x + C.w), a10 = at(gc, R.y + C.z),
+                       a11 = at(gc, R.y + C.w);
+      const cx<double> w00 = at(wb, R.x + C.z), w01 = at(wb, R.x + C.w), w10 = at(wb, R.y + C.z),
+                       w11 = at(wb, R.y + C.w);
+      // column pair's own entries: (p, p) at row p col p, (q, q), (p, q)
+      const double app = at(gc, C.x + C.z).re, aqq = at(gc, C.y + C.w).re;
+      const cx<double> gpq = at(gc, C.x + C.w);
       double cc, zcr, zci;
-      if (jac_angle(Gc[pc][pc].re, Gc[qc][qc].re, Gc[pc][qc], tol, cc, zcr, zci)) anyrot = isw + 1;
+      if (jac_angle(app, aqq, gpq, tol, cc, zcr, zci)) anyrot = isw + 1;
       const double cr = __shfl(cc, src, 64), zrr = __shfl(zcr, src, 64), zri = __shfl(zci, src, 64);
       // H = G_block J_c; x * (-conj(zc)) = -(x.re zcr + x.im zci) + i (x.re zci - x.im zcr)
       const double h00r = a00.re * cc - (a01.re * zcr + a01.im * zci);
@@ -230,16 +268,20 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
       const double h11r = a10.re * zcr - a10.im * zci + a11.re * cc;
       const double h11i = a10.re * zci + a10.im * zcr + a11.im * cc;
       // G' = J_r^dag H, J_r^dag = [[cr, -zr], [conj(zr), cr]]
-      Gn[pr][pc] = cx<double>{cr * h00r - (zrr * h10r - zri * h10i), cr * h00i - (zrr * h10i + zri * h10r)};
-      Gn[pr][qc] = cx<double>{cr * h01r - (zrr * h11r - zri * h11i), cr * h01i - (zrr * h11i + zri * h11r)};
-      Gn[qr][pc] = cx<double>{zrr * h00r + zri * h00i + cr * h10r, zrr * h00i - zri * h00r + cr * h10i};
-      Gn[qr][qc] = cx<double>{zrr * h01r + zri * h01i + cr * h11r, zrr * h01i - zri * h01r + cr * h11i};
+      at(gn, R.x + C.z) = cx<double>{cr * h00r - (zrr * h10r - zri * h10i), cr * h00i - (zrr * h10i + zri * h10r)};
+      at(gn, R.x + C.w) = cx<double>{cr * h01r - (zrr * h11r - zri * h11i), cr * h01i - (zrr * h11i + zri * h11r)};
+      at(gn, R.y + C.z) = cx<double>{zrr * h00r + zri * h00i + cr * h10r, zrr * h00i - zri * h00r + cr * h10i};
+      at(gn, R.y + C.w) = cx<double>{zrr * h01r + zri * h01i + cr * h11r, zrr * h01i - zri * h01r + cr * h11i};
       if (!(zcr == 0.0 && zci == 0.0)) {
         // W' = W_block J_c on rows (pr, qr)
-        W[pr][pc] = cx<double>{w00.re * cc - (w01.re * zcr + w01.im * zci), w00.im * cc + (w01.re * zci - w01.im * zcr)};
-        W[pr][qc] = cx<double>{w00.re * zcr - w00.im * zci + w01.re * cc, w00.re * zci + w00.im * zcr + w01.im * cc};
-        W[qr][pc] = cx<double>{w10.re * cc - (w11.re * zcr + w11.im * zci), w10.im * cc + (w11.re * zci - w11.im * zcr)};
-        W[qr][qc] = cx<double>{w10.re * zcr - w10.im * zci + w11.re * cc, w10.re * zci + w10.im * zcr + w11.im * cc};
+        at(wb, R.x + C.z) =
+            cx<double>{w00.re * cc - (w01.re * zcr + w01.im * zci), w00.im * cc + (w01.re * zci - w01.im * zcr)};
+        at(wb, R.x + C.w) =
+            cx<double>{w00.re * zcr - w00.im * zci + w01.re * cc, w00.re * zci + w00.im * zcr + w01.im * cc};
+        at(wb, R.y + C.z) =
+            cx<double>{w10.re * cc - (w11.re * zcr + w11.im * zci), w10.im * cc + (w11.re * zci - w11.im * zcr)};
+        at(wb, R.y + C.w) =
+            cx<double>{w10.re * zcr - w10.im * zci + w11.re * cc, w10.re * zci + w10.im * zcr + w11.im * cc};
       }
       __syncthreads();
     }
