@@ -548,9 +548,267 @@ __global__ __launch_bounds__(256) void k_vh_rows(VkBatch vb) {
 }
 
 // ---------------------------------------------------------------- launchers
+// Panel factorisation over several workgroups (panels of at least
+// QMW_MIN_ROWS rows).  Workgroup w holds panel rows [256 w, 256 w + 256), one
+// per thread, all QNB columns in FP64 registers, and the columns are factored
+// right-looking.  Column j needs the tail norm |x_{>j}|^2 and alpha = x_j
+// (summed over the problem's workgroups; every workgroup then forms the same
+// reflector, LAPACK's complex Householder as in k_qr_panel, and scales its
+// rows of v_j), then one more sum: w_k = v_j^dag a_k (k > j) and
+// z_q = v_q^dag v_j (q < j), after which a_k <- a_k - c_k v_j with
+// c_k = conj(tau_j) w_k (H_j^dag from the left) and
+// T[0:j, j] = -tau_j T[0:j, 0:j] z.  The second sum also carries, for column
+// j + 1, A = |a_{j+1}|^2, B = a_{j+1}^dag v_j, C = |v_j|^2 over the rows below
+// j + 1 and the row-(j + 1) entries, so that its tail norm
+// A - 2 Re(c B) + |c|^2 C and alpha come without a sum of their own; when the
+// expansion could lose more than about one digit to cancellation
+// (result < 1/10 of A + 2|c||B| + |c|^2 C) the norm is summed exactly
+// instead (a rank-deficient panel takes a few such sums; a generic one none
+// after its first column).  Sums run per wave, over waves in order, then over workgroups in
+// order, so every workgroup gets the same bits and takes the same decisions.
+// A barrier is a counter every workgroup increments and polls; the poll
+// gives up after QMW_SPIN rounds, and then no later barrier of the launch
+// waits (tau is poisoned with NaN, which the caller reports as a numerical
+// failure), so every wave finishes.
+constexpr int QMW_SPIN = 1 << 20;
+static_assert(QMW_ROWS * QMW_MAXWG >= QPN, "every panel row needs a thread");
+static_assert(2 * (QNB - 1) + 8 <= QMW_VALS && QMW_ROWS / 64 == 4, "partial layout");
+
+// Per-wave sums of C values per lane through LDS: each wave writes its
+// values value-major (stride 65 doubles, so a wave's write and the summing
+// threads' reads spread over the banks), then thread (w, i) adds the 64
+// entries of value i of wave w with four accumulators in a fixed order --
+// one pass instead of C dependent shuffle chains.  red[w][i] <- the sum.
+constexpr int QMW_LD = 65;
+template <int C>
+__device__ __forceinline__ void qmw_block_sum(const double (&vals)[C], double (*red)[QMW_VALS], double* big, int tid) {
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int i = 0; i < C; ++i) big[(wv * C + i) * QMW_LD + lane] = vals[i];
+  __syncthreads();
+  if (tid < 4 * C) {
+    const int w = tid / C, i = tid - w * C;
+    const double* p = big + (w * C + i) * QMW_LD;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+    for (int l = 0; l < 64; l += 4) {
+      s0 += p[l];
+      s1 += p[l + 1];
+      s2 += p[l + 2];
+      s3 += p[l + 3];
+    }
+    red[w][i] = (s0 + s1) + (s2 + s3);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(QMW_ROWS) void k_qr_panel_mw(QrBatch qb, QrSyncBatch sb, int p0) {
+  const int pi = blockIdx.y;
+  if (pi >= qb.count) return;
+  const QrProb P = qb.p[pi];
+  if (p0 >= P.r) return;
+  const int n = P.n, N = n - p0;
+  const int nwg = (N + QMW_ROWS - 1) / QMW_ROWS;
+  const int w = blockIdx.x;
+  if (w >= nwg) return;
+  const int nb = min(QNB, P.r - p0);
+  const QrSyncProb S = sb.p[pi];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int rr = w * QMW_ROWS + tid;   // panel row (absolute row p0 + rr)
+  const bool live = rr < N;
+  const int rcl = min(rr, N - 1);
+  cx<T>* M = (cx<T>*)P.M;
+  cx<T>* tau = (cx<T>*)P.tau;
+  cx<T>* Tf = (cx<T>*)P.Tf + (size_t)(p0 / QNB) * QNB * QNB;
+  cx<double> a[QNB];
+#pragma unroll
+  for (int k = 0; k < QNB; ++k) {
+    const cx<T> t = M[(size_t)(p0 + min(k, nb - 1)) * n + p0 + rcl];   // clamped, masked
+    const bool use = live && k < nb;
+    a[k] = use ? cx<double>{(double)t.re, (double)t.im} : cx<double>{0.0, 0.0};
+  }
+  __shared__ double red[QMW_ROWS / 64][QMW_VALS];
+  __shared__ double big[QMW_ROWS / 64 * (2 * (QNB - 1) + 8) * QMW_LD];
+  __shared__ double tot[QMW_VALS];
+  __shared__ cx<double> Tl[QNB][QNB + 1];
+  __shared__ int timed_out;
+  if (tid == 0) timed_out = 0;
+  unsigned bar = 0;   // barriers passed in this launch (uniform)
+  // block partials red[][0:C) -> this workgroup's slot, barrier, sum over
+  // workgroups in order -> tot[0:C).  One release (thread 0's add; the
+  // block barrier before it orders the other threads' stores) and one
+  // acquire (thread 0's fence after the wait; the block barrier after it
+  // orders the other threads' loads) per barrier.
+  auto grid_sum = [&](int C) {
+    __syncthreads();
+    double* mine = S.part + ((size_t)(bar & 1) * QMW_MAXWG + w) * QMW_VALS;
+    if (tid < C) mine[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+    __syncthreads();
+    ++bar;
+    if (tid == 0) {
+      __hip_atomic_fetch_add(S.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned target = S.base + bar * (unsigned)nwg;
+      int it = 0;
+      while (!timed_out &&
+             (int)(__hip_atomic_load(S.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++it > QMW_SPIN) timed_out = 1;   // no later barrier of this launch waits either
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (tid < C) {
+      const double* all = S.part + (size_t)((bar - 1) & 1) * QMW_MAXWG * QMW_VALS + tid;
+      double v[QMW_MAXWG];
+#pragma unroll
+      for (int u = 0; u < QMW_MAXWG; ++u) v[u] = all[(size_t)min(u, nwg - 1) * QMW_VALS];
+      double t = 0;
+#pragma unroll
+      for (int u = 0; u < QMW_MAXWG; ++u)
+        if (u < nwg) t += v[u];
+      tot[tid] = t;
+    }
+    __syncthreads();
+  };
+
+  double xn2 = 0, ar = 0, ai = 0;   // column j's tail norm and alpha, when carried over
+  bool exact = true;                // sum column j's tail norm directly
+  for (int j = 0; j < nb; ++j) {
+    cx<double> xj{0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < QNB; ++k)
+      if (k == j) xj = a[k];
+    if (exact) {
+      const double v1[3] = {rr > j ? xj.re * xj.re + xj.im * xj.im : 0.0, rr == j ? xj.re : 0.0,
+                            rr == j ? xj.im : 0.0};
+      qmw_block_sum<3>(v1, red, big, tid);
+      grid_sum(3);
+      xn2 = tot[0];
+      ar = tot[1];
+      ai = tot[2];
+    }
+    double tr = 0, ti = 0, scr = 0, sci = 0, beta = ar;
+    if (xn2 > 0 || ai != 0) {
+      const double nrm = sqrt(ar * ar + ai * ai + xn2);
+      beta = (ar >= 0) ? -nrm : nrm;
+      tr = (beta - ar) / beta;
+      ti = -ai / beta;
+      const double dr = ar - beta, di = ai, d2 = dr * dr + di * di;
+      scr = dr / d2;
+      sci = -di / d2;
+    }
+    const bool trivial = (tr == 0.0 && ti == 0.0);
+    // this row of column j: beta on the diagonal, the scaled tail below
+    cx<double> vj{0.0, 0.0};
+    if (rr == j) {
+      xj = cx<double>{beta, 0.0};
+      vj = cx<double>{1.0, 0.0};
+    } else if (rr > j) {
+      if (!trivial) xj = cx<double>{xj.re * scr - xj.im * sci, xj.re * sci + xj.im * scr};
+      vj = xj;
+    }
+#pragma unroll
+    for (int k = 0; k < QNB; ++k)
+      if (k == j) a[k] = xj;
+    // w_k (slot k - 1, k > j), z_q (slot q, q < j), and column j + 1's
+    // A, B, C and row-(j + 1) entries of a_{j+1} and v_j (slots 30..37)
+    const int jn = j + 1;
+    {
+      constexpr int NV = 2 * (QNB - 1) + 8;
+      double v2[NV];
+      cx<double> an{0.0, 0.0};
+#pragma unroll
+      for (int sidx = 0; sidx < QNB - 1; ++sidx) {
+        const bool isw = sidx >= j;
+        const cx<double> ak = a[sidx + 1];
+        const cx<double> aq = a[sidx];
+        if (sidx + 1 == jn) an = ak;
+        const cx<double> vq = (rr == sidx) ? cx<double>{1.0, 0.0} : (rr > sidx ? aq : cx<double>{0.0, 0.0});
+        // w: conj(vj) a_k ; z: conj(vq) vj
+        const cx<double> x = isw ? vj : vq, y = isw ? ak : vj;
+        v2[2 * sidx] = x.re * y.re + x.im * y.im;
+        v2[2 * sidx + 1] = x.re * y.im - x.im * y.re;
+      }
+      const bool below = rr > jn, at = rr == jn;
+      v2[30] = below ? an.re * an.re + an.im * an.im : 0.0;
+      v2[31] = below ? an.re * vj.re + an.im * vj.im : 0.0;   // conj(a) v
+      v2[32] = below ? an.re * vj.im - an.im * vj.re : 0.0;
+      v2[33] = below ? vj.re * vj.re + vj.im * vj.im : 0.0;
+      v2[34] = at ? an.re : 0.0;
+      v2[35] = at ? an.im : 0.0;
+      v2[36] = at ? vj.re : 0.0;
+      v2[37] = at ? vj.im : 0.0;
+      qmw_block_sum<NV>(v2, red, big, tid);
+    }
+    grid_sum(2 * (QNB - 1) + 8);
+    // a_k -= conj(tau) w_k v_j for k > j
+    const double ctr = tr, cti = -ti;
+#pragma unroll
+    for (int k = 1; k < QNB; ++k) {
+      if (k > j) {
+        const double wr = tot[2 * (k - 1)], wi = tot[2 * (k - 1) + 1];
+        const double fr = ctr * wr - cti * wi, fi = ctr * wi + cti * wr;
+        a[k].re -= vj.re * fr - vj.im * fi;
+        a[k].im -= vj.re * fi + vj.im * fr;
+      }
+    }
+    // column j + 1's tail norm and alpha from the expansion, unless it may
+    // have cancelled
+    if (jn < nb) {
+      const double wr = tot[2 * j], wi = tot[2 * j + 1];
+      const double cr = ctr * wr - cti * wi, ci = ctr * wi + cti * wr;   // c = conj(tau) w_{j+1}
+      const double A = tot[30], Br = tot[31], Bi = tot[32], Cv = tot[33];
+      const double c2 = cr * cr + ci * ci;
+      const double est = A - 2.0 * (cr * Br - ci * Bi) + c2 * Cv;
+      const double scale = A + 2.0 * sqrt(c2 * (Br * Br + Bi * Bi)) + c2 * Cv;
+      exact = !(est >= 0.1 * scale);
+      xn2 = est;
+      // alpha' = a_{j+1}[j+1] - c v_j[j+1]
+      ar = tot[34] - (cr * tot[36] - ci * tot[37]);
+      ai = tot[35] - (cr * tot[37] + ci * tot[36]);
+    }
+    // column j of T
+    if (tid == 0) Tl[j][j] = cx<double>{tr, ti};
+    if (tid < j) {
+      double sr = 0, si = 0;
+      for (int b = tid; b < j; ++b) {
+        const cx<double> t = Tl[tid][b];
+        const double zr = tot[2 * b], zi = tot[2 * b + 1];
+        sr += t.re * zr - t.im * zi;
+        si += t.re * zi + t.im * zr;
+      }
+      Tl[tid][j] = cx<double>{-(tr * sr - ti * si), -(tr * si + ti * sr)};
+    }
+    if (w == 0 && tid == 0) tau[p0 + j] = cx<T>{(T)tr, (T)ti};
+    __syncthreads();
+  }
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < QNB; ++k)
+      if (k < nb) M[(size_t)(p0 + k) * n + p0 + rr] = cx<T>{(T)a[k].re, (T)a[k].im};
+  }
+  if (w == 0 && tid < QNB * QNB) {
+    const int ta = tid / QNB, tb = tid % QNB;
+    const cx<double> t = (ta < nb && tb < nb && ta <= tb) ? Tl[ta][tb] : cx<double>{0, 0};
+    Tf[tid] = cx<T>{(T)t.re, (T)t.im};
+  }
+  if (tid == 0) {
+    if (timed_out) tau[p0] = cx<T>{(T)NAN, (T)NAN};
+    // barriers not taken (norms carried over) still count, so the counter
+    // ends at base + 2 nb per workgroup as the caller expects; every
+    // workgroup has passed the last barrier here, so no wait is disturbed
+    const unsigned rest = 2u * (unsigned)nb - bar;
+    if (rest) __hip_atomic_fetch_add(S.cnt, rest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 template <typename T>
 void launch_qr_panel(const QrBatch& b, int p0, hipStream_t s) {
   hipLaunchKernelGGL(k_qr_panel<T>, dim3(b.count), dim3(QPT), 0, s, b, p0);
+}
+template <typename T>
+void launch_qr_panel_mw(const QrBatch& b, const QrSyncBatch& sy, int p0, int maxwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_qr_panel_mw<T>, dim3(maxwg, b.count), dim3(QMW_ROWS), 0, s, b, sy, p0);
 }
 template <typename T>
 void launch_qr_apply(const QrApplyBatch& b, int p0, int maxcols, hipStream_t s) {
@@ -582,6 +840,7 @@ void launch_vh_rows(const VkBatch& b, size_t maxel, hipStream_t s) {
 
 #define QINST(T)                                                                  \
   template void launch_qr_panel<T>(const QrBatch&, int, hipStream_t);             \
+  template void launch_qr_panel_mw<T>(const QrBatch&, const QrSyncBatch&, int, int, hipStream_t); \
   template void launch_qr_apply<T>(const QrApplyBatch&, int, int, hipStream_t);   \
   template void launch_lower_from_r<T>(const LowerBatch&, int, int, hipStream_t); \
   template void launch_build_y<T>(const VkBatch&, size_t, hipStream_t);           \

@@ -26,6 +26,7 @@ void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
 void launch_sort_trunc(const TruncBatch&, hipStream_t);
 template <typename T> void launch_qr_panel(const QrBatch&, int, hipStream_t);
+template <typename T> void launch_qr_panel_mw(const QrBatch&, const QrSyncBatch&, int, int, hipStream_t);
 template <typename T> void launch_qr_apply(const QrApplyBatch&, int, int, hipStream_t);
 template <typename T> void launch_lower_from_r(const LowerBatch&, int, int, hipStream_t);
 template <typename T> void launch_build_y(const VkBatch&, size_t, hipStream_t);
@@ -76,6 +77,9 @@ struct Slot {
   int* pchk = nullptr;
   size_t cap_mn = 0, cap_A = 0, cap_V = 0, cap_n = 0, cap_r = 0, cap_Y = 0;
   size_t cap_pairs = 0, cap_gch = 0;
+  unsigned* qcnt = nullptr;   // multi-workgroup QR panel: barrier counter (zeroed once)
+  double* qpart = nullptr;    // ... and partial sums
+  unsigned qbase = 0;         // the counter's value after the launches so far
 };
 
 void dfree(void* p) {
@@ -248,6 +252,12 @@ void ensure_slot(mpo_ctx* h, Slot& s, size_t mn, size_t nA, size_t nV, size_t nn
 
 void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY, size_t nwp, size_t nw2) {
   const size_t e = h->esz;
+  if (!s.qcnt) {
+    s.qpart = (double*)dalloc(2 * QMW_MAXWG * QMW_VALS * sizeof(double));
+    s.qcnt = (unsigned*)dalloc(sizeof(unsigned));
+    hip_check(hipMemset(s.qcnt, 0, sizeof(unsigned)), "QR barrier counter");
+    s.qbase = 0;
+  }
   if (s.cap_r < r) {
     dfree(s.tau);
     dfree(s.Tf);
@@ -476,8 +486,26 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
                             h->slots[p].qw2, s.n, s.r, s.n, c0, c1, s.m};
       if (p0 < s.r) maxtrail = std::max(maxtrail, c1 - c0);
     }
+    // tall panels on several workgroups (counter barriers), short ones on one
+    int maxN = 0;
+    for (int p = 0; p < count; ++p)
+      if (p0 < sh[p].r) maxN = std::max(maxN, sh[p].n - p0);
+    const bool multi = maxN >= QMW_MIN_ROWS;
+    QrSyncBatch sy{};
+    if (multi) {
+      for (int p = 0; p < count; ++p) {
+        Slot& sl = h->slots[p];
+        sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase};
+        if (p0 < sh[p].r) {
+          const unsigned nwg = (unsigned)((sh[p].n - p0 + QMW_ROWS - 1) / QMW_ROWS);
+          const unsigned nb = (unsigned)std::min(QNB, sh[p].r - p0);
+          sl.qbase += 2 * nb * nwg;
+        }
+      }
+    }
     timed(h, MPO_PROF_QR, [&] {
-      launch_qr_panel<T>(qb, p0, st);
+      if (multi) launch_qr_panel_mw<T>(qb, sy, p0, (maxN + QMW_ROWS - 1) / QMW_ROWS, st);
+      else launch_qr_panel<T>(qb, p0, st);
       launch_qr_apply<T>(tr, p0, maxtrail, st);
     });
   }
@@ -743,6 +771,8 @@ void destroy(mpo_ctx* h) {
     dfree(s.pflag);
     dfree(s.bmod);
     dfree(s.pchk);
+    dfree(s.qcnt);
+    dfree(s.qpart);
   }
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);

@@ -343,3 +343,55 @@ def test_full_size_chi1024_update(lib, prec):
     assert sv_err(s_gpu, r.s[:r.k]) <= TOL[prec]
     assert abs(info["discarded"] - r.discarded) <= 1e-4 * r.total
     assert np.max(np.abs(right @ right.conj().T - np.eye(info["k"]))) <= 1e-4
+
+
+def test_fp64_update_on_tall_panels(lib):
+    """chi = 384 on both sides (theta 1536 x 1536): the QR preconditioner's
+    panels of 1024 rows or more run on several workgroups (4 to 6) that meet
+    at counter barriers; FP64 against the oracle."""
+    import bench
+    n, sites, lams, bond = bench.micro_state(384)
+    rng = np.random.default_rng(91)
+    go, gi = bench.haar_su4(rng), bench.haar_su4(rng)
+    m = mo.OracleMPO(n)
+    m.B = [s.copy() for s in sites]
+    m.lam = [l.copy() for l in lams]
+    r = mo.bond_update(m, bond, go, gi, 384, 1e-8, "weight", vectors=False)
+    g = lib.MPO(n, 384, 1e-8, 1, PREC["fp64"])
+    g.load_state(sites, lams)
+    info = g.absorb(bond, go, gi)
+    s_gpu = g.singular_values(bond)
+    right = g.read_site(bond + 1).reshape(info["k"], -1)
+    g.close()
+    assert info["k"] == r.k
+    assert sv_err(s_gpu, r.s[:r.k]) <= TOL["fp64"]
+    assert abs(info["discarded"] - r.discarded) <= 1e-10 * r.total
+    assert np.max(np.abs(right @ right.conj().T - np.eye(info["k"]))) <= 1e-10
+
+
+def test_fp64_rank_deficient_tall_panels(lib):
+    """theta of rank 8 (all bonds chi = 256, the left tensor a rank-8 product,
+    no gate): in the first panel of 1024 rows the later columns are
+    combinations of the first eight, so the carried tail norms cancel and the
+    multi-workgroup panel falls back to exact sums; FP64 against the oracle."""
+    import bench
+    n, sites, lams, bond = bench.micro_state(256)
+    rng = np.random.default_rng(93)
+    cl, cm = sites[bond].shape[0], sites[bond].shape[2]
+    u = rng.standard_normal((cl * 4, 8)) + 1j * rng.standard_normal((cl * 4, 8))
+    v = rng.standard_normal((8, cm)) + 1j * rng.standard_normal((8, cm))
+    b = u @ v
+    sites[bond] = (b / np.linalg.norm(b)).reshape(cl, 4, cm)
+    m = mo.OracleMPO(n)
+    m.B = [x.copy() for x in sites]
+    m.lam = [x.copy() for x in lams]
+    r = mo.bond_update(m, bond, None, None, 256, 1e-12, "rel_sv", vectors=False)
+    g = lib.MPO(n, 256, 1e-12, 0, PREC["fp64"])
+    g.load_state(sites, lams)
+    info = g.absorb(bond, None, None)
+    s_gpu = g.singular_values(bond)
+    right = g.read_site(bond + 1).reshape(info["k"], -1)
+    g.close()
+    assert info["k"] == r.k <= 8
+    assert sv_err(s_gpu, r.s[:r.k]) <= TOL["fp64"]
+    assert np.max(np.abs(right @ right.conj().T - np.eye(info["k"]))) <= 1e-10
