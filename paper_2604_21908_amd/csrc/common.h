@@ -145,7 +145,7 @@ struct QrBatch {
 // chunk order and multiplies by op(T) (w2: QNB x ldp), k_qr_upd subtracts V w2.
 constexpr int QRC1 = 512;
 constexpr int QRC2 = 256;
-// Multi-workgroup panel factorisation: the panel's rows are spread over up to
+// Panel factorisation: the panel's rows are spread over up to
 // QMW_MAXWG workgroups of QMW_ROWS threads (one row each); the workgroups of a
 // problem exchange FP64 partial sums through `part` and meet at barriers on
 // the counter `cnt`, which only ever grows (compared modulo 2^32): a launch
@@ -154,7 +154,6 @@ constexpr int QRC2 = 256;
 constexpr int QMW_ROWS = 256;
 constexpr int QMW_MAXWG = 16;
 constexpr int QMW_VALS = 40;        // doubles per workgroup partial
-constexpr int QMW_MIN_ROWS = 1024;  // shorter panels use the one-workgroup kernel
 struct QrSyncProb {
   unsigned* cnt;
   double* part;    // 2 (alternating by barrier) x QMW_MAXWG x QMW_VALS

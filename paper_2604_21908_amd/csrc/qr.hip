@@ -7,9 +7,11 @@
 // Veselic), and the right singular vectors of theta are V = Q [W; 0] with W
 // the accumulated Jacobi rotations -- no division by singular values.
 //
-//   k_qr_panel   one workgroup factors a QNB-column panel (complex Householder
-//                reflectors, LAPACK's sign convention, left-looking) and builds
-//                the upper-triangular T of the compact WY form; FP64 reductions
+//   k_qr_panel   up to 16 workgroups factor a QNB-column panel (complex
+//                Householder reflectors, LAPACK's sign convention,
+//                right-looking, rows in FP64 registers, FP64 sums across the
+//                workgroups) and build the upper-triangular T of the compact
+//                WY form
 //   k_qr_w1/w2/upd  C <- (I - V op(T) V^dag) C: row-chunked partial products
 //                V^dag C, their FP64 sum times op(T), the rank-QNB update; the
 //                trailing update (op = dag) and the formation of V (op = identity)
@@ -20,294 +22,7 @@
 
 namespace mpo {
 
-// Left-looking factorisation of the QNB-column panel at p0, one workgroup of
-// 512 threads (8 waves) per problem, with the current column held in LDS in
-// FP64 (rows p0..n-1, n - p0 <= 4096).  Column j of the panel:
-//  (1) wave w serves the earlier reflectors q = w and q = w + 8 (q < j):
-//      w_q = v_q^dag x and, for q < j - 1, z_q = v_q^dag v_{j-1}, which
-//      completes column j - 1 of T: T[0:j-1, j-1] = -tau_{j-1} T[0:j-1, 0:j-1] z;
-//      then u = T^dag w and x <- x - V u  (Q^dag = I - V T^dag V^dag);
-//  (2) the tail norm, and thread 0 forms the reflector (LAPACK's complex
-//      Householder: beta = -sign(Re alpha) |x|, tau = (beta - alpha) / beta,
-//      v = [1; x_tail / (alpha - beta)]).
-// The panel's columns come from HBM (the previous launch wrote them), so every
-// loop is unrolled far enough that a thread's loads are in flight together;
-// 512 threads leave room for that in registers.  The last column of T is
-// completed after the loop.
 constexpr int QPN = 4096;   // largest panel height: n <= 4 chi_max
-constexpr int QPT = 512;    // threads of the panel workgroup
-constexpr int QRT = QPN / QPT;
-constexpr int QDU = 8;      // rows per lane whose loads a dot loop keeps in flight
-constexpr int QUG = 1;      // rows per thread updated together
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-template <typename T>
-__global__ __launch_bounds__(QPT) void k_qr_panel(QrBatch qb, int p0) {
-  const int pi = blockIdx.x;
-  if (pi >= qb.count) return;
-  const QrProb P = qb.p[pi];
-  if (p0 >= P.r) return;
-  const int nb = min(QNB, P.r - p0);
-  const int n = P.n;
-  const int N = n - p0;                    // rows of the panel
-  cx<T>* M = (cx<T>*)P.M;
-  cx<T>* tau = (cx<T>*)P.tau;
-  cx<T>* Tf = (cx<T>*)P.Tf + (size_t)(p0 / QNB) * QNB * QNB;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  __shared__ cx<double> xs[QPN];           // the current column
-  __shared__ double red[QPT / 64];
-  __shared__ cx<double> Wd[QNB], Zd[QNB], U[QNB], Tl[QNB][QNB + 1];
-  __shared__ double bc[8];
-
-  // v_q at panel row r (absolute row p0 + r): 1 on its diagonal, the stored
-  // tail below it, 0 above
-  auto vq = [&](int q, int r) -> cx<double> {
-    if (r == q) return cx<double>{1.0, 0.0};
-    if (r < q) return cx<double>{0.0, 0.0};
-    const cx<T> t = M[(size_t)(p0 + q) * n + p0 + r];
-    return cx<double>{(double)t.re, (double)t.im};
-  };
-  // T[0:c, c] = -tau_c T[0:c, 0:c] Zd[0:c]  (threads < c; Tl[c][c] = tau_c is set
-  // when reflector c is formed)
-  auto t_column = [&](int c) {
-    if (tid < c) {
-      const cx<double> tc = Tl[c][c];
-      double sr = 0, si = 0;
-      for (int b = tid; b < c; ++b) {
-        const cx<double> t = Tl[tid][b], z = Zd[b];
-        sr += t.re * z.re - t.im * z.im;
-        si += t.re * z.im + t.im * z.re;
-      }
-      Tl[tid][c] = cx<double>{-(tc.re * sr - tc.im * si), -(tc.re * si + tc.im * sr)};
-    }
-  };
-  // z_q = v_q^dag v_c for q = wv and q = wv + 8 below c (one wave)
-  auto z_dots = [&](int c) {
-    const int qa = wv, qb2 = wv + 8;
-    const bool hb = qb2 < c;
-    const cx<T>* va = M + (size_t)(p0 + qa) * n + p0;
-    const cx<T>* vb = M + (size_t)(p0 + (hb ? qb2 : qa)) * n + p0;
-    const cx<T>* yc = M + (size_t)(p0 + c) * n + p0;
-    double ar = 0, ai = 0, br = 0, bi = 0;
-    if (lane == 0) {     // row c: v_c[c] = 1
-      ar = (double)va[c].re;
-      ai = -(double)va[c].im;
-      if (hb) {
-        br = (double)vb[c].re;
-        bi = -(double)vb[c].im;
-      }
-    }
-    for (int r0 = c + 1; r0 < N; r0 += 64 * QDU) {
-#pragma unroll
-      for (int k = 0; k < QDU; ++k) {
-        const int r = r0 + lane + 64 * k;
-        const int rc = min(r, N - 1);
-        const cx<T> y = yc[rc], v = va[rc], w = vb[rc];
-        const double mk = (r < N) ? 1.0 : 0.0;
-        ar += mk * ((double)v.re * (double)y.re + (double)v.im * (double)y.im);
-        ai += mk * ((double)v.re * (double)y.im - (double)v.im * (double)y.re);
-        br += mk * ((double)w.re * (double)y.re + (double)w.im * (double)y.im);
-        bi += mk * ((double)w.re * (double)y.im - (double)w.im * (double)y.re);
-      }
-    }
-    ar = wave_sum(ar);
-    ai = wave_sum(ai);
-    br = wave_sum(br);
-    bi = wave_sum(bi);
-    if (lane == 0) {
-      Zd[qa] = cx<double>{ar, ai};
-      if (hb) Zd[qb2] = cx<double>{br, bi};
-    }
-  };
-
-  for (int jj = 0; jj < nb; ++jj) {
-    cx<T>* colj = M + (size_t)(p0 + jj) * n + p0;
-    {
-      cx<T> t[QRT];
-#pragma unroll
-      for (int u = 0; u < QRT; ++u) t[u] = colj[min(tid + QPT * u, N - 1)];   // clamped: no branch
-#pragma unroll
-      for (int u = 0; u < QRT; ++u) {
-        const int r = tid + QPT * u;
-        if (r < N) xs[r] = cx<double>{(double)t[u].re, (double)t[u].im};
-      }
-    }
-    __syncthreads();
-    if (jj > 0) {
-      if (wv < jj) {
-        // w_q for q = wv (rows > wv) and q = wv + 8 (rows > wv + 8); the
-        // diagonal terms v_q[q] = 1 are taken by lane 0
-        const int qa = wv, qb2 = wv + 8;
-        const bool hb = qb2 < jj;
-        const cx<T>* va = M + (size_t)(p0 + qa) * n + p0;
-        const cx<T>* vb = M + (size_t)(p0 + (hb ? qb2 : qa)) * n + p0;
-        double ar = 0, ai = 0, br = 0, bi = 0;
-        if (lane == 0) {
-          ar = xs[qa].re;
-          ai = xs[qa].im;
-          if (hb) {
-            br = xs[qb2].re;
-            bi = xs[qb2].im;
-          }
-        }
-        // z_q = v_q^dag v_{j-1} for q < j - 1 rides along: row j - 1 of
-        // v_{j-1} is 1 (lane 0 adds conj(v_q[j-1])), rows >= j are stored
-        const bool za = qa < jj - 1, zb = hb && qb2 < jj - 1;
-        const cx<T>* yc = M + (size_t)(p0 + max(jj - 1, 0)) * n + p0;
-        double zar = 0, zai = 0, zbr = 0, zbi = 0;
-        if (lane == 0 && za) {
-          zar = (double)va[jj - 1].re;
-          zai = -(double)va[jj - 1].im;
-          if (zb) {
-            zbr = (double)vb[jj - 1].re;
-            zbi = -(double)vb[jj - 1].im;
-          }
-        }
-        // blocks of QDU rows per lane: clamped addresses and masks instead of
-        // bounds branches, so a block's loads are in flight together
-        for (int r0 = qa + 1; r0 < N; r0 += 64 * QDU) {
-#pragma unroll
-          for (int k = 0; k < QDU; ++k) {
-            const int r = r0 + lane + 64 * k;
-            const int rc = min(r, N - 1);
-            const cx<double> x = xs[rc];
-            const cx<T> v = va[rc], w = vb[rc], y = yc[rc];
-            const double ma = (r < N) ? 1.0 : 0.0;
-            const double mb = (hb && r > qb2 && r < N) ? 1.0 : 0.0;
-            const double mz = (za && r >= jj && r < N) ? 1.0 : 0.0;
-            const double mzb = (zb && r >= jj && r < N) ? 1.0 : 0.0;
-            ar += ma * ((double)v.re * x.re + (double)v.im * x.im);
-            ai += ma * ((double)v.re * x.im - (double)v.im * x.re);
-            br += mb * ((double)w.re * x.re + (double)w.im * x.im);
-            bi += mb * ((double)w.re * x.im - (double)w.im * x.re);
-            zar += mz * ((double)v.re * (double)y.re + (double)v.im * (double)y.im);
-            zai += mz * ((double)v.re * (double)y.im - (double)v.im * (double)y.re);
-            zbr += mzb * ((double)w.re * (double)y.re + (double)w.im * (double)y.im);
-            zbi += mzb * ((double)w.re * (double)y.im - (double)w.im * (double)y.re);
-          }
-        }
-        ar = wave_sum(ar);
-        ai = wave_sum(ai);
-        br = wave_sum(br);
-        bi = wave_sum(bi);
-        zar = wave_sum(zar);
-        zai = wave_sum(zai);
-        zbr = wave_sum(zbr);
-        zbi = wave_sum(zbi);
-        if (lane == 0) {
-          Wd[qa] = cx<double>{ar, ai};
-          if (hb) Wd[qb2] = cx<double>{br, bi};
-          if (za) Zd[qa] = cx<double>{zar, zai};
-          if (zb) Zd[qb2] = cx<double>{zbr, zbi};
-        }
-      }
-      __syncthreads();
-      t_column(jj - 1);
-      __syncthreads();
-      if (tid < jj) {   // u_a = sum_{b <= a} conj(T[b][a]) w_b
-        double ur = 0, ui = 0;
-        for (int b = 0; b <= tid; ++b) {
-          const cx<double> t = Tl[b][tid], w = Wd[b];
-          ur += t.re * w.re + t.im * w.im;
-          ui += t.re * w.im - t.im * w.re;
-        }
-        U[tid] = cx<double>{ur, ui};
-      }
-      __syncthreads();
-      // every load from a valid address (row and column clamped), the value
-      // masked afterwards, so the loads of a row group are in flight together
-      for (int g = 0; g < QRT; g += QUG) {
-        cx<double> xg[QUG];
-#pragma unroll
-        for (int u = 0; u < QUG; ++u) {
-          const int rc = min(tid + QPT * (g + u), N - 1);
-          cx<double> x = xs[rc];
-#pragma unroll
-          for (int q = 0; q < QNB - 1; ++q) {
-            // the loaded value is always used (times a 0/1 mask), so the
-            // compiler cannot sink the load behind a branch on q < j
-            const int cq = min(q, jj - 1);
-            const cx<T> t = M[(size_t)(p0 + cq) * n + p0 + rc];
-            const double live = (q < jj) ? 1.0 : 0.0;
-            const double below = (rc > q) ? live : 0.0;
-            const double diag = (rc == q) ? live : 0.0;
-            const double vr = below * (double)t.re + diag;
-            const double vi = below * (double)t.im;
-            const cx<double> uq = U[cq];
-            x.re -= vr * uq.re - vi * uq.im;
-            x.im -= vr * uq.im + vi * uq.re;
-          }
-          xg[u] = x;
-        }
-#pragma unroll
-        for (int u = 0; u < QUG; ++u) {
-          const int r = tid + QPT * (g + u);
-          if (r < N) xs[r] = xg[u];
-        }
-      }
-      __syncthreads();
-    }
-    double s = 0;
-    for (int r = jj + 1 + tid; r < N; r += QPT) s += xs[r].re * xs[r].re + xs[r].im * xs[r].im;
-    s = wave_sum(s);
-    if (lane == 0) red[wv] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double xn2 = 0;
-      for (int w = 0; w < QPT / 64; ++w) xn2 += red[w];
-      const double ar = xs[jj].re, ai = xs[jj].im;
-      double tr = 0, ti = 0, scr = 0, sci = 0, beta = ar;
-      if (xn2 > 0 || ai != 0) {
-        const double nrm = sqrt(ar * ar + ai * ai + xn2);
-        beta = (ar >= 0) ? -nrm : nrm;
-        tr = (beta - ar) / beta;
-        ti = -ai / beta;
-        const double dr = ar - beta, di = ai, d2 = dr * dr + di * di;
-        scr = dr / d2;
-        sci = -di / d2;
-      }
-      bc[0] = beta;
-      bc[1] = tr;
-      bc[2] = ti;
-      bc[3] = scr;
-      bc[4] = sci;
-      Tl[jj][jj] = cx<double>{tr, ti};
-      tau[p0 + jj] = cx<T>{(T)tr, (T)ti};
-    }
-    __syncthreads();
-    {
-      const double beta = bc[0], scr = bc[3], sci = bc[4];
-      const bool trivial = (bc[1] == 0.0 && bc[2] == 0.0);
-#pragma unroll
-      for (int u = 0; u < QRT; ++u) {
-        const int r = tid + QPT * u;
-        if (r < N) {
-          cx<double> y = xs[r];
-          if (r == jj) y = cx<double>{beta, 0.0};
-          else if (r > jj && !trivial) y = cx<double>{xs[r].re * scr - xs[r].im * sci, xs[r].re * sci + xs[r].im * scr};
-          colj[r] = cx<T>{(T)y.re, (T)y.im};
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // last column of T: z_q = v_q^dag v_{nb-1}
-  if (nb > 1) {
-    if (wv < nb - 1) z_dots(nb - 1);
-    __syncthreads();
-    t_column(nb - 1);
-    __syncthreads();
-  }
-  if (tid < QNB * QNB) {
-    const int a = tid / QNB, b = tid % QNB;
-    const cx<double> t = (a < nb && b < nb && a <= b) ? Tl[a][b] : cx<double>{0, 0};
-    Tf[tid] = cx<T>{(T)t.re, (T)t.im};
-  }
-}
 
 // V (rows [p0, n), nb columns) at row i, column a of the panel at p0.
 template <typename T>
@@ -548,8 +263,7 @@ __global__ __launch_bounds__(256) void k_vh_rows(VkBatch vb) {
 }
 
 // ---------------------------------------------------------------- launchers
-// Panel factorisation over several workgroups (panels of at least
-// QMW_MIN_ROWS rows).  Workgroup w holds panel rows [256 w, 256 w + 256), one
+// Panel factorisation over several workgroups.  Workgroup w holds panel rows [256 w, 256 w + 256), one
 // per thread, all QNB columns in FP64 registers, and the columns are factored
 // right-looking.  Column j needs the tail norm |x_{>j}|^2 and alpha = x_j
 // (summed over the problem's workgroups; every workgroup then forms the same
@@ -602,7 +316,7 @@ __device__ __forceinline__ void qmw_block_sum(const double (&vals)[C], double (*
 }
 
 template <typename T>
-__global__ __launch_bounds__(QMW_ROWS) void k_qr_panel_mw(QrBatch qb, QrSyncBatch sb, int p0) {
+__global__ __launch_bounds__(QMW_ROWS) void k_qr_panel(QrBatch qb, QrSyncBatch sb, int p0) {
   const int pi = blockIdx.y;
   if (pi >= qb.count) return;
   const QrProb P = qb.p[pi];
@@ -803,12 +517,8 @@ __global__ __launch_bounds__(QMW_ROWS) void k_qr_panel_mw(QrBatch qb, QrSyncBatc
 }
 
 template <typename T>
-void launch_qr_panel(const QrBatch& b, int p0, hipStream_t s) {
-  hipLaunchKernelGGL(k_qr_panel<T>, dim3(b.count), dim3(QPT), 0, s, b, p0);
-}
-template <typename T>
-void launch_qr_panel_mw(const QrBatch& b, const QrSyncBatch& sy, int p0, int maxwg, hipStream_t s) {
-  hipLaunchKernelGGL(k_qr_panel_mw<T>, dim3(maxwg, b.count), dim3(QMW_ROWS), 0, s, b, sy, p0);
+void launch_qr_panel(const QrBatch& b, const QrSyncBatch& sy, int p0, int maxwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_qr_panel<T>, dim3(maxwg, b.count), dim3(QMW_ROWS), 0, s, b, sy, p0);
 }
 template <typename T>
 void launch_qr_apply(const QrApplyBatch& b, int p0, int maxcols, hipStream_t s) {
@@ -839,8 +549,7 @@ void launch_vh_rows(const VkBatch& b, size_t maxel, hipStream_t s) {
 }
 
 #define QINST(T)                                                                  \
-  template void launch_qr_panel<T>(const QrBatch&, int, hipStream_t);             \
-  template void launch_qr_panel_mw<T>(const QrBatch&, const QrSyncBatch&, int, int, hipStream_t); \
+  template void launch_qr_panel<T>(const QrBatch&, const QrSyncBatch&, int, int, hipStream_t); \
   template void launch_qr_apply<T>(const QrApplyBatch&, int, int, hipStream_t);   \
   template void launch_lower_from_r<T>(const LowerBatch&, int, int, hipStream_t); \
   template void launch_build_y<T>(const VkBatch&, size_t, hipStream_t);           \

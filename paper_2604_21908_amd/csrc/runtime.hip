@@ -25,8 +25,7 @@ template <typename T> void launch_ns_corr(const cx<double>*, cx<T>*, int, hipStr
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
 void launch_sort_trunc(const TruncBatch&, hipStream_t);
-template <typename T> void launch_qr_panel(const QrBatch&, int, hipStream_t);
-template <typename T> void launch_qr_panel_mw(const QrBatch&, const QrSyncBatch&, int, int, hipStream_t);
+template <typename T> void launch_qr_panel(const QrBatch&, const QrSyncBatch&, int, int, hipStream_t);
 template <typename T> void launch_qr_apply(const QrApplyBatch&, int, int, hipStream_t);
 template <typename T> void launch_lower_from_r(const LowerBatch&, int, int, hipStream_t);
 template <typename T> void launch_build_y(const VkBatch&, size_t, hipStream_t);
@@ -486,26 +485,21 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
                             h->slots[p].qw2, s.n, s.r, s.n, c0, c1, s.m};
       if (p0 < s.r) maxtrail = std::max(maxtrail, c1 - c0);
     }
-    // tall panels on several workgroups (counter barriers), short ones on one
+    // the panel on ceil(rows / QMW_ROWS) workgroups that meet at counter barriers
     int maxN = 0;
-    for (int p = 0; p < count; ++p)
-      if (p0 < sh[p].r) maxN = std::max(maxN, sh[p].n - p0);
-    const bool multi = maxN >= QMW_MIN_ROWS;
     QrSyncBatch sy{};
-    if (multi) {
-      for (int p = 0; p < count; ++p) {
-        Slot& sl = h->slots[p];
-        sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase};
-        if (p0 < sh[p].r) {
-          const unsigned nwg = (unsigned)((sh[p].n - p0 + QMW_ROWS - 1) / QMW_ROWS);
-          const unsigned nb = (unsigned)std::min(QNB, sh[p].r - p0);
-          sl.qbase += 2 * nb * nwg;
-        }
+    for (int p = 0; p < count; ++p) {
+      Slot& sl = h->slots[p];
+      sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase};
+      if (p0 < sh[p].r) {
+        maxN = std::max(maxN, sh[p].n - p0);
+        const unsigned nwg = (unsigned)((sh[p].n - p0 + QMW_ROWS - 1) / QMW_ROWS);
+        const unsigned nb = (unsigned)std::min(QNB, sh[p].r - p0);
+        sl.qbase += 2 * nb * nwg;
       }
     }
     timed(h, MPO_PROF_QR, [&] {
-      if (multi) launch_qr_panel_mw<T>(qb, sy, p0, (maxN + QMW_ROWS - 1) / QMW_ROWS, st);
-      else launch_qr_panel<T>(qb, p0, st);
+      launch_qr_panel<T>(qb, sy, p0, (maxN + QMW_ROWS - 1) / QMW_ROWS, st);
       launch_qr_apply<T>(tr, p0, maxtrail, st);
     });
   }
