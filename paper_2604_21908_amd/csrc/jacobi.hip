@@ -319,6 +319,7 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
   __shared__ __attribute__((aligned(16))) __bf16 Sh[4][32][72];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int I = wave >> 1, J = wave & 1, g8 = (lane >> 4) * 8;
+  const bool mirror = I == 1 && J == 0;
   const cx<float>* A = (const cx<float>*)P.A;
   double gr[4] = {0, 0, 0, 0}, gi[4] = {0, 0, 0, 0};
   // the next 64-row slab is loaded into registers while this one is multiplied
@@ -346,6 +347,9 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
     __syncthreads();
     if (s0 + 64 < r1) fetch(s0 + 64);
     v4f are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+    // block (1, 0) is the conjugate transpose of block (0, 1): its wave only
+    // stages
+    if (!mirror) {
 #pragma unroll
     for (int kk = 0; kk < 64; kk += 32) {
       const int cx_ = I * 16 + (lane & 15), cy = J * 16 + (lane & 15), k = kk + g8;
@@ -358,6 +362,7 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
       aim = mma3_bf16(xr, yi, aim);
       aim = mma3_bf16(xn, yr, aim);
     }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       gr[r] += (double)are[r];
@@ -366,10 +371,12 @@ __global__ __launch_bounds__(256) void k_jac_gram_bf16(JacBatch jb, int step) {
     __syncthreads();
   }
   cx<double>* out = P.gpart + ((size_t)blockIdx.x * P.ngchunk + blockIdx.y) * 1024;
+  if (mirror) return;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = I * 16 + MF<float>::row(lane, r), j = J * 16 + (lane & 15);
     out[i * 32 + j] = cx<double>{gr[r], gi[r]};
+    if (I != J) out[j * 32 + i] = cx<double>{gr[r], -gi[r]};
   }
 }
 
