@@ -24,13 +24,21 @@ namespace mpo {
 
 constexpr int QPN = 4096;   // largest panel height: n <= 4 chi_max
 
-// V (rows [p0, n), nb columns) at row i, column a of the panel at p0.
+// V (rows [p0, n), nb columns) at row i, column a of the panel at p0; zero
+// unless `ok`.  The load always goes to a valid address (row and column
+// clamped) and the value is selected afterwards, so that a thread's loads
+// are issued together rather than each behind a branch.
 template <typename T>
-__device__ __forceinline__ cx<T> v_entry(const cx<T>* M, int n, int p0, int nb, int i, int a) {
-  if (a >= nb || i >= n) return cx<T>{0, 0};
-  if (i == p0 + a) return cx<T>{1, 0};
-  if (i > p0 + a) return M[(size_t)(p0 + a) * n + i];
-  return cx<T>{0, 0};
+__device__ __forceinline__ cx<T> v_entry(const cx<T>* M, int n, int p0, int nb, int i, int a, bool ok) {
+  const int ac = min(a, nb - 1);
+  const int ic = min(max(i, p0 + ac), n - 1);
+  const cx<T> t = M[(size_t)(p0 + ac) * n + ic];
+  const bool live = ok && a < nb && i < n;
+  // the loaded value is always used (times a 0/1 mask), so the compiler
+  // cannot sink the load behind a branch
+  const T below = (live && i > p0 + a) ? (T)1 : (T)0;
+  const T diag = (live && i == p0 + a) ? (T)1 : (T)0;
+  return cx<T>{below * t.re + diag, below * t.im};
 }
 
 // Partial products V^dag C over the QRC1 rows of chunk blockIdx.y, for the
@@ -60,17 +68,20 @@ __global__ __launch_bounds__(256) void k_qr_w1(QrApplyBatch ab, int p0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   acc_t wre = {0, 0, 0, 0}, wim = {0, 0, 0, 0};
   for (int r0 = rbeg; r0 < rend; r0 += 128) {
+    static_assert((128 * QNB) % 256 == 0 && (128 * QAT) % 256 == 0, "whole staging rounds");
 #pragma unroll
-    for (int e = tid; e < 128 * QNB; e += 256) {
+    for (int j = 0; j < 128 * QNB / 256; ++j) {
+      const int e = tid + 256 * j;
       const int rr = e % 128, a = e / 128, i = r0 + rr;
-      Vs[rr][a] = (i < rend) ? v_entry(M, n, p0, nb, i, a) : cx<T>{0, 0};
+      Vs[rr][a] = v_entry(M, n, p0, nb, i, a, i < rend);
     }
 #pragma unroll
-    for (int e = tid; e < 128 * QAT; e += 256) {
+    for (int j = 0; j < 128 * QAT / 256; ++j) {
+      const int e = tid + 256 * j;
       const int rr = e % 128, c = e / 128, i = r0 + rr;
-      cx<T> v = {0, 0};
-      if (i < rend && c < ncols) v = C[(size_t)(cbeg + c) * P.ldc + i];
-      Cs[rr][c] = v;
+      const cx<T> v = C[(size_t)(cbeg + min(c, ncols - 1)) * P.ldc + min(i, rend - 1)];   // clamped, masked
+      const T mk = (i < rend && c < ncols) ? (T)1 : (T)0;
+      Cs[rr][c] = cx<T>{mk * v.re, mk * v.im};
     }
     __syncthreads();
 #pragma unroll
@@ -169,7 +180,26 @@ __global__ __launch_bounds__(256) void k_qr_upd(QrApplyBatch ab, int p0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
     const int a = tid / QAT, c = tid % QAT;
-    W2[a][c] = (c < ncols) ? ((const cx<T>*)P.w2)[(size_t)a * P.ldp + cbeg + c] : cx<T>{0, 0};
+    const cx<T> w = ((const cx<T>*)P.w2)[(size_t)a * P.ldp + cbeg + min(c, ncols - 1)];   // clamped, masked
+    const T mk = c < ncols ? (T)1 : (T)0;
+    W2[a][c] = cx<T>{mk * w.re, mk * w.im};
+  }
+  // every load of the workgroup first (C may alias M, so loads are not moved
+  // past the stores by the compiler), then the products, then the stores
+  cx<T> cv[4][4], vv[4][QNB / 4];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int i = rbeg + wave * 64 + st * 16 + (lane & 15);
+    const bool valid = i < n && i < rbeg + QRC2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = MF<T>::row(lane, r);
+      const cx<T> v = C[(size_t)(cbeg + min(c, ncols - 1)) * P.ldc + min(i, n - 1)];   // clamped, masked
+      const T mk = (valid && c < ncols) ? (T)1 : (T)0;
+      cv[st][r] = cx<T>{mk * v.re, mk * v.im};
+    }
+#pragma unroll
+    for (int kq = 0; kq < QNB / 4; ++kq) vv[st][kq] = v_entry(M, n, p0, nb, i, 4 * kq + (lane >> 4), valid);
   }
   __syncthreads();
 #pragma unroll
@@ -179,16 +209,13 @@ __global__ __launch_bounds__(256) void k_qr_upd(QrApplyBatch ab, int p0) {
     acc_t cre, cim;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int c = MF<T>::row(lane, r);
-      cx<T> v = {0, 0};
-      if (valid && c < ncols) v = C[(size_t)(cbeg + c) * P.ldc + i];
-      cre[r] = v.re;
-      cim[r] = v.im;
+      cre[r] = cv[st][r].re;
+      cim[r] = cv[st][r].im;
     }
 #pragma unroll
-    for (int k0 = 0; k0 < QNB; k0 += 4) {
-      const int a = k0 + (lane >> 4);
-      const cx<T> v = valid ? v_entry(M, n, p0, nb, i, a) : cx<T>{0, 0};
+    for (int kq = 0; kq < QNB / 4; ++kq) {
+      const int a = 4 * kq + (lane >> 4);
+      const cx<T> v = vv[st][kq];
       const cx<T> w = W2[a][lane & 15];   // A[c][a] = w2[a][c], negated for the subtraction
       cre = MF<T>::mma(-w.re, v.re, cre);
       cre = MF<T>::mma(w.im, v.im, cre);
