@@ -57,40 +57,47 @@ __global__ __launch_bounds__(256) void k_gemm(GemmBatch gb) {
       for (int r = 0; r < 4; ++r) { accr[i][j][r] = 0; acci[i][j][r] = 0; }
   const cx<T>* A = (const cx<T>*)P.A;
   const cx<T>* B = (const cx<T>*)P.B;
+  // The next K-slab of both tiles is loaded into registers while the current
+  // one is multiplied.  Every load goes to a clamped valid address; the value
+  // is masked (multiplied by 0 or 1) only when it is written to LDS, so a
+  // thread's loads stay in flight together instead of each being waited for
+  // behind a bounds branch.  B's two layouts share one address formula.
+  cx<T> an[4], bn[4];
+  const bool bt = P.bmode != 0;                                  // B given as op(W) = conj(W)^T
+  const int ar = tid >> 2, akk = (tid & 3) * 4;                  // A: row, first k
+  const int br0 = bt ? (tid >> 2) : (tid >> 4);                  // B: k row (or n row)
+  const int bc0 = bt ? (tid & 3) * 4 : (tid & 15) * 4;           // B: first n (or k)
+  const int browmax = bt ? P.N - 1 : P.K - 1, bcolmax = bt ? P.K - 1 : P.N - 1;
+  const T bsign = bt ? (T)-1 : (T)1;
+  auto load = [&](int k0) {
+    const cx<T>* arow = A + (size_t)min(m0 + ar, P.M - 1) * P.lda;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) an[u] = arow[min(k0 + akk + u, P.K - 1)];
+    const int brow = (bt ? n0 : k0) + br0, bcol = (bt ? k0 : n0) + bc0;
+    const cx<T>* bp = B + (size_t)min(brow, browmax) * P.ldb;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) bn[u] = bp[min(bcol + u, bcolmax)];
+  };
+  load(0);
   for (int k0 = 0; k0 < P.K; k0 += GK) {
     {
-      const int r = tid >> 2, kk = (tid & 3) * 4;
-      const int gr = m0 + r;
+      const bool arow_ok = m0 + ar < P.M;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int gk = k0 + kk + u;
-        cx<T> v = {0, 0};
-        if (gr < P.M && gk < P.K) v = A[(size_t)gr * P.lda + gk];
-        As[r][kk + u] = v;
+        const T mk = (arow_ok && k0 + akk + u < P.K) ? (T)1 : (T)0;
+        As[ar][akk + u] = cx<T>{mk * an[u].re, mk * an[u].im};
       }
-    }
-    if (P.bmode == 0) {
-      const int r = tid >> 4, c = (tid & 15) * 4;
-      const int gk = k0 + r;
+      const int brow = (bt ? n0 : k0) + br0, bcol = (bt ? k0 : n0) + bc0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int gc = n0 + c + u;
-        cx<T> v = {0, 0};
-        if (gk < P.K && gc < P.N) v = B[(size_t)gk * P.ldb + gc];
-        Bs[r][c + u] = v;
-      }
-    } else {
-      const int r = tid >> 2, kk = (tid & 3) * 4;
-      const int gn = n0 + r;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gk = k0 + kk + u;
-        cx<T> v = {0, 0};
-        if (gn < P.N && gk < P.K) v = B[(size_t)gn * P.ldb + gk];
-        Bs[kk + u][r] = cx<T>{v.re, -v.im};
+        const T mk = (brow <= browmax && bcol + u <= bcolmax) ? (T)1 : (T)0;
+        const cx<T> v{mk * bn[u].re, bsign * mk * bn[u].im};
+        if (bt) Bs[bc0 + u][br0] = v;
+        else Bs[br0][bc0 + u] = v;
       }
     }
     __syncthreads();
+    if (k0 + GK < P.K) load(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       cx<T> a[2], b[2];
