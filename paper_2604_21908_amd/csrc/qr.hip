@@ -362,11 +362,16 @@ __global__ __launch_bounds__(QMW_ROWS) void k_qr_panel(QrBatch qb, QrSyncBatch s
   cx<T>* tau = (cx<T>*)P.tau;
   cx<T>* Tf = (cx<T>*)P.Tf + (size_t)(p0 / QNB) * QNB * QNB;
   cx<double> a[QNB];
+  {
+    // all loads first (clamped addresses), then the masks and conversions
+    cx<T> raw[QNB];
 #pragma unroll
-  for (int k = 0; k < QNB; ++k) {
-    const cx<T> t = M[(size_t)(p0 + min(k, nb - 1)) * n + p0 + rcl];   // clamped, masked
-    const bool use = live && k < nb;
-    a[k] = use ? cx<double>{(double)t.re, (double)t.im} : cx<double>{0.0, 0.0};
+    for (int k = 0; k < QNB; ++k) raw[k] = M[(size_t)(p0 + min(k, nb - 1)) * n + p0 + rcl];
+#pragma unroll
+    for (int k = 0; k < QNB; ++k) {
+      const double mk = (live && k < nb) ? 1.0 : 0.0;
+      a[k] = cx<double>{mk * (double)raw[k].re, mk * (double)raw[k].im};
+    }
   }
   __shared__ double red[QMW_ROWS / 64][QMW_VALS];
   __shared__ double big[QMW_ROWS / 64 * (2 * (QNB - 1) + 8) * QMW_LD];
