@@ -209,6 +209,11 @@ double tol_bf16(const mpo_ctx* h, int m) { return std::max(1e-4, tol_for(h, m));
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// Leading dimension of the Jacobi operand (m rows, column-major): tall
+// operands get 64 entries of padding so that the columns a step reads side by
+// side do not sit at a power-of-two stride.
+int lda_jacobi(int m) { return m >= 1024 ? m + 64 : m; }
+
 void ensure_slot(mpo_ctx* h, Slot& s, size_t mn, size_t nA, size_t nV, size_t nn) {
   const size_t e = h->esz;
   if (s.cap_mn < mn) {
@@ -318,7 +323,7 @@ bool finite_gate(const double* g) {
 }
 
 struct RShape {
-  int m, n, r, rpad;
+  int m, n, r, rpad, lda;
 };
 struct RShapes {
   RShape s[MAXB];
@@ -328,7 +333,7 @@ template <typename S>
 RShapes sh_r(const S* sh, int count) {
   RShapes o{};
   o.count = count;
-  for (int p = 0; p < count; ++p) o.s[p] = RShape{sh[p].m, sh[p].n, sh[p].r, sh[p].rpad};
+  for (int p = 0; p < count; ++p) o.s[p] = RShape{sh[p].m, sh[p].n, sh[p].r, sh[p].rpad, sh[p].lda};
   return o;
 }
 
@@ -387,7 +392,7 @@ void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStrea
     launch_lower_from_r<T>(lw, s.m, s.rpad, st);
     GemmBatch g3{};
     g3.count = 1;
-    g3.p[0] = GemmProb{sl.V, h->lbuf, jb.p[p].A, s.rpad, s.m, s.rpad, s.rpad, s.m, s.m, 0};
+    g3.p[0] = GemmProb{sl.V, h->lbuf, jb.p[p].A, s.rpad, s.m, s.rpad, s.rpad, s.m, s.lda, 0};
     launch_gemm<T>(g3, s.rpad, s.m, st);
   }
 }
@@ -399,7 +404,7 @@ template <typename T>
 mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool commit) {
   hipStream_t st = h->stream;
   struct Shape {
-    int i, chil, chim, chir, m, n, r, rpad, nblk;
+    int i, chil, chim, chir, m, n, r, rpad, nblk, lda;
   };
   Shape sh[MAXB];
   int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0, maxgch = 1;
@@ -416,6 +421,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     s.n = 4 * s.chir;
     s.r = std::min(s.m, s.n);
     s.rpad = round_up(s.r, 2 * JB);
+    s.lda = lda_jacobi(s.m);
     s.nblk = s.rpad / JB;
     maxM = std::max(maxM, s.m);
     maxN = std::max(maxN, s.n);
@@ -425,7 +431,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     maxpairs = std::max(maxpairs, s.nblk / 2);
     maxblk = std::max(maxblk, s.nblk);
     Slot& sl = h->slots[p];
-    ensure_slot(h, sl, (size_t)s.m * s.n, (size_t)s.m * s.rpad, commit ? (size_t)s.rpad * s.rpad : 0,
+    ensure_slot(h, sl, (size_t)s.m * s.n, (size_t)s.lda * s.rpad, commit ? (size_t)s.rpad * s.rpad : 0,
                 (size_t)s.rpad);
     ensure_qr(h, sl, (size_t)s.r, commit ? (size_t)s.n * s.r : 0,
               (size_t)((s.n + QRC1 - 1) / QRC1) * QNB * s.m, (size_t)QNB * s.m);
@@ -508,7 +514,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   lwb.count = count;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
-    lwb.p[p] = LowerProb{h->slots[p].theta0, h->slots[p].A, s.n, s.m, s.r, s.rpad, s.m};
+    lwb.p[p] = LowerProb{h->slots[p].theta0, h->slots[p].A, s.n, s.m, s.r, s.rpad, s.lda};
   }
   timed(h, MPO_PROF_QR, [&] { launch_lower_from_r<T>(lwb, maxM, maxrpad, st); });
 
@@ -518,7 +524,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     const Shape& s = sh[p];
     Slot& sl = h->slots[p];
     jb.p[p] = JacProb{sl.A,      commit ? sl.V : nullptr, h->states + p, sl.norms, (cx<double>*)sl.gpart, sl.dmat,
-                      sl.pflag,  sl.bmod, sl.pchk, tol_for(O(p), s.m), s.m, s.m, s.r, s.rpad, s.nblk,
+                      sl.pflag,  sl.bmod, sl.pchk, tol_for(O(p), s.m), s.m, s.lda, s.r, s.rpad, s.nblk,
                       (int)sl.cap_gch};
   }
   timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
