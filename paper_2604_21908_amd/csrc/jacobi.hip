@@ -109,23 +109,37 @@ __device__ __forceinline__ double rsq_nr2(double x) {
 // t^2 + 2 zeta t - 1 = 0, zeta = (g_qq - g_pp) / (2 |g_pq|); it zeroes the
 // (p, q) entry of J^dag G J.  Only c needs full accuracy: c^2 + |z|^2 = 1
 // holds for whatever tau is used, so tau (which only sets how well the entry
-// is zeroed) comes from once-refined estimates.  Returns false (c = 1, z = 0)
+// is zeroed) comes from cheaper estimates.  Returns false (c = 1, z = 0)
 // when |g_pq| is below tol sqrt(g_pp g_qq).  Branch-free: evaluated for every
 // lane, the identity selected where no rotation applies.
+// FINE: the once-refined estimates for 1 / |g_pq|, sqrt(1 + zeta^2) and the
+// tangent (about 2^-45: the FP64 form, whose tolerance is near FP64 rounding);
+// otherwise the bare hardware estimates (about 2^-23), enough to zero the
+// entry to well below the FP32 and mixed forms' tolerances.  c is fully
+// refined either way.
+template <bool FINE>
+__device__ __forceinline__ double est_rsq(double x) {
+  return FINE ? rsq_nr1(x) : __builtin_amdgcn_rsq(x);
+}
+template <bool FINE>
+__device__ __forceinline__ double est_rcp(double x) {
+  return FINE ? rcp_nr1(x) : __builtin_amdgcn_rcp(x);
+}
+template <bool FINE>
 __device__ __forceinline__ bool jac_angle(double app, double aqq, cx<double> g, double tol, double& c, double& zr,
                                           double& zi) {
   const double g2 = g.re * g.re + g.im * g.im;
   const bool rot = (g2 > 0.0) & (g2 > tol * tol * fmax(app * aqq, 0.0));
   const double g2s = rot ? g2 : 1.0;
-  const double rm = rsq_nr1(g2s);                      // ~ 1 / |g_pq|
+  const double rm = est_rsq<FINE>(g2s);                // ~ 1 / |g_pq|
   const double zeta = 0.5 * (aqq - app) * rm;
   const double az = fabs(zeta);
   // 1 / (|zeta| + sqrt(1 + zeta^2)); for |zeta| > 2^60 the root is |zeta| to
   // working precision and zeta^2 could overflow
   const bool big = az > 0x1p60;
   const double z1 = big ? 1.0 : 1.0 + zeta * zeta;
-  const double h = z1 * rsq_nr1(z1);
-  const double ta = rcp_nr1(big ? az : az + h) * (big ? 0.5 : 1.0);
+  const double h = z1 * est_rsq<FINE>(z1);
+  const double ta = est_rcp<FINE>(big ? az : az + h) * (big ? 0.5 : 1.0);
   const double t = zeta >= 0.0 ? ta : -ta;
   // the phase g_pq / |g_pq| first (|g_pq| may be near the underflow limit,
   // its reciprocal near overflow), then tau = t e and |tau|^2 = t^2 |e|^2
@@ -256,7 +270,7 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
       const double app = at(gc, C.x + C.z).re, aqq = at(gc, C.y + C.w).re;
       const cx<double> gpq = at(gc, C.x + C.w);
       double cc, zcr, zci;
-      if (jac_angle(app, aqq, gpq, tol, cc, zcr, zci)) anyrot = isw + 1;
+      if (jac_angle<sizeof(T) == 8>(app, aqq, gpq, tol, cc, zcr, zci)) anyrot = isw + 1;
       const double cr = __shfl(cc, src, 64), zrr = __shfl(zcr, src, 64), zri = __shfl(zci, src, 64);
       // H = G_block J_c; x * (-conj(zc)) = -(x.re zcr + x.im zci) + i (x.re zci - x.im zcr)
       const double h00r = a00.re * cc - (a01.re * zcr + a01.im * zci);
