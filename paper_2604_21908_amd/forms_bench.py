@@ -41,11 +41,17 @@ def _progress(tag):
     return cb
 
 
+class _TimeLimit(Exception):
+    pass
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("form", choices=["batch", "serve", "peak"])
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--chi", type=int, default=256)
+    ap.add_argument("--time-limit", type=float, default=0.0,
+                    help="peak: stop a precision's run after this many seconds and report how far it got")
     ap.add_argument("--precisions", default="fp32,mixed")
     ap.add_argument("--count", type=int, default=16)
     ap.add_argument("--tau", type=float, default=1e5)
@@ -66,19 +72,52 @@ def main(argv=None):
                                                  tau=tau, unswap="parallel"))
             steps = [0]
             t0 = _t.perf_counter()
+            last = [t0]
             orig = c.absorb_step
 
             def step(orig=orig):
+                if a.time_limit and _t.perf_counter() - t0 > a.time_limit:
+                    raise _TimeLimit()
                 orig()
                 steps[0] += 1
-                if steps[0] % 5 == 0:
-                    print(f"  [{prec}] step {steps[0]}, max chi {max(c.m.bond_dims())}, "
-                          f"t = {_t.perf_counter() - t0:.1f} s", flush=True)
+                now = _t.perf_counter()
+                if steps[0] % 5 == 0 or now - last[0] > 20:
+                    last[0] = now
+                    print(f"  [{prec}] step {steps[0]} of {total_steps}, max chi {max(c.m.bond_dims())}, "
+                          f"updates {c.bond_updates}, t = {now - t0:.1f} s", flush=True)
+            total_steps = max(len(c.c_left), len(c.c_right))
             c.absorb_step = step
-            res = c.run()
+
+            def unswap_by_cycle(c=c, prec=prec):
+                # one parallel cycle per call until a cycle accepts nothing:
+                # with strict acceptance a cycle reduces iff it accepts, so
+                # this is the library's own loop, with a line per cycle
+                before = c.m.total_elements()
+                log = []
+                for it in range(c.cfg.max_unswap_iters):
+                    got = c.m.unswap(c.cfg.unswap, c.cfg.relaxed, 1)
+                    log += got
+                    print(f"  [{prec}] unswap cycle {it + 1}: {len(got)} accepted, "
+                          f"size {c.m.total_elements()}, t = {_t.perf_counter() - t0:.1f} s", flush=True)
+                    if not got:
+                        break
+                c.record_unswap(log, before)
+                return log
+            if c.cfg.unswap == "parallel" and not c.cfg.relaxed:
+                c.unswap = unswap_by_cycle
+            try:
+                res = c.run()
+            except _TimeLimit:
+                ks = [x["k"] for x in c.trace if "k" in x]
+                out["runs"].append({"precision": prec, "finished": False, "seconds": round(_t.perf_counter() - t0, 3),
+                                    "absorption_steps": steps[0], "of_steps": total_steps,
+                                    "bond_updates": c.bond_updates, "max_chi": max(ks) if ks else 1})
+                c.close()
+                print(json.dumps(out["runs"][-1]), flush=True)
+                continue
             c.close()
             ks = [x["k"] for x in res.trace if "k" in x]
-            out["runs"].append({"precision": prec, "time_to_peak_s": round(res.seconds, 3),
+            out["runs"].append({"precision": prec, "finished": True, "time_to_peak_s": round(res.seconds, 3),
                                 "bond_updates": res.bond_updates, "max_chi": max(ks),
                                 "peak_ok": bool((res.bits == circ.peak).all()), "p_peak": res.prob,
                                 "updates_per_s": round(res.bond_updates / res.seconds, 1)})
