@@ -24,6 +24,8 @@ import json
 import sys
 import time
 
+import numpy as np
+
 from . import batch as bt
 from . import circuitgen as cg
 from . import driver as dr
@@ -45,6 +47,42 @@ class _TimeLimit(Exception):
     pass
 
 
+class _Checkpoint(Exception):
+    pass
+
+
+def _save_state(path, c, steps, seconds, max_k):
+    """The contraction after a complete unswapping stage: every site tensor
+    and bond vector as stored, both wire layouts, the absorption steps done
+    and the bookkeeping of the time-to-peak (numpy .npz, no pickles)."""
+    n = c.n
+    # the MPO's own precision (complex64 values round-trip exactly)
+    dt = np.complex128 if c.cfg.precision == "fp64" else np.complex64
+    arrs = {f"site{i}": c.m.read_site(i).astype(dt) for i in range(n)}
+    arrs.update({f"lam{b}": c.m.singular_values(b) for b in range(n - 1)})
+    arrs.update(out_site_of=c.out_w.site_of, out_logical_at=c.out_w.logical_at, in_site_of=c.in_w.site_of,
+                in_logical_at=c.in_w.logical_at, steps=np.array(steps), seconds=np.array(seconds),
+                max_k=np.array(max_k), bond_updates=np.array(c.bond_updates))
+    np.savez(path, **arrs)
+
+
+def _load_state(path, c):
+    """Inverse of _save_state on a fresh Contractor of the same circuit and
+    configuration; returns (steps, seconds, max_k)."""
+    z = np.load(path)
+    steps = int(z["steps"])
+    for _ in range(steps):                 # the layers those steps absorbed, innermost first
+        if c.c_left:
+            c.c_left.pop(0)
+        if c.c_right:
+            c.c_right.pop(0)
+    c.out_w.site_of, c.out_w.logical_at = z["out_site_of"].copy(), z["out_logical_at"].copy()
+    c.in_w.site_of, c.in_w.logical_at = z["in_site_of"].copy(), z["in_logical_at"].copy()
+    c.m.load_state([z[f"site{i}"] for i in range(c.n)], [z[f"lam{b}"] for b in range(c.n - 1)])
+    c.bond_updates = int(z["bond_updates"])
+    return steps, float(z["seconds"]), int(z["max_k"])
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("form", choices=["batch", "serve", "peak"])
@@ -52,6 +90,13 @@ def main(argv=None):
     ap.add_argument("--chi", type=int, default=256)
     ap.add_argument("--time-limit", type=float, default=0.0,
                     help="peak: stop a precision's run after this many seconds and report how far it got")
+    ap.add_argument("--checkpoint-after", type=float, default=0.0,
+                    help="peak: after the first unswapping stage that ends past this many seconds, save the "
+                         "contraction's state to --state and stop (one precision)")
+    ap.add_argument("--checkpoint-max-elements", type=float, default=4e6,
+                    help="peak: checkpoint only at a stage whose MPO holds at most this many elements")
+    ap.add_argument("--state", default="", help="peak: checkpoint file (.npz)")
+    ap.add_argument("--resume", action="store_true", help="peak: continue from --state")
     ap.add_argument("--precisions", default="fp32,mixed")
     ap.add_argument("--count", type=int, default=16)
     ap.add_argument("--tau", type=float, default=1e5)
@@ -71,6 +116,9 @@ def main(argv=None):
             c = dr.Contractor(circ, dr.RunConfig(chi_max=a.chi, cutoff=1e-8, cutoff_mode="weight", precision=prec,
                                                  tau=tau, unswap="parallel"))
             steps = [0]
+            done_s, max_k0 = 0.0, 1
+            if a.resume:
+                steps[0], done_s, max_k0 = _load_state(a.state, c)
             t0 = _t.perf_counter()
             last = [t0]
             orig = c.absorb_step
@@ -84,8 +132,8 @@ def main(argv=None):
                 if steps[0] % 5 == 0 or now - last[0] > 20:
                     last[0] = now
                     print(f"  [{prec}] step {steps[0]} of {total_steps}, max chi {max(c.m.bond_dims())}, "
-                          f"updates {c.bond_updates}, t = {now - t0:.1f} s", flush=True)
-            total_steps = max(len(c.c_left), len(c.c_right))
+                          f"updates {c.bond_updates}, t = {done_s + now - t0:.1f} s", flush=True)
+            total_steps = steps[0] + max(len(c.c_left), len(c.c_right))
             c.absorb_step = step
 
             def unswap_by_cycle(c=c, prec=prec):
@@ -98,15 +146,29 @@ def main(argv=None):
                     got = c.m.unswap(c.cfg.unswap, c.cfg.relaxed, 1)
                     log += got
                     print(f"  [{prec}] unswap cycle {it + 1}: {len(got)} accepted, "
-                          f"size {c.m.total_elements()}, t = {_t.perf_counter() - t0:.1f} s", flush=True)
+                          f"size {c.m.total_elements()}, t = {done_s + _t.perf_counter() - t0:.1f} s", flush=True)
                     if not got:
                         break
                 c.record_unswap(log, before)
+                elapsed = done_s + _t.perf_counter() - t0
+                if (a.checkpoint_after and elapsed > a.checkpoint_after and (c.c_left or c.c_right)
+                        and c.m.total_elements() <= a.checkpoint_max_elements):
+                    ks = [x["k"] for x in c.trace if "k" in x]
+                    _save_state(a.state, c, steps[0], elapsed, max([max_k0] + ks))
+                    raise _Checkpoint()
                 return log
             if c.cfg.unswap == "parallel" and not c.cfg.relaxed:
                 c.unswap = unswap_by_cycle
             try:
                 res = c.run()
+            except _Checkpoint:
+                z = np.load(a.state)
+                out["runs"].append({"precision": prec, "checkpoint": a.state, "seconds": round(float(z["seconds"]), 3),
+                                    "absorption_steps": int(z["steps"]), "of_steps": total_steps,
+                                    "bond_updates": int(z["bond_updates"]), "max_chi": int(z["max_k"])})
+                c.close()
+                print(json.dumps(out["runs"][-1]), flush=True)
+                continue
             except _TimeLimit:
                 ks = [x["k"] for x in c.trace if "k" in x]
                 out["runs"].append({"precision": prec, "finished": False, "seconds": round(_t.perf_counter() - t0, 3),
@@ -117,10 +179,12 @@ def main(argv=None):
                 continue
             c.close()
             ks = [x["k"] for x in res.trace if "k" in x]
-            out["runs"].append({"precision": prec, "finished": True, "time_to_peak_s": round(res.seconds, 3),
-                                "bond_updates": res.bond_updates, "max_chi": max(ks),
+            secs = done_s + res.seconds
+            out["runs"].append({"precision": prec, "finished": True, "time_to_peak_s": round(secs, 3),
+                                "resumed": bool(a.resume), "bond_updates": res.bond_updates,
+                                "max_chi": max([max_k0] + ks),
                                 "peak_ok": bool((res.bits == circ.peak).all()), "p_peak": res.prob,
-                                "updates_per_s": round(res.bond_updates / res.seconds, 1)})
+                                "updates_per_s": round(res.bond_updates / secs, 1)})
             print(json.dumps(out["runs"][-1]), flush=True)
         print(json.dumps(out), flush=True)
         return

@@ -96,3 +96,40 @@ def test_group_unswap_equals_per_mpo(mods, prec):
             assert np.array_equal(ha.read_site(i), hb.read_site(i))
         ha.close()
         hb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_unswap_one_cycle_per_call_equals_sweep(mods, prec):
+    """With strict acceptance a parallel cycle reduces iff it accepts a swap,
+    so one-cycle calls repeated until a call accepts nothing (how the peak
+    form prints a line per cycle) give the log and tensors of one sweep call."""
+    from oracle import mpo_oracle as mo
+    from paper_2604_21908_amd import mpo as mpolib
+    code = {"fp64": 0, "fp32": 1}[prec]
+    rng = np.random.default_rng(8)
+    n = 8
+    m = mo.OracleMPO(n)
+    for layer in range(3):                     # stacked SWAP layers: several cycles of work
+        for b in range(layer % 2, n - 1, 2):
+            mo.commit(m, mo.bond_update(m, b, mo.SWAP4, mo.SWAP4 if layer == 1 else None, 64, 1e-12, "rel_sv"))
+    b0 = int(rng.integers(0, n - 1))
+    mo.commit(m, mo.bond_update(m, b0, cg.haar_su4(rng), None, 64, 1e-12, "rel_sv"))
+    ha = mpolib.MPO(n, 64, 1e-12, 0, code)
+    hb = mpolib.MPO(n, 64, 1e-12, 0, code)
+    ha.load_state(m.B, m.lam)
+    hb.load_state(m.B, m.lam)
+    whole = ha.unswap("parallel", False, 20)
+    pieces, calls = [], 0
+    for _ in range(20):
+        got = hb.unswap("parallel", False, 1)
+        calls += 1
+        pieces += got
+        if not got:
+            break
+    assert len(whole) > 0
+    assert pieces == whole
+    assert ha.bond_dims() == hb.bond_dims()
+    for i in range(n):
+        assert np.array_equal(ha.read_site(i), hb.read_site(i))
+    ha.close()
+    hb.close()
