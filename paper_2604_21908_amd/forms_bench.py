@@ -93,6 +93,9 @@ def main(argv=None):
     ap.add_argument("--checkpoint-after", type=float, default=0.0,
                     help="peak: after the first unswapping stage that ends past this many seconds, save the "
                          "contraction's state to --state and stop (one precision)")
+    ap.add_argument("--checkpoint-at-step", type=int, default=0,
+                    help="peak: save to --state and stop at the end of the first unswapping stage after this "
+                         "many absorption steps (whatever the time and size)")
     ap.add_argument("--checkpoint-max-elements", type=float, default=4e6,
                     help="peak: checkpoint only at a stage whose MPO holds at most this many elements")
     ap.add_argument("--state", default="", help="peak: checkpoint file (.npz)")
@@ -151,8 +154,10 @@ def main(argv=None):
                         break
                 c.record_unswap(log, before)
                 elapsed = done_s + _t.perf_counter() - t0
-                if (a.checkpoint_after and elapsed > a.checkpoint_after and (c.c_left or c.c_right)
-                        and c.m.total_elements() <= a.checkpoint_max_elements):
+                at_time = (a.checkpoint_after and elapsed > a.checkpoint_after
+                           and c.m.total_elements() <= a.checkpoint_max_elements)
+                at_step = a.checkpoint_at_step and steps[0] >= a.checkpoint_at_step
+                if (at_time or at_step) and (c.c_left or c.c_right):
                     ks = [x["k"] for x in c.trace if "k" in x]
                     _save_state(a.state, c, steps[0], elapsed, max([max_k0] + ks))
                     raise _Checkpoint()
