@@ -8,7 +8,10 @@ MPO state (random right-canonical site tensors, geometric lambda spectra over
 four decades, seed 7) is resident in HBM before timing starts; every step
 absorbs a fresh Haar-random SU(4) pair (G_out, G_in).
 
-Prints one JSON line (see the design doc for the roofline and baseline definitions).
+Prints one JSON line: the rate of the timed updates (`value`), the roofline of
+the dominant kernel class (algorithmic bytes or flops per launch over the
+event-measured launch time, against the MI355X peak, with the HBM traffic the
+counters measured for it) and the CPU oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -254,8 +257,8 @@ def main():
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the path is single-GPU, "
-              f"see DESIGN.md for how it would shard", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the bond update runs on a "
+              f"single GPU and there is no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
     if args.calibrate_copy:
