@@ -32,21 +32,34 @@
  *
  * Streams.  All device work of a handle is enqueued on the HIP stream given at
  * init (NULL = the default stream).  Calls that return host data synchronise
- * that stream.  A handle is not thread-safe; different handles may be used
- * from different threads on different streams.
+ * that stream.  An absorption waits on the stream too, also with
+ * info == NULL: the Jacobi SVD reads its convergence flags back once per sweep
+ * (the sweep count is data dependent and decided on the host), and the kept
+ * rank k, read back before the write-back, sets the shapes of the write-back
+ * launches.  Only the write-back kernels may still be running when an
+ * absorption returns; later work on the stream is ordered after them.  A
+ * handle is not thread-safe; different handles may be used from different
+ * threads on different streams.
  *
  * Errors.  Every call returns an mpo_status_t; no C++ exception crosses the
- * ABI.  On a negative status the MPO is unchanged (all checks and allocations
- * happen before the first write).  mpo_last_error() gives a message.
+ * ABI.  On a negative status of an absorption (or of any call that changes a
+ * single update) the MPO is unchanged: all checks and allocations happen
+ * before the first write, and the device-side failure flags (non-finite
+ * singular values, a QR panel barrier that gave up) are read back before the
+ * write-back.  mpo_unswap_sweep is a sequence of such updates: after a failure
+ * the swaps accepted before it stay applied and are reported in the log.
+ * mpo_last_error() gives a message.
  *
- * Memory.  The handle owns its device memory (hipMalloc); the caller owns
- * every host array passed in.  Site tensors are allocated at init for their
- * largest possible shape, so later calls do not allocate for the MPO itself;
- * SVD workspaces grow on demand and are kept until mpo_free.
+ * Memory.  The handle owns its device memory (hipMalloc, or the alloc/free
+ * hooks of mpo_config_t); the caller owns every host array passed in.  Site
+ * tensors are allocated at init for their largest possible shape, so later
+ * calls do not allocate for the MPO itself; SVD workspaces grow on demand and
+ * are kept until mpo_free.
  */
 #ifndef MPO_H
 #define MPO_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -60,7 +73,7 @@ typedef enum {
   MPO_WARN_NOCONV = 1,   /* result written, but a Jacobi SVD reached its sweep cap */
   MPO_EINVAL = -1,       /* bad argument (range, NULL, inconsistent sizes)        */
   MPO_ENOMEM = -2,       /* device allocation failed                             */
-  MPO_EHIP = -3,         /* HIP runtime error                                    */
+  MPO_EHIP = -3,         /* HIP runtime error, or a device-side wait that gave up */
   MPO_ENUMERIC = -4,     /* NaN/Inf in a gate or in the singular values          */
   MPO_EOVERFLOW = -5     /* log truncated at log_cap (the sweep itself completed) */
 } mpo_status_t;
@@ -72,9 +85,11 @@ typedef enum { MPO_CUT_REL_SV = 0, MPO_CUT_DISCARDED_WEIGHT = 1 } mpo_cutoff_mod
 typedef enum {
   MPO_FP64 = 0,             /* complex128 tensors, FP64 MFMA                          */
   MPO_FP32 = 1,             /* complex64 tensors, FP32 arithmetic                      */
-  MPO_MIXED_SPLITBF16 = 2   /* complex64 tensors, Jacobi rotations as split-BF16 MFMA
-                               products with FP32 accumulation, then an FP64
-                               re-orthogonalisation and an FP32 polish              */
+  MPO_MIXED_SPLITBF16 = 2   /* complex64 tensors, Jacobi Gram matrices and theta's
+                               rotations as split-BF16 MFMA products with FP32
+                               accumulation; updates that keep vectors then
+                               re-orthogonalise the accumulated rotations in FP64
+                               (polar step) and recompute the operand from R   */
 } mpo_precision_t;
 
 typedef struct {
@@ -85,6 +100,17 @@ typedef struct {
   int32_t precision;      /* mpo_precision_t                                    */
   int32_t max_sweeps;     /* Jacobi sweep cap per SVD; 0 = default (30)          */
   double jacobi_tol;      /* off-diagonal tolerance; 0 = default for precision */
+  int64_t tau_elems;      /* Alg. 1 threshold tau on size(M) (App. A.4), read by
+                             mpo_tau_reached; <= 0 = never reached            */
+  /* Device-memory hooks.  When `alloc` is non-NULL every device buffer of the
+   * handle (site tensors, bond vectors, SVD workspaces, temporaries) comes
+   * from alloc(bytes, alloc_ctx) and goes back through free(ptr, alloc_ctx);
+   * alloc returns NULL on failure (the call then fails with MPO_ENOMEM and the
+   * MPO is unchanged).  Buffers must be usable by work on the handle's stream
+   * and 256-byte aligned.  NULL hooks: hipMalloc / hipFree. */
+  void* (*alloc)(size_t bytes, void* alloc_ctx);
+  void (*free)(void* ptr, void* alloc_ctx);
+  void* alloc_ctx;
 } mpo_config_t;
 
 typedef struct {
@@ -135,9 +161,16 @@ mpo_status_t mpo_absorb_batch(mpo_handle_t h, int32_t count, const int32_t* bond
  * Sequential: largest available bond first (ties: lowest index), best of
  * L/R/B by (k, discarded weight, side order).  Parallel: batches in the order
  * both-even, both-odd, left-even, left-odd, right-even, right-odd until a full
- * cycle lowers nothing.  Accepted swaps are written to log[0..log_cap) in
- * order; *n_accepted gets the total count (which may exceed log_cap, then
- * MPO_EOVERFLOW is returned after the sweep completed). */
+ * cycle lowers nothing.  Trials are values-only SVDs; an accepted swap is then
+ * committed with vectors, and the committed rank decides: a commit that does
+ * not lower (relaxed: raises) the bond is undone from a copy of the two sites
+ * and the bond vector, and neither logged nor counted as a reduction (in the
+ * mixed form a trial's rank can differ from the commit's near the cutoff).  A
+ * trial whose inputs (B_b, B_b+1, lambda_b-1) are unchanged since its last
+ * evaluation on the same side reuses that result (bit-identical).  Accepted
+ * swaps are written to log[0..log_cap) in order; *n_accepted gets the total
+ * count (which may exceed log_cap, then MPO_EOVERFLOW is returned after the
+ * sweep completed). */
 mpo_status_t mpo_unswap_sweep(mpo_handle_t h, const mpo_unswap_opts_t* opts, mpo_swap_t* log,
                               int32_t log_cap, int32_t* n_accepted);
 
@@ -167,6 +200,18 @@ mpo_status_t mpo_read_site(mpo_handle_t h, int32_t site, double* out, int64_t ca
 mpo_status_t mpo_load_state(mpo_handle_t h, const int32_t* dims, const double* sites,
                             const double* lams);
 mpo_status_t mpo_sync(mpo_handle_t h);
+/* Alg. 1's test "size(M) >= tau" with tau = cfg.tau_elems: *reached = 1 when
+ * it holds (never when tau_elems <= 0); *size (may be NULL) gets size(M). */
+mpo_status_t mpo_tau_reached(mpo_handle_t h, int32_t* reached, int64_t* size);
+/* One SWAP trial of Sec. II.B.2 at `bond` (side 0 = L, 1 = R, 2 = B): the
+ * values-only truncated SVD that mpo_unswap_sweep decides on; info receives
+ * its k and weights.  The MPO is not changed. */
+mpo_status_t mpo_trial_swap(mpo_handle_t h, int32_t bond, int32_t side, mpo_update_info_t* info);
+/* Counters since init: out[0] committed bond updates, out[1] SWAP-trial SVDs
+ * run, out[2] trials served from the unchanged-input memo, out[3] unswap
+ * commits undone, out[4] device allocations made through the alloc hook.
+ * Up to `cap` entries are written. */
+mpo_status_t mpo_counters(mpo_handle_t h, int64_t* out, int32_t cap);
 
 /* ---- groups: one batch of bond updates across several MPOs -------------- *
  * A group owns workspace and a stream but no MPO.  mpo_group_absorb applies

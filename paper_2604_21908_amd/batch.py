@@ -31,10 +31,12 @@ UNSWAP = object()      # next_step(): the circuit waits for its unswapping stage
 class CircuitTask:
     """Alg. 1 for one circuit as a resumable state machine."""
 
-    def __init__(self, circuit, cfg: dr.RunConfig, tag=None, group_unswap: bool = False):
+    def __init__(self, circuit, cfg: dr.RunConfig, tag=None, group_unswap: bool = False, keep_lams: bool = False):
         self.circuit = circuit
         self.cfg = cfg
         self.tag = tag
+        self.keep_lams = keep_lams
+        self.lams: Optional[List[np.ndarray]] = None
         self.group_unswap = group_unswap and cfg.unswap == "parallel"
         self.c = dr.Contractor(circuit, cfg)
         self.phase_started = False
@@ -60,12 +62,14 @@ class CircuitTask:
                     self.phase_started = False
                 self.result = c.finish()
                 self.t_done = time.perf_counter()
+                if self.keep_lams:
+                    self.lams = c.lambdas()
                 c.close()
                 return None
             if not self.phase_started:
                 self.phase_started = True
                 return c.plan_absorb()
-            if c.m.total_elements() < self.cfg.tau:
+            if not c.m.tau_reached():
                 return c.plan_absorb()
             if self.group_unswap:
                 return UNSWAP
@@ -136,12 +140,14 @@ def run_round(tasks: Sequence[CircuitTask], group: Optional[_mpo.Group], per_upd
     return issued
 
 
-def run_batched(circuits_cfgs, precision: str = "fp32", per_update: bool = False) -> dict:
+def run_batched(circuits_cfgs, precision: str = "fp32", per_update: bool = False, keep_lams: bool = False) -> dict:
     """Contracts (circuit, RunConfig) pairs in lockstep; returns results and
-    aggregate throughput."""
+    aggregate throughput (with keep_lams, also every circuit's final bond
+    vectors, read after its peak readout)."""
     group = None if per_update else _mpo.Group(_mpo.PRECISIONS[precision])
     t0 = time.perf_counter()
-    tasks = [CircuitTask(c, cfg, tag=i, group_unswap=not per_update) for i, (c, cfg) in enumerate(circuits_cfgs)]
+    tasks = [CircuitTask(c, cfg, tag=i, group_unswap=not per_update, keep_lams=keep_lams)
+             for i, (c, cfg) in enumerate(circuits_cfgs)]
     updates = 0
     rounds = 0
     while not all(t.done for t in tasks):
@@ -151,4 +157,4 @@ def run_batched(circuits_cfgs, precision: str = "fp32", per_update: bool = False
     if group is not None:
         group.close()
     return dict(results=[t.result for t in tasks], seconds=secs, bond_updates=updates, rounds=rounds,
-                updates_per_s=updates / secs if secs > 0 else 0.0)
+                updates_per_s=updates / secs if secs > 0 else 0.0, lams=[t.lams for t in tasks])

@@ -158,6 +158,8 @@ struct QrSyncProb {
   unsigned* cnt;
   double* part;    // 2 (alternating by barrier) x QMW_MAXWG x QMW_VALS
   unsigned base;
+  int spin;        // polls before a barrier gives up (0: give up at once)
+  int* fail;       // set to 1 when a barrier gave up (the problem's status word)
 };
 struct QrSyncBatch {
   QrSyncProb p[MAXB];
@@ -210,7 +212,7 @@ struct TruncResult {
   double total;
   double s0;
   int bad;        // non-finite singular value seen
-  int pad;
+  int qr_fail;    // a QR panel barrier gave up: the factorisation is invalid
 };
 struct TruncProb {
   const double* norms;   // ncol_pad column norms

@@ -295,10 +295,21 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(TruncBatch tb) {
   const TruncProb P = tb.p[pi];
   __shared__ double key[4096];
   __shared__ int idx[4096];
+  __shared__ int nonfinite;
   int N2 = 1;
   while (N2 < P.ncol_pad) N2 <<= 1;
+  if (threadIdx.x == 0) nonfinite = 0;
+  __syncthreads();
+  // A non-finite norm is flagged before anything else reads it and enters the
+  // sort as -1 (every comparison with NaN is false, which would break the
+  // sorting network), so the result is an error, never a silent zero.
   for (int i = threadIdx.x; i < N2; i += blockDim.x) {
-    key[i] = (i < P.ncol) ? P.norms[i] : -1.0;
+    double v = (i < P.ncol) ? P.norms[i] : -1.0;
+    if (!isfinite(v)) {
+      nonfinite = 1;
+      v = -1.0;
+    }
+    key[i] = v;
     idx[i] = i;
   }
   __syncthreads();
@@ -369,7 +380,7 @@ __global__ __launch_bounds__(1024) void k_sort_trunc(TruncBatch tb) {
     P.res->discarded = disc;
     P.res->total = total;
     P.res->s0 = s0;
-    P.res->bad = bad || !isfinite(total);
+    P.res->bad = bad || nonfinite || !isfinite(total);
   }
 }
 

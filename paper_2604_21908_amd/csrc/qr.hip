@@ -308,10 +308,11 @@ __global__ __launch_bounds__(256) void k_vh_rows(VkBatch vb) {
 // after its first column).  Sums run per wave, over waves in order, then over workgroups in
 // order, so every workgroup gets the same bits and takes the same decisions.
 // A barrier is a counter every workgroup increments and polls; the poll
-// gives up after QMW_SPIN rounds, and then no later barrier of the launch
-// waits (tau is poisoned with NaN, which the caller reports as a numerical
-// failure), so every wave finishes.
-constexpr int QMW_SPIN = 1 << 20;
+// gives up after `spin` rounds (a launch argument; 0 gives up at once), and
+// then no later barrier of the launch waits, so every wave finishes.  A
+// workgroup that gave up sets the problem's status word, which the host reads
+// with the truncation result and turns into an error before anything of the
+// MPO is written.
 static_assert(QMW_ROWS * QMW_MAXWG >= QPN, "every panel row needs a thread");
 static_assert(2 * (QNB - 1) + 8 <= QMW_VALS && QMW_ROWS / 64 == 4, "partial layout");
 
@@ -378,7 +379,7 @@ __global__ __launch_bounds__(QMW_ROWS) void k_qr_panel(QrBatch qb, QrSyncBatch s
   __shared__ double tot[QMW_VALS];
   __shared__ cx<double> Tl[QNB][QNB + 1];
   __shared__ int timed_out;
-  if (tid == 0) timed_out = 0;
+  if (tid == 0) timed_out = S.spin <= 0 ? 1 : 0;
   unsigned bar = 0;   // barriers passed in this launch (uniform)
   // block partials red[][0:C) -> this workgroup's slot, barrier, sum over
   // workgroups in order -> tot[0:C).  One release (thread 0's add; the
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(QMW_ROWS) void k_qr_panel(QrBatch qb, QrSyncBatch s
       while (!timed_out &&
              (int)(__hip_atomic_load(S.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
         __builtin_amdgcn_s_sleep(1);
-        if (++it > QMW_SPIN) timed_out = 1;   // no later barrier of this launch waits either
+        if (++it > S.spin) timed_out = 1;   // no later barrier of this launch waits either
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(QMW_ROWS) void k_qr_panel(QrBatch qb, QrSyncBatch s
     Tf[tid] = cx<T>{(T)t.re, (T)t.im};
   }
   if (tid == 0) {
-    if (timed_out) tau[p0] = cx<T>{(T)NAN, (T)NAN};
+    if (timed_out) *S.fail = 1;
     // barriers not taken (norms carried over) still count, so the counter
     // ends at base + 2 nb per workgroup as the caller expects; every
     // workgroup has passed the last barrier here, so no wait is disturbed

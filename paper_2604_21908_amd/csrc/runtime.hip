@@ -81,18 +81,6 @@ struct Slot {
   unsigned qbase = 0;         // the counter's value after the launches so far
 };
 
-void dfree(void* p) {
-  if (p) (void)hipFree(p);
-}
-void* dalloc(size_t bytes) {
-  void* p = nullptr;
-  if (bytes == 0) bytes = 16;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    throw NoMem{};
-  }
-  return p;
-}
 
 struct Req {
   int bond;
@@ -150,9 +138,57 @@ struct mpo_ctx {
   size_t cap_ns = 0, cap_l = 0;
   double prof_ms[MPO_PROF_CLASSES] = {0};
   int64_t prof_n[MPO_PROF_CLASSES] = {0};
+  // device allocations made through the caller's hooks
+  int64_t hook_allocs = 0;
+  // spin bound of the QR panel's cross-workgroup barrier (0: give up at once)
+  int qr_spin = 1 << 20;
+  // Content versions: site_ver[i] changes whenever site i (and, for i >= 1,
+  // lambda_{i-1}, which is only written together with site i) is written.
+  // A SWAP trial at bond b reads exactly B_b, B_{b+1} and lambda_{b-1}, so
+  // a trial whose (site_ver[b], site_ver[b+1]) equal those of its last
+  // evaluation on the same side reproduces that result bit for bit.
+  std::vector<uint64_t> site_ver;
+  uint64_t ver_clock = 0;
+  struct TrialMemo {
+    uint64_t v0 = 0, v1 = 0;
+    bool valid = false;
+    Res res;
+  };
+  std::vector<TrialMemo> trial_memo;   // (n - 1) x 3 sides
+  bool trial_reuse = true;
+  // counters (mpo_counters): committed updates, trial SVDs run, trials served
+  // from the memo, unswap commits reverted because they did not lower the bond
+  int64_t n_updates = 0, n_trials = 0, n_trials_reused = 0, n_reverted = 0;
+  // per-commit backups of the two sites and the bond vector of an unswap commit
+  std::vector<void*> bk;
+  std::vector<size_t> bk_cap;
 };
 
 namespace {
+
+// Device memory of a handle: through the caller's hooks when mpo_config_t
+// provides them (e.g. PyTorch's caching allocator), else hipMalloc / hipFree.
+void dfree(mpo_ctx* h, void* p) {
+  if (!p) return;
+  if (h->cfg.free) h->cfg.free(p, h->cfg.alloc_ctx);
+  else (void)hipFree(p);
+}
+void* dalloc(mpo_ctx* h, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  bytes = (bytes + 255) / 256 * 256;
+  if (h->cfg.alloc) {
+    p = h->cfg.alloc(bytes, h->cfg.alloc_ctx);
+    if (!p) throw NoMem{};
+    h->hook_allocs += 1;
+    return p;
+  }
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    throw NoMem{};
+  }
+  return p;
+}
 
 mpo_status_t fail(mpo_ctx* h, mpo_status_t st, const std::string& msg) {
   if (h) h->err = msg;
@@ -217,39 +253,39 @@ int lda_jacobi(int m) { return m >= 1024 ? m + 64 : m; }
 void ensure_slot(mpo_ctx* h, Slot& s, size_t mn, size_t nA, size_t nV, size_t nn) {
   const size_t e = h->esz;
   if (s.cap_mn < mn) {
-    dfree(s.theta0);
-    dfree(s.thetan);
+    dfree(h, s.theta0);
+    dfree(h, s.thetan);
     s.theta0 = s.thetan = nullptr;
     s.cap_mn = 0;
-    s.theta0 = dalloc(mn * e);
-    s.thetan = dalloc(mn * e);
+    s.theta0 = dalloc(h, mn * e);
+    s.thetan = dalloc(h, mn * e);
     s.cap_mn = mn;
   }
   if (s.cap_A < nA) {
-    dfree(s.A);
+    dfree(h, s.A);
     s.A = nullptr;
     s.cap_A = 0;
-    s.A = dalloc(nA * e);
+    s.A = dalloc(h, nA * e);
     s.cap_A = nA;
   }
   if (nV && s.cap_V < nV) {
-    dfree(s.V);
+    dfree(h, s.V);
     s.V = nullptr;
     s.cap_V = 0;
-    s.V = dalloc(nV * e);
+    s.V = dalloc(h, nV * e);
     s.cap_V = nV;
   }
   if (s.cap_n < nn) {
-    dfree(s.norms);
-    dfree(s.s_sorted);
-    dfree(s.perm);
+    dfree(h, s.norms);
+    dfree(h, s.s_sorted);
+    dfree(h, s.perm);
     s.norms = nullptr;
     s.s_sorted = nullptr;
     s.perm = nullptr;
     s.cap_n = 0;
-    s.norms = (double*)dalloc(nn * sizeof(double));
-    s.s_sorted = (double*)dalloc(nn * sizeof(double));
-    s.perm = (int*)dalloc(nn * sizeof(int));
+    s.norms = (double*)dalloc(h, nn * sizeof(double));
+    s.s_sorted = (double*)dalloc(h, nn * sizeof(double));
+    s.perm = (int*)dalloc(h, nn * sizeof(int));
     s.cap_n = nn;
   }
 }
@@ -257,39 +293,39 @@ void ensure_slot(mpo_ctx* h, Slot& s, size_t mn, size_t nA, size_t nV, size_t nn
 void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY, size_t nwp, size_t nw2) {
   const size_t e = h->esz;
   if (!s.qcnt) {
-    s.qpart = (double*)dalloc(2 * QMW_MAXWG * QMW_VALS * sizeof(double));
-    s.qcnt = (unsigned*)dalloc(sizeof(unsigned));
+    s.qpart = (double*)dalloc(h, 2 * QMW_MAXWG * QMW_VALS * sizeof(double));
+    s.qcnt = (unsigned*)dalloc(h, sizeof(unsigned));
     hip_check(hipMemset(s.qcnt, 0, sizeof(unsigned)), "QR barrier counter");
     s.qbase = 0;
   }
   if (s.cap_r < r) {
-    dfree(s.tau);
-    dfree(s.Tf);
+    dfree(h, s.tau);
+    dfree(h, s.Tf);
     s.tau = s.Tf = nullptr;
     s.cap_r = 0;
-    s.tau = dalloc(r * e);
-    s.Tf = dalloc(((r + QNB - 1) / QNB) * QNB * QNB * e);
+    s.tau = dalloc(h, r * e);
+    s.Tf = dalloc(h, ((r + QNB - 1) / QNB) * QNB * QNB * e);
     s.cap_r = r;
   }
   if (s.cap_qwp < nwp) {
-    dfree(s.qwp);
+    dfree(h, s.qwp);
     s.qwp = nullptr;
     s.cap_qwp = 0;
-    s.qwp = dalloc(nwp * sizeof(cx<double>));
+    s.qwp = dalloc(h, nwp * sizeof(cx<double>));
     s.cap_qwp = nwp;
   }
   if (s.cap_qw2 < nw2) {
-    dfree(s.qw2);
+    dfree(h, s.qw2);
     s.qw2 = nullptr;
     s.cap_qw2 = 0;
-    s.qw2 = dalloc(nw2 * e);
+    s.qw2 = dalloc(h, nw2 * e);
     s.cap_qw2 = nw2;
   }
   if (nY && s.cap_Y < nY) {
-    dfree(s.Y);
+    dfree(h, s.Y);
     s.Y = nullptr;
     s.cap_Y = 0;
-    s.Y = dalloc(nY * e);
+    s.Y = dalloc(h, nY * e);
     s.cap_Y = nY;
   }
 }
@@ -297,19 +333,19 @@ void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY, size_t nwp, size_t nw2)
 void ensure_jac(mpo_ctx* h, Slot& s, size_t pairs, size_t gch) {
   if (s.cap_pairs < pairs || s.cap_gch < gch) {
     const size_t np = std::max(pairs, s.cap_pairs), ng = std::max(gch, s.cap_gch);
-    dfree(s.gpart);
-    dfree(s.dmat);
-    dfree(s.pflag);
-    dfree(s.bmod);
-    dfree(s.pchk);
+    dfree(h, s.gpart);
+    dfree(h, s.dmat);
+    dfree(h, s.pflag);
+    dfree(h, s.bmod);
+    dfree(h, s.pchk);
     s.gpart = s.dmat = nullptr;
     s.pflag = s.bmod = s.pchk = nullptr;
     s.cap_pairs = s.cap_gch = 0;
-    s.gpart = dalloc(np * ng * 1024 * sizeof(cx<double>));
-    s.dmat = dalloc(np * 1024 * h->esz);
-    s.pflag = (int*)dalloc(np * sizeof(int));
-    s.bmod = (int*)dalloc(2 * np * sizeof(int));
-    s.pchk = (int*)dalloc(4 * np * np * sizeof(int));
+    s.gpart = dalloc(h, np * ng * 1024 * sizeof(cx<double>));
+    s.dmat = dalloc(h, np * 1024 * h->esz);
+    s.pflag = (int*)dalloc(h, np * sizeof(int));
+    s.bmod = (int*)dalloc(h, 2 * np * sizeof(int));
+    s.pchk = (int*)dalloc(h, 4 * np * np * sizeof(int));
     s.cap_pairs = np;
     s.cap_gch = ng;
   }
@@ -352,22 +388,22 @@ void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStrea
     const RShape& s = rs.s[p];
     const size_t nn = (size_t)s.rpad * s.rpad;
     if (h->cap_ns < nn) {
-      dfree(h->ns_x);
-      dfree(h->ns_s);
-      dfree(h->ns_y);
+      dfree(h, h->ns_x);
+      dfree(h, h->ns_s);
+      dfree(h, h->ns_y);
       h->ns_x = h->ns_s = h->ns_y = nullptr;
       h->cap_ns = 0;
-      h->ns_x = dalloc(nn * sizeof(cx<double>));
-      h->ns_s = dalloc(nn * sizeof(cx<double>));
-      h->ns_y = dalloc(2 * nn * h->esz);   // E and the new W, working precision
+      h->ns_x = dalloc(h, nn * sizeof(cx<double>));
+      h->ns_s = dalloc(h, nn * sizeof(cx<double>));
+      h->ns_y = dalloc(h, 2 * nn * h->esz);   // E and the new W, working precision
       h->cap_ns = nn;
     }
     const size_t nl = (size_t)s.m * s.rpad;
     if (h->cap_l < nl) {
-      dfree(h->lbuf);
+      dfree(h, h->lbuf);
       h->lbuf = nullptr;
       h->cap_l = 0;
-      h->lbuf = dalloc(nl * h->esz);
+      h->lbuf = dalloc(h, nl * h->esz);
       h->cap_l = nl;
     }
     Slot& sl = h->slots[p];
@@ -451,6 +487,8 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   }
   hip_check(hipMemcpyAsync(h->d_gates, h->h_gates, (size_t)count * 64 * sizeof(double), hipMemcpyHostToDevice, st),
             "gate upload");
+  // per-problem status words (the QR barrier's failure flag) start clear
+  hip_check(hipMemsetAsync(h->results, 0, (size_t)count * sizeof(TruncResult), st), "status clear");
 
   // theta0 = B_i B_{i+1}
   GemmBatch gb{};
@@ -496,7 +534,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     QrSyncBatch sy{};
     for (int p = 0; p < count; ++p) {
       Slot& sl = h->slots[p];
-      sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase};
+      sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase, h->qr_spin, &h->results[p].qr_fail};
       if (p0 < sh[p].r) {
         maxN = std::max(maxN, sh[p].n - p0);
         const unsigned nwg = (unsigned)((sh[p].n - p0 + QMW_ROWS - 1) / QMW_ROWS);
@@ -586,8 +624,9 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
             "result readback");
   hip_check(hipStreamSynchronize(st), "result sync");
   drain_events(h);
-  bool anybad = false;
+  bool anybad = false, qrfail = false;
   for (int p = 0; p < count; ++p) {
+    qrfail |= h->h_results[p].qr_fail != 0;
     out[p].k = h->h_results[p].k;
     out[p].disc = h->h_results[p].discarded;
     out[p].total = h->h_results[p].total;
@@ -597,6 +636,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     out[p].noconv = h->h_states[p].active != 0;
     anybad |= out[p].bad;
   }
+  if (qrfail) return fail(h, MPO_EHIP, "QR panel barrier gave up waiting (factorisation invalid)");
   if (anybad) return fail(h, MPO_ENUMERIC, "non-finite singular values");
   if (!commit) return MPO_OK;
 
@@ -626,7 +666,13 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     timed(h, MPO_PROF_WRITEBACK, [&] { launch_qr_apply<T>(qa, p0, maxk, st); });
   timed(h, MPO_PROF_WRITEBACK, [&] { launch_vh_rows<T>(vb, maxel, st); });
   timed(h, MPO_PROF_WRITEBACK_GEMM, [&] { launch_gemm<T>(lb, maxM, maxk, st); });
-  for (int p = 0; p < count; ++p) O(p)->chi[sh[p].i + 1] = out[p].k;
+  for (int p = 0; p < count; ++p) {
+    mpo_ctx* o = O(p);
+    o->chi[sh[p].i + 1] = out[p].k;
+    o->site_ver[sh[p].i] = ++o->ver_clock;
+    o->site_ver[sh[p].i + 1] = ++o->ver_clock;
+    o->n_updates += 1;
+  }
   return MPO_OK;
 }
 
@@ -668,6 +714,240 @@ Req swap_req(int bond, int side) {
   return Req{bond, (side == 0 || side == 2) ? SWAP_G : nullptr, (side == 1 || side == 2) ? SWAP_G : nullptr, nullptr};
 }
 
+// One SWAP trial: the values-only update of a bond with SWAP on the given
+// side(s) (Sec. II.B.2).  `owner` is the MPO it reads.
+struct Trial {
+  mpo_ctx* owner;
+  int bond, side;
+};
+
+// Runs the trials through `x` (values only, nothing of any MPO is written).
+// A trial whose inputs B_b, B_{b+1}, lambda_{b-1} have the same versions as at
+// its last evaluation on the same side takes that evaluation's result: the
+// kernels are deterministic, so re-running it would give the same bits.
+mpo_status_t run_trials(mpo_ctx* x, const std::vector<Trial>& trials, std::vector<Res>& res) {
+  res.assign(trials.size(), Res{});
+  std::vector<Req> todo;
+  std::vector<size_t> where;
+  for (size_t t = 0; t < trials.size(); ++t) {
+    const Trial& q = trials[t];
+    mpo_ctx* o = q.owner;
+    const auto& m = o->trial_memo[(size_t)q.bond * 3 + q.side];
+    if (o->trial_reuse && m.valid && m.v0 == o->site_ver[q.bond] && m.v1 == o->site_ver[q.bond + 1]) {
+      res[t] = m.res;
+      o->n_trials_reused += 1;
+      continue;
+    }
+    Req r = swap_req(q.bond, q.side);
+    r.owner = o;
+    todo.push_back(r);
+    where.push_back(t);
+  }
+  if (todo.empty()) return MPO_OK;
+  std::vector<Res> got;
+  mpo_status_t st = updates(x, todo, got, false);
+  if (st != MPO_OK) return st;
+  for (size_t j = 0; j < todo.size(); ++j) {
+    const Trial& q = trials[where[j]];
+    mpo_ctx* o = q.owner;
+    auto& m = o->trial_memo[(size_t)q.bond * 3 + q.side];
+    m.v0 = o->site_ver[q.bond];
+    m.v1 = o->site_ver[q.bond + 1];
+    m.valid = true;
+    m.res = got[j];
+    o->n_trials += 1;
+    res[where[j]] = got[j];
+  }
+  return MPO_OK;
+}
+
+void ensure_backup(mpo_ctx* x, size_t slot, size_t bytes) {
+  if (x->bk.size() <= slot) {
+    x->bk.resize(slot + 1, nullptr);
+    x->bk_cap.resize(slot + 1, 0);
+  }
+  if (x->bk_cap[slot] < bytes) {
+    dfree(x, x->bk[slot]);
+    x->bk[slot] = nullptr;
+    x->bk_cap[slot] = 0;
+    x->bk[slot] = dalloc(x, bytes);
+    x->bk_cap[slot] = bytes;
+  }
+}
+
+// Commits accepted SWAPs (vectors and write-back, through `x`) and keeps a
+// commit only when its committed rank is at most limit[c]; otherwise the two
+// sites, the bond vector and the bond dimension are restored from a copy taken
+// just before.  The committed rank decides, so an accepted swap always lowers
+// (relaxed: never raises) its bond in the arithmetic that wrote the MPO, even
+// where the values-only trial of the mixed form rounded differently.
+mpo_status_t commit_checked(mpo_ctx* x, const std::vector<Trial>& commits, const std::vector<int>& limit,
+                            std::vector<char>& kept, std::vector<Res>& cres) {
+  kept.assign(commits.size(), 1);
+  cres.clear();
+  if (commits.empty()) return MPO_OK;
+  hipStream_t st = x->stream;
+  struct Saved {
+    size_t e0, e1, nl;
+    int chi;
+  };
+  std::vector<Saved> sv(commits.size());
+  for (size_t c = 0; c < commits.size(); ++c) {
+    mpo_ctx* o = commits[c].owner;
+    const int b = commits[c].bond;
+    Saved& v = sv[c];
+    v.e0 = (size_t)o->chi[b] * 4 * o->chi[b + 1] * o->esz;
+    v.e1 = (size_t)o->chi[b + 1] * 4 * o->chi[b + 2] * o->esz;
+    v.nl = (size_t)o->chi[b + 1] * sizeof(double);
+    v.chi = o->chi[b + 1];
+    ensure_backup(x, c, v.e0 + v.e1 + v.nl);
+  }
+  for (size_t c = 0; c < commits.size(); ++c) {
+    mpo_ctx* o = commits[c].owner;
+    const int b = commits[c].bond;
+    char* d = (char*)x->bk[c];
+    const Saved& v = sv[c];
+    hip_check(hipMemcpyAsync(d, o->site[b], v.e0, hipMemcpyDeviceToDevice, st), "commit backup");
+    hip_check(hipMemcpyAsync(d + v.e0, o->site[b + 1], v.e1, hipMemcpyDeviceToDevice, st), "commit backup");
+    hip_check(hipMemcpyAsync(d + v.e0 + v.e1, o->lam[b], v.nl, hipMemcpyDeviceToDevice, st), "commit backup");
+  }
+  std::vector<Req> reqs;
+  for (const Trial& q : commits) {
+    Req r = swap_req(q.bond, q.side);
+    r.owner = q.owner;
+    reqs.push_back(r);
+  }
+  mpo_status_t s = updates(x, reqs, cres, true);
+  if (s != MPO_OK) return s;
+  for (size_t c = 0; c < commits.size(); ++c) {
+    if (cres[c].k <= limit[c]) continue;
+    mpo_ctx* o = commits[c].owner;
+    const int b = commits[c].bond;
+    const char* d = (const char*)x->bk[c];
+    const Saved& v = sv[c];
+    hip_check(hipMemcpyAsync(o->site[b], d, v.e0, hipMemcpyDeviceToDevice, st), "commit restore");
+    hip_check(hipMemcpyAsync(o->site[b + 1], d + v.e0, v.e1, hipMemcpyDeviceToDevice, st), "commit restore");
+    hip_check(hipMemcpyAsync(o->lam[b], d + v.e0 + v.e1, v.nl, hipMemcpyDeviceToDevice, st), "commit restore");
+    o->chi[b + 1] = v.chi;
+    o->site_ver[b] = ++o->ver_clock;
+    o->site_ver[b + 1] = ++o->ver_clock;
+    o->n_reverted += 1;
+    kept[c] = 0;
+  }
+  hip_check(hipStreamSynchronize(st), "commit sync");
+  return MPO_OK;
+}
+
+// The parallel schedule (App. A.1) on several MPOs in lockstep, through the
+// executor x: batches both-even, both-odd, left-even, left-odd, right-even,
+// right-odd; in each, every bond of the parity is tried at once (disjoint
+// bonds are independent in Vidal form), and each bond whose trial lowers (or,
+// relaxed, keeps) its dimension is committed.  An MPO leaves after a cycle
+// with no strict reduction, or after max_iters cycles.
+mpo_status_t unswap_parallel(mpo_ctx* x, const std::vector<mpo_ctx*>& hs, int max_iters, bool relaxed,
+                             std::vector<std::vector<mpo_swap_t>>& acc, bool& noconv) {
+  static const int order[6][2] = {{2, 0}, {2, 1}, {0, 0}, {0, 1}, {1, 0}, {1, 1}};
+  const size_t count = hs.size();
+  acc.assign(count, {});
+  std::vector<char> active(count, 1), reduced(count, 0);
+  for (int cyc = 0; cyc < max_iters; ++cyc) {
+    bool any = false;
+    for (size_t p = 0; p < count; ++p) {
+      reduced[p] = 0;
+      any |= active[p] != 0;
+    }
+    if (!any) break;
+    for (int c = 0; c < 6; ++c) {
+      const int side = order[c][0], parity = order[c][1];
+      std::vector<Trial> trials;
+      std::vector<size_t> who;
+      for (size_t p = 0; p < count; ++p) {
+        if (!active[p]) continue;
+        for (int b = parity; b <= hs[p]->n - 2; b += 2) {
+          trials.push_back(Trial{hs[p], b, side});
+          who.push_back(p);
+        }
+      }
+      if (trials.empty()) continue;
+      std::vector<Res> tr;
+      mpo_status_t r = run_trials(x, trials, tr);
+      if (r != MPO_OK) return r;
+      std::vector<Trial> commits;
+      std::vector<int> limit, chi_before;
+      std::vector<size_t> cwho;
+      for (size_t t = 0; t < trials.size(); ++t) {
+        noconv |= tr[t].noconv;
+        const int chi_b = trials[t].owner->chi[trials[t].bond + 1];
+        if (tr[t].k < chi_b || (relaxed && tr[t].k == chi_b)) {
+          commits.push_back(trials[t]);
+          limit.push_back(relaxed ? chi_b : chi_b - 1);
+          chi_before.push_back(chi_b);
+          cwho.push_back(who[t]);
+        }
+      }
+      std::vector<char> kept;
+      std::vector<Res> cr;
+      r = commit_checked(x, commits, limit, kept, cr);
+      if (r != MPO_OK) return r;
+      for (size_t c = 0; c < commits.size(); ++c) {
+        noconv |= cr[c].noconv;
+        if (!kept[c]) continue;
+        acc[cwho[c]].push_back(mpo_swap_t{side, commits[c].bond});
+        if (cr[c].k < chi_before[c]) reduced[cwho[c]] = 1;
+      }
+    }
+    for (size_t p = 0; p < count; ++p)
+      if (!reduced[p]) active[p] = 0;
+  }
+  return MPO_OK;
+}
+
+// The sequential schedule (Alg. 1): the largest available bond first (ties:
+// lowest index), its L, R and B trials, the best by (k, discarded weight,
+// side order); accepted when it lowers (relaxed: keeps) the bond, after which
+// the neighbouring bonds become available again.
+mpo_status_t unswap_sequential(mpo_ctx* h, int max_iters, bool relaxed, std::vector<mpo_swap_t>& acc,
+                               bool& noconv) {
+  const int n = h->n;
+  std::set<int> avail;
+  for (int b = 0; b <= n - 2; ++b) avail.insert(b);
+  const size_t cap = (size_t)max_iters * (n - 1);
+  while (!avail.empty() && acc.size() < cap) {
+    int i = -1, best_chi = -1;
+    for (int b : avail)
+      if (h->chi[b + 1] > best_chi) {
+        best_chi = h->chi[b + 1];
+        i = b;
+      }
+    std::vector<Trial> trials = {Trial{h, i, 0}, Trial{h, i, 1}, Trial{h, i, 2}};
+    std::vector<Res> tr;
+    mpo_status_t r = run_trials(h, trials, tr);
+    if (r != MPO_OK) return r;
+    int bs = 0;
+    noconv |= tr[0].noconv;
+    for (int sd = 1; sd < 3; ++sd) {
+      noconv |= tr[sd].noconv;
+      const double tol = WEIGHT_TIE_REL * std::max(tr[sd].total, tr[bs].total);
+      if (tr[sd].k < tr[bs].k || (tr[sd].k == tr[bs].k && tr[sd].disc < tr[bs].disc - tol)) bs = sd;
+    }
+    avail.erase(i);
+    const int chi_i = h->chi[i + 1];
+    if (tr[bs].k < chi_i || (relaxed && tr[bs].k == chi_i)) {
+      std::vector<char> kept;
+      std::vector<Res> cr;
+      r = commit_checked(h, {trials[bs]}, {relaxed ? chi_i : chi_i - 1}, kept, cr);
+      if (r != MPO_OK) return r;
+      noconv |= cr[0].noconv;
+      if (kept[0]) {
+        acc.push_back(mpo_swap_t{bs, i});
+        if (i - 1 >= 0) avail.insert(i - 1);
+        if (i + 1 <= n - 2) avail.insert(i + 1);
+      }
+    }
+  }
+  return MPO_OK;
+}
+
 template <typename T>
 mpo_status_t extract_impl(mpo_ctx* h, uint8_t* bits, double* prob, double* norm2) {
   hipStream_t st = h->stream;
@@ -677,11 +957,12 @@ mpo_status_t extract_impl(mpo_ctx* h, uint8_t* bits, double* prob, double* norm2
   int maxchi = 1;
   for (int i = 0; i <= n; ++i) maxchi = std::max(maxchi, h->chi[i]);
   const size_t bytes = (eoff[n + 1] + (size_t)maxchi * maxchi + 6 * (size_t)maxchi + 8) * sizeof(cx<double>) + n + 64;
-  char* buf = (char*)dalloc(bytes);
+  char* buf = (char*)dalloc(h, bytes);
   struct Free {
+    mpo_ctx* h;
     char* p;
-    ~Free() { dfree(p); }
-  } guard{buf};
+    ~Free() { dfree(h, p); }
+  } guard{h, buf};
   cx<double>* E = (cx<double>*)buf;
   cx<double>* tmp = E + eoff[n + 1];
   cx<double>* v0 = tmp + (size_t)maxchi * maxchi;
@@ -735,11 +1016,11 @@ int64_t pow4_capped(int e, int64_t cap) {
 // Batch-execution resources of a handle or group: per-problem workspace
 // slots (grown on demand), Jacobi states, truncation results, gate staging.
 void init_workspace(mpo_ctx* h) {
-  h->ones = (double*)dalloc(sizeof(double));
+  h->ones = (double*)dalloc(h, sizeof(double));
   h->slots.assign(MAXB, Slot{});
-  h->states = (JacState*)dalloc(MAXB * sizeof(JacState));
-  h->results = (TruncResult*)dalloc(MAXB * sizeof(TruncResult));
-  h->d_gates = (double*)dalloc(MAXB * 64 * sizeof(double));
+  h->states = (JacState*)dalloc(h, MAXB * sizeof(JacState));
+  h->results = (TruncResult*)dalloc(h, MAXB * sizeof(TruncResult));
+  h->d_gates = (double*)dalloc(h, MAXB * 64 * sizeof(double));
   hip_check(hipHostMalloc((void**)&h->h_states, MAXB * sizeof(JacState), hipHostMallocDefault), "pinned");
   hip_check(hipHostMalloc((void**)&h->h_results, MAXB * sizeof(TruncResult), hipHostMallocDefault), "pinned");
   hip_check(hipHostMalloc((void**)&h->h_gates, MAXB * 64 * sizeof(double), hipHostMallocDefault), "pinned");
@@ -751,42 +1032,43 @@ void init_workspace(mpo_ctx* h) {
 void destroy(mpo_ctx* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  for (void* p : h->site) dfree(p);
-  for (double* p : h->lam) dfree(p);
+  for (void* p : h->site) dfree(h, p);
+  for (double* p : h->lam) dfree(h, p);
   for (Slot& s : h->slots) {
-    dfree(s.theta0);
-    dfree(s.thetan);
-    dfree(s.A);
-    dfree(s.V);
-    dfree(s.norms);
-    dfree(s.s_sorted);
-    dfree(s.perm);
-    dfree(s.tau);
-    dfree(s.Tf);
-    dfree(s.qwp);
-    dfree(s.qw2);
-    dfree(s.Y);
-    dfree(s.gpart);
-    dfree(s.dmat);
-    dfree(s.pflag);
-    dfree(s.bmod);
-    dfree(s.pchk);
-    dfree(s.qcnt);
-    dfree(s.qpart);
+    dfree(h, s.theta0);
+    dfree(h, s.thetan);
+    dfree(h, s.A);
+    dfree(h, s.V);
+    dfree(h, s.norms);
+    dfree(h, s.s_sorted);
+    dfree(h, s.perm);
+    dfree(h, s.tau);
+    dfree(h, s.Tf);
+    dfree(h, s.qwp);
+    dfree(h, s.qw2);
+    dfree(h, s.Y);
+    dfree(h, s.gpart);
+    dfree(h, s.dmat);
+    dfree(h, s.pflag);
+    dfree(h, s.bmod);
+    dfree(h, s.pchk);
+    dfree(h, s.qcnt);
+    dfree(h, s.qpart);
   }
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
-  dfree(h->ns_x);
-  dfree(h->ns_s);
-  dfree(h->ns_y);
-  dfree(h->lbuf);
-  dfree(h->ones);
-  dfree(h->states);
-  dfree(h->results);
-  dfree(h->d_gates);
+  for (void* p : h->bk) dfree(h, p);
+  dfree(h, h->ns_x);
+  dfree(h, h->ns_s);
+  dfree(h, h->ns_y);
+  dfree(h, h->lbuf);
+  dfree(h, h->ones);
+  dfree(h, h->states);
+  dfree(h, h->results);
+  dfree(h, h->d_gates);
   if (h->h_states) (void)hipHostFree(h->h_states);
   if (h->h_results) (void)hipHostFree(h->h_results);
   if (h->h_gates) (void)hipHostFree(h->h_gates);
@@ -820,10 +1102,19 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
   {
     const char* t = std::getenv("MPO_TRACE");
     h->trace = t && t[0] == '1';
+    // MPO_TRIAL_REUSE=0 re-runs every SWAP trial (the memo is exact, so this
+    // only changes the time); MPO_QR_SPIN sets the QR barrier's poll bound
+    // (0 makes every multi-workgroup panel give up at once: a forced failure).
+    const char* r = std::getenv("MPO_TRIAL_REUSE");
+    h->trial_reuse = !(r && r[0] == '0');
+    const char* q = std::getenv("MPO_QR_SPIN");
+    if (q && q[0]) h->qr_spin = std::max(0, std::atoi(q));
   }
   mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
     const int n = h->n;
     h->chi.assign(n + 1, 1);
+    h->site_ver.assign(n, 0);
+    h->trial_memo.assign((size_t)(n - 1) * 3, mpo_ctx::TrialMemo{});
     h->bond_cap.resize(n - 1);
     for (int b = 0; b < n - 1; ++b)
       h->bond_cap[b] = (int)pow4_capped(std::min(b + 1, n - 1 - b), cfg->chi_max);
@@ -833,9 +1124,9 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
     for (int i = 0; i < n; ++i) {
       const size_t cl = i > 0 ? h->bond_cap[i - 1] : 1, cr = i < n - 1 ? h->bond_cap[i] : 1;
       h->site_cap[i] = cl * 4 * cr;
-      h->site[i] = dalloc(h->site_cap[i] * h->esz);
+      h->site[i] = dalloc(h, h->site_cap[i] * h->esz);
     }
-    for (int b = 0; b < n - 1; ++b) h->lam[b] = (double*)dalloc(h->bond_cap[b] * sizeof(double));
+    for (int b = 0; b < n - 1; ++b) h->lam[b] = (double*)dalloc(h, h->bond_cap[b] * sizeof(double));
     init_workspace(h);
     const double one = 1.0;
     const double hv = 0.70710678118654752440;
@@ -956,75 +1247,29 @@ mpo_status_t mpo_group_unswap(mpo_group_t g, int32_t count, const mpo_handle_t* 
   if (!opts || count < 0 || (count > 0 && !handles) || log_cap_each < 0 || (log_cap_each > 0 && count > 0 && !logs))
     return fail(x, MPO_EINVAL, "bad arguments");
   if (opts->schedule != 1) return fail(x, MPO_EINVAL, "group unswapping runs the parallel schedule (1)");
+  std::vector<mpo_ctx*> hs;
   for (int p = 0; p < count; ++p) {
     mpo_ctx* o = handles[p];
     if (!o || o->n == 0) return fail(x, MPO_EINVAL, "null handle");
     if (o->prec != x->prec) return fail(x, MPO_EINVAL, "handle precision differs from the group's");
     for (int q = 0; q < p; ++q)
       if (handles[q] == o) return fail(x, MPO_EINVAL, "handles must be distinct");
+    hs.push_back(o);
   }
   const int max_iters = opts->max_iters > 0 ? opts->max_iters : 20;
-  const bool relaxed = opts->relaxed != 0;
-  std::vector<std::vector<mpo_swap_t>> acc(count);
-  std::vector<char> active(count, 1), reduced(count, 0);
+  std::vector<std::vector<mpo_swap_t>> acc;
   bool noconv = false;
-  mpo_status_t s = guarded(x, [&]() -> mpo_status_t {
-    static const int order[6][2] = {{2, 0}, {2, 1}, {0, 0}, {0, 1}, {1, 0}, {1, 1}};
-    for (int cyc = 0; cyc < max_iters; ++cyc) {
-      bool any = false;
-      for (int p = 0; p < count; ++p) {
-        reduced[p] = 0;
-        any |= active[p] != 0;
-      }
-      if (!any) break;
-      for (int c = 0; c < 6; ++c) {
-        const int side = order[c][0], parity = order[c][1];
-        std::vector<Req> trials;
-        std::vector<int> who;
-        for (int p = 0; p < count; ++p) {
-          if (!active[p]) continue;
-          for (int b = parity; b <= handles[p]->n - 2; b += 2) {
-            Req q = swap_req(b, side);
-            q.owner = handles[p];
-            trials.push_back(q);
-            who.push_back(p);
-          }
-        }
-        if (trials.empty()) continue;
-        std::vector<Res> tr;
-        mpo_status_t r = updates(x, trials, tr, false);
-        if (r != MPO_OK) return r;
-        std::vector<Req> commits;
-        for (size_t t = 0; t < trials.size(); ++t) {
-          noconv |= tr[t].noconv;
-          const int p = who[t], b = trials[t].bond;
-          const int chi_b = handles[p]->chi[b + 1];
-          if (tr[t].k < chi_b || (relaxed && tr[t].k == chi_b)) {
-            commits.push_back(trials[t]);
-            acc[p].push_back(mpo_swap_t{side, b});
-            if (tr[t].k < chi_b) reduced[p] = 1;
-          }
-        }
-        if (!commits.empty()) {
-          std::vector<Res> cr;
-          r = updates(x, commits, cr, true);
-          if (r != MPO_OK) return r;
-          for (auto& y : cr) noconv |= y.noconv;
-        }
-      }
-      for (int p = 0; p < count; ++p)
-        if (!reduced[p]) active[p] = 0;
-    }
-    return MPO_OK;
-  });
-  if (s < 0) return s;
+  mpo_status_t s =
+      guarded(x, [&]() -> mpo_status_t { return unswap_parallel(x, hs, max_iters, opts->relaxed != 0, acc, noconv); });
+  // the swaps accepted before a failure stay applied and are reported
   bool over = false;
   for (int p = 0; p < count; ++p) {
-    const int nacc = (int)acc[p].size();
+    const int nacc = p < (int)acc.size() ? (int)acc[p].size() : 0;
     for (int j = 0; j < nacc && j < log_cap_each; ++j) logs[(size_t)p * log_cap_each + j] = acc[p][j];
     if (n_accepted) n_accepted[p] = nacc;
     over |= nacc > log_cap_each;
   }
+  if (s < 0) return s;
   if (over) return fail(x, MPO_EOVERFLOW, "accepted-swap log truncated");
   return noconv ? MPO_WARN_NOCONV : MPO_OK;
 }
@@ -1086,82 +1331,18 @@ mpo_status_t mpo_unswap_sweep(mpo_handle_t h, const mpo_unswap_opts_t* opts, mpo
   const int max_iters = opts->max_iters > 0 ? opts->max_iters : 20;
   const bool relaxed = opts->relaxed != 0;
   std::vector<mpo_swap_t> acc;
+  std::vector<std::vector<mpo_swap_t>> a;
   bool noconv = false;
   mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
-    const int n = h->n;
-    if (opts->schedule == 1) {
-      static const int order[6][2] = {{2, 0}, {2, 1}, {0, 0}, {0, 1}, {1, 0}, {1, 1}};
-      for (int cyc = 0; cyc < max_iters; ++cyc) {
-        bool reduced = false;
-        for (int c = 0; c < 6; ++c) {
-          const int side = order[c][0], parity = order[c][1];
-          std::vector<Req> trials;
-          for (int b = parity; b <= n - 2; b += 2) trials.push_back(swap_req(b, side));
-          if (trials.empty()) continue;
-          std::vector<Res> tr;
-          mpo_status_t r = updates(h, trials, tr, false);
-          if (r != MPO_OK) return r;
-          std::vector<Req> commits;
-          for (size_t t = 0; t < trials.size(); ++t) {
-            noconv |= tr[t].noconv;
-            const int b = trials[t].bond;
-            const int chi_b = h->chi[b + 1];
-            if (tr[t].k < chi_b || (relaxed && tr[t].k == chi_b)) {
-              commits.push_back(trials[t]);
-              acc.push_back(mpo_swap_t{side, b});
-              if (tr[t].k < chi_b) reduced = true;
-            }
-          }
-          if (!commits.empty()) {
-            std::vector<Res> cr;
-            r = updates(h, commits, cr, true);
-            if (r != MPO_OK) return r;
-            for (auto& x : cr) noconv |= x.noconv;
-          }
-        }
-        if (!reduced) break;
-      }
-    } else {
-      std::set<int> avail;
-      for (int b = 0; b <= n - 2; ++b) avail.insert(b);
-      const size_t cap = (size_t)max_iters * (n - 1);
-      while (!avail.empty() && acc.size() < cap) {
-        int i = -1, best_chi = -1;
-        for (int b : avail)
-          if (h->chi[b + 1] > best_chi) {
-            best_chi = h->chi[b + 1];
-            i = b;
-          }
-        std::vector<Req> trials = {swap_req(i, 0), swap_req(i, 1), swap_req(i, 2)};
-        std::vector<Res> tr;
-        mpo_status_t r = updates(h, trials, tr, false);
-        if (r != MPO_OK) return r;
-        int bs = 0;
-        for (int sd = 1; sd < 3; ++sd) {
-          noconv |= tr[sd].noconv;
-          const double tol = WEIGHT_TIE_REL * std::max(tr[sd].total, tr[bs].total);
-          if (tr[sd].k < tr[bs].k || (tr[sd].k == tr[bs].k && tr[sd].disc < tr[bs].disc - tol)) bs = sd;
-        }
-        avail.erase(i);
-        const int chi_i = h->chi[i + 1];
-        if (tr[bs].k < chi_i || (relaxed && tr[bs].k == chi_i)) {
-          std::vector<Req> commit = {trials[bs]};
-          std::vector<Res> cr;
-          r = updates(h, commit, cr, true);
-          if (r != MPO_OK) return r;
-          noconv |= cr[0].noconv;
-          acc.push_back(mpo_swap_t{bs, i});
-          if (i - 1 >= 0) avail.insert(i - 1);
-          if (i + 1 <= n - 2) avail.insert(i + 1);
-        }
-      }
-    }
-    return MPO_OK;
+    if (opts->schedule == 1) return unswap_parallel(h, {h}, max_iters, relaxed, a, noconv);
+    return unswap_sequential(h, max_iters, relaxed, acc, noconv);
   });
-  if (s < 0) return s;
+  if (opts->schedule == 1 && !a.empty()) acc = a[0];
+  // the swaps accepted before a failure stay applied and are reported
   const int nacc = (int)acc.size();
   for (int j = 0; j < nacc && j < log_cap; ++j) log[j] = acc[j];
   if (n_accepted) *n_accepted = nacc;
+  if (s < 0) return s;
   if (nacc > log_cap) return fail(h, MPO_EOVERFLOW, "accepted-swap log truncated");
   return noconv ? MPO_WARN_NOCONV : MPO_OK;
 }
@@ -1211,11 +1392,12 @@ mpo_status_t mpo_read_site(mpo_handle_t h, int32_t site, double* out, int64_t ca
     if (h->prec == MPO_FP64) {
       hip_check(hipMemcpyAsync(out, h->site[site], ne * 16, hipMemcpyDeviceToHost, h->stream), "read site");
     } else {
-      void* tmp = dalloc(ne * 16);
+      void* tmp = dalloc(h, ne * 16);
       struct F {
+        mpo_ctx* h;
         void* p;
-        ~F() { dfree(p); }
-      } g{tmp};
+        ~F() { dfree(h, p); }
+      } g{h, tmp};
       launch_convert<double, float>((cx<double>*)tmp, (const cx<float>*)h->site[site], ne, h->stream);
       hip_check(hipMemcpyAsync(out, tmp, ne * 16, hipMemcpyDeviceToHost, h->stream), "read site");
       hip_check(hipStreamSynchronize(h->stream), "read sync");
@@ -1236,35 +1418,71 @@ mpo_status_t mpo_load_state(mpo_handle_t h, const int32_t* dims, const double* s
   for (int b = 0; b < n - 1; ++b)
     if (chi[b + 1] > 4 * chi[b] || chi[b + 1] > 4 * chi[b + 2])
       return fail(h, MPO_EINVAL, "bond dimensions are not reachable (chi_b > 4 chi_neighbour)");
+  size_t tot = 0, ltot = 0;
+  for (int i = 0; i < n; ++i) tot += (size_t)chi[i] * 4 * chi[i + 1];
+  for (int b = 0; b < n - 1; ++b) ltot += chi[b + 1];
+  for (size_t j = 0; j < 2 * tot; ++j)
+    if (!std::isfinite(sites[j])) return fail(h, MPO_ENUMERIC, "non-finite site tensor entry");
+  for (size_t j = 0; j < ltot; ++j)
+    if (!std::isfinite(lams[j]) || lams[j] < 0) return fail(h, MPO_EINVAL, "bond values must be finite and >= 0");
+  // Everything is staged on the device first; the MPO is written only after
+  // every allocation and upload has succeeded, by device-side copies.
   return guarded(h, [&]() -> mpo_status_t {
-    size_t off = 0, loff = 0;
-    size_t maxe = 0;
-    for (int i = 0; i < n; ++i) maxe = std::max(maxe, (size_t)chi[i] * 4 * chi[i + 1]);
-    void* tmp = dalloc(maxe * 16);
+    void* stage = dalloc(h, tot * 16 + ltot * sizeof(double));
     struct F {
+      mpo_ctx* h;
       void* p;
-      ~F() { dfree(p); }
-    } g{tmp};
+      ~F() { dfree(h, p); }
+    } g{h, stage};
+    cx<double>* sd = (cx<double>*)stage;
+    double* ld = (double*)(sd + tot);
+    hip_check(hipMemcpyAsync(sd, sites, tot * 16, hipMemcpyHostToDevice, h->stream), "load stage");
+    hip_check(hipMemcpyAsync(ld, lams, ltot * sizeof(double), hipMemcpyHostToDevice, h->stream), "load stage");
+    hip_check(hipStreamSynchronize(h->stream), "load stage sync");
+    size_t off = 0, loff = 0;
     for (int i = 0; i < n; ++i) {
       const size_t ne = (size_t)chi[i] * 4 * chi[i + 1];
-      if (h->prec == MPO_FP64) {
-        hip_check(hipMemcpyAsync(h->site[i], sites + 2 * off, ne * 16, hipMemcpyHostToDevice, h->stream), "load");
-      } else {
-        hip_check(hipMemcpyAsync(tmp, sites + 2 * off, ne * 16, hipMemcpyHostToDevice, h->stream), "load");
-        launch_convert<float, double>((cx<float>*)h->site[i], (const cx<double>*)tmp, ne, h->stream);
-      }
-      hip_check(hipStreamSynchronize(h->stream), "load sync");
+      if (h->prec == MPO_FP64)
+        hip_check(hipMemcpyAsync(h->site[i], sd + off, ne * 16, hipMemcpyDeviceToDevice, h->stream), "load");
+      else
+        launch_convert<float, double>((cx<float>*)h->site[i], sd + off, ne, h->stream);
       off += ne;
     }
     for (int b = 0; b < n - 1; ++b) {
-      hip_check(hipMemcpyAsync(h->lam[b], lams + loff, chi[b + 1] * sizeof(double), hipMemcpyHostToDevice, h->stream),
+      hip_check(hipMemcpyAsync(h->lam[b], ld + loff, chi[b + 1] * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
                 "load lam");
       loff += chi[b + 1];
     }
-    hip_check(hipStreamSynchronize(h->stream), "load sync");
     h->chi = chi;
+    for (int i = 0; i < n; ++i) h->site_ver[i] = ++h->ver_clock;
+    hip_check(hipStreamSynchronize(h->stream), "load sync");
     return MPO_OK;
   });
+}
+
+mpo_status_t mpo_tau_reached(mpo_handle_t h, int32_t* reached, int64_t* size) {
+  if (!h || !reached) return MPO_EINVAL;
+  int64_t t = 0;
+  for (int i = 0; i < h->n; ++i) t += (int64_t)h->chi[i] * 4 * h->chi[i + 1];
+  *reached = (h->cfg.tau_elems > 0 && t >= h->cfg.tau_elems) ? 1 : 0;
+  if (size) *size = t;
+  return MPO_OK;
+}
+
+mpo_status_t mpo_trial_swap(mpo_handle_t h, int32_t bond, int32_t side, mpo_update_info_t* info) {
+  if (!h || !info || bond < 0 || bond > h->n - 2 || side < 0 || side > 2) return MPO_EINVAL;
+  std::vector<Res> res;
+  mpo_status_t s = guarded(h, [&]() { return run_trials(h, {Trial{h, bond, side}}, res); });
+  if (s < 0) return s;
+  *info = mpo_update_info_t{res[0].k, res[0].sweeps, res[0].disc, res[0].total, res[0].rotations, 0};
+  return res[0].noconv ? MPO_WARN_NOCONV : MPO_OK;
+}
+
+mpo_status_t mpo_counters(mpo_handle_t h, int64_t* out, int32_t cap) {
+  if (!h || cap < 0 || (cap > 0 && !out)) return MPO_EINVAL;
+  const int64_t v[5] = {h->n_updates, h->n_trials, h->n_trials_reused, h->n_reverted, h->hook_allocs};
+  for (int j = 0; j < cap && j < 5; ++j) out[j] = v[j];
+  return MPO_OK;
 }
 
 mpo_status_t mpo_sync(mpo_handle_t h) {

@@ -157,9 +157,13 @@ class Contractor:
         self.in_w = Wires(self.n)
         self.trace: List[Dict] = []
         self.bond_updates = 0
-        self.trial_updates = 0
         mode = _mpo.CUT_REL_SV if cfg.cutoff_mode == "rel_sv" else _mpo.CUT_WEIGHT
-        self.m = _mpo.MPO(self.n, cfg.chi_max, cfg.cutoff, mode, _mpo.PRECISIONS[cfg.precision], stream=stream)
+        if np.isfinite(cfg.tau) and cfg.tau <= 0:
+            raise ValueError("tau must be positive (or inf for no unswapping)")
+        # size(M) is an integer, so size >= ceil(tau) exactly when size >= tau
+        tau_elems = int(np.ceil(cfg.tau)) if np.isfinite(cfg.tau) else 0
+        self.m = _mpo.MPO(self.n, cfg.chi_max, cfg.cutoff, mode, _mpo.PRECISIONS[cfg.precision], stream=stream,
+                          tau_elems=tau_elems)
 
     def close(self):
         self.m.close()
@@ -200,7 +204,10 @@ class Contractor:
         bits = site_bits[self.out_w.site_of]
         return RunResult(bits.astype(np.uint8), p, n2, site_bits, list(map(int, self.out_w.site_of)),
                          list(map(int, self.in_w.site_of)), self.trace, 0.0, self.bond_updates,
-                         self.trial_updates)
+                         self.m.counters()["trials"])
+
+    def lambdas(self) -> List[np.ndarray]:
+        return [self.m.singular_values(b) for b in range(self.n - 1)]
 
     def unswap(self):
         if self.cfg.unswap == "none":
@@ -224,7 +231,7 @@ class Contractor:
         t0 = time.perf_counter()
         while self.c_left or self.c_right:
             self.absorb_step()
-            while self.m.total_elements() < self.cfg.tau and (self.c_left or self.c_right):
+            while not self.m.tau_reached() and (self.c_left or self.c_right):
                 self.absorb_step()
             self.unswap()
         site_bits, p, n2 = self.m.extract_peak()
@@ -232,7 +239,7 @@ class Contractor:
         bits = site_bits[self.out_w.site_of]
         return RunResult(bits.astype(np.uint8), p, n2, site_bits, list(map(int, self.out_w.site_of)),
                          list(map(int, self.in_w.site_of)), self.trace, secs, self.bond_updates,
-                         self.trial_updates)
+                         self.m.counters()["trials"])
 
 
 def contract(circuit, cfg: RunConfig, stream=None) -> RunResult:

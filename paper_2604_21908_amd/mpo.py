@@ -23,17 +23,25 @@ SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
 
 EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_batch", "mpo_unswap_sweep",
             "mpo_extract_peak", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
-            "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_profile", "mpo_last_error", "mpo_version",
+            "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_tau_reached", "mpo_trial_swap", "mpo_counters",
+            "mpo_profile", "mpo_last_error", "mpo_version",
             "mpo_group_create", "mpo_group_free", "mpo_group_absorb", "mpo_group_unswap", "mpo_group_profile",
             "mpo_group_last_error"]
+COUNTERS = ["updates", "trials", "trials_reused", "commits_undone", "hook_allocs"]
 PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_gram", "finalize", "writeback", "writeback_gemm", "qr",
                 "reorth", "jacobi_evd", "jacobi_rot"]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class MpoConfig(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("chi_max", ctypes.c_int32), ("cutoff", ctypes.c_double),
                 ("cutoff_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("max_sweeps", ctypes.c_int32), ("jacobi_tol", ctypes.c_double)]
+                ("max_sweeps", ctypes.c_int32), ("jacobi_tol", ctypes.c_double),
+                ("tau_elems", ctypes.c_int64), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class UpdateInfo(ctypes.Structure):
@@ -88,6 +96,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mpo_read_site.argtypes = [P, I32, dp, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.mpo_load_state.argtypes = [P, ctypes.POINTER(I32), dp, dp]
     lib.mpo_sync.argtypes = [P]
+    lib.mpo_tau_reached.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    lib.mpo_trial_swap.argtypes = [P, I32, I32, ctypes.POINTER(UpdateInfo)]
+    lib.mpo_counters.argtypes = [P, ctypes.POINTER(I64), I32]
     lib.mpo_profile.argtypes = [P, I32, dp, ctypes.POINTER(I64)]
     lib.mpo_last_error.argtypes = [P]
     lib.mpo_last_error.restype = ctypes.c_char_p
@@ -127,17 +138,68 @@ def _current_stream():
     return None
 
 
+class TorchAllocator:
+    """alloc/free hooks of mpo_config_t backed by PyTorch's caching allocator
+    on one stream; `limit` (bytes) makes allocations beyond it fail, which the
+    library reports as MPO_ENOMEM."""
+
+    def __init__(self, stream=None, limit: Optional[int] = None):
+        import torch
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+        if isinstance(stream, ctypes.c_void_p):
+            stream = stream.value
+        self.stream = stream          # raw hipStream_t (int) or None: the current stream
+        self.limit = limit
+        self.live = {}
+        self.calls = 0
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _ctx):
+        try:
+            if self.limit is not None and sum(self.live.values()) + nbytes > self.limit:
+                return None
+            ptr = self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            self.live[int(ptr)] = int(nbytes)
+            self.calls += 1
+            return int(ptr)
+        except Exception:
+            return None
+
+    def _free(self, ptr, _ctx):
+        try:
+            if ptr and int(ptr) in self.live:
+                del self.live[int(ptr)]
+                self.torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    @property
+    def bytes_live(self) -> int:
+        return sum(self.live.values())
+
+
 class MPO:
-    """One device-resident MPO (a libmpo handle)."""
+    """One device-resident MPO (a libmpo handle).  By default its device
+    memory comes from PyTorch's caching allocator (allocator="torch"); pass
+    allocator=None for hipMalloc, or a TorchAllocator instance."""
 
     def __init__(self, n: int, chi_max: int, cutoff: float, cutoff_mode: int = CUT_REL_SV,
-                 precision: int = FP64, max_sweeps: int = 0, jacobi_tol: float = 0.0, stream=None):
+                 precision: int = FP64, max_sweeps: int = 0, jacobi_tol: float = 0.0, stream=None,
+                 tau_elems: int = 0, allocator="torch"):
         self.lib = load_library()
         self.n = n
         self.precision = precision
-        cfg = MpoConfig(n, chi_max, cutoff, cutoff_mode, precision, max_sweeps, jacobi_tol)
-        h = ctypes.c_void_p()
         st = stream if stream is not None else _current_stream()
+        if allocator == "torch":
+            allocator = TorchAllocator(st)
+        self.allocator = allocator
+        cfg = MpoConfig(n, chi_max, cutoff, cutoff_mode, precision, max_sweeps, jacobi_tol, int(tau_elems))
+        if allocator is not None:
+            cfg.alloc = allocator.alloc_fn
+            cfg.free = allocator.free_fn
+        h = ctypes.c_void_p()
         s = self.lib.mpo_init_identity(ctypes.byref(cfg), st, ctypes.byref(h))
         if s != 0:
             raise MpoError(s, "mpo_init_identity failed")
@@ -254,6 +316,23 @@ class MPO:
 
     def sync(self):
         self._check(self.lib.mpo_sync(self.h), "mpo_sync")
+
+    def tau_reached(self) -> bool:
+        r = ctypes.c_int32()
+        self._check(self.lib.mpo_tau_reached(self.h, ctypes.byref(r), None), "mpo_tau_reached")
+        return bool(r.value)
+
+    def trial_swap(self, bond: int, side: int) -> dict:
+        info = UpdateInfo()
+        s = self.lib.mpo_trial_swap(self.h, bond, side, ctypes.byref(info))
+        self._check(s, "mpo_trial_swap", ok=(0, 1))
+        return dict(k=info.chi_new, sweeps=info.sweeps, discarded=info.discarded_weight,
+                    total=info.total_weight, noconv=(s == 1))
+
+    def counters(self) -> dict:
+        out = (ctypes.c_int64 * len(COUNTERS))()
+        self._check(self.lib.mpo_counters(self.h, out, len(COUNTERS)), "mpo_counters")
+        return {c: int(out[i]) for i, c in enumerate(COUNTERS)}
 
     def profile(self, on: bool) -> dict:
         """Returns {class: (ms, launches)} accumulated so far, resets, and

@@ -12,7 +12,6 @@ its peak readout.
 """
 from __future__ import annotations
 
-import collections
 import dataclasses
 import time
 from typing import Callable, List, Optional, Sequence
@@ -31,6 +30,37 @@ class Request:
     n: int
     depth: int
     seed: int
+    circuit: Optional[cg.Circuit] = None     # built before serving starts (host memory)
+
+
+def prepare(requests: Sequence[Request], reading: str = "A") -> None:
+    """Builds every request's circuit up front: a circuit is already in host
+    memory when it arrives, so generation is not part of its time-to-peak."""
+    for r in requests:
+        if r.circuit is None:
+            r.circuit = cg.mirrored_peaked_circuit(r.n, r.depth, r.seed, reading=reading)
+
+
+def admit(pending: Sequence[Request], used_bytes: int, budget_bytes: int, free_slots: int, chi_max: int):
+    """First-come-first-served admission by projected memory: the head of the
+    queue is admitted while a slot is free and its n chi_max^2 16 B fits in
+    what the resident requests leave of the budget; a request that could not
+    fit even alone is refused.  Returns (admitted, refused, still_waiting)."""
+    admitted, refused, waiting = [], [], []
+    used = used_bytes
+    blocked = False
+    for r in pending:
+        need = projected_bytes(r.n, chi_max)
+        if need > budget_bytes:
+            refused.append(r)
+            continue
+        if not blocked and len(admitted) < free_slots and used + need <= budget_bytes:
+            admitted.append(r)
+            used += need
+        else:
+            blocked = True          # no overtaking: later requests wait behind the head
+            waiting.append(r)
+    return admitted, refused, waiting
 
 
 @dataclasses.dataclass
@@ -41,6 +71,8 @@ class Served:
     bits_ok: bool
     prob: float
     updates: int
+    bits: Optional[np.ndarray] = None
+    lams: Optional[list] = None
 
     @property
     def time_to_peak(self) -> float:
@@ -51,15 +83,27 @@ def projected_bytes(n: int, chi_max: int) -> int:
     return n * chi_max * chi_max * 16
 
 
+def _device_used_bytes(torch) -> int:
+    free, total = torch.cuda.mem_get_info()
+    return int(total - free)
+
+
 def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max_slots: int = 64,
-          reading: str = "A", on_round: Optional[Callable[[int, int], None]] = None) -> dict:
+          reading: str = "A", on_round: Optional[Callable[[int, int], None]] = None,
+          keep_lams: bool = False) -> dict:
+    import torch
     reqs = sorted(requests, key=lambda r: r.t_arrival)
+    prepare(reqs, reading)
     group = _mpo.Group(_mpo.PRECISIONS[cfg.precision])
-    pending: collections.deque = collections.deque()
+    pending: List[Request] = []
     active: List[tuple] = []
     done: List[Served] = []
+    refused: List[Request] = []
     used = 0
     peak_used = 0
+    torch.cuda.synchronize()
+    dev0 = _device_used_bytes(torch)
+    dev_peak = 0
     i = 0
     rounds = 0
     t0 = time.perf_counter()
@@ -68,14 +112,12 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
         while i < len(reqs) and reqs[i].t_arrival <= now:
             pending.append(reqs[i])
             i += 1
-        while pending and len(active) < max_slots:
-            r = pending[0]
+        adm, ref, pending = admit(pending, used, budget_bytes, max_slots - len(active), cfg.chi_max)
+        refused += ref
+        for r in adm:
             need = projected_bytes(r.n, cfg.chi_max)
-            if used + need > budget_bytes and active:
-                break
-            pending.popleft()
-            circ = cg.mirrored_peaked_circuit(r.n, r.depth, r.seed, reading=reading)
-            active.append((r, bt.CircuitTask(circ, cfg, group_unswap=True), time.perf_counter() - t0, need))
+            task = bt.CircuitTask(r.circuit, cfg, group_unswap=True, keep_lams=keep_lams)
+            active.append((r, task, time.perf_counter() - t0, need))
             used += need
             peak_used = max(peak_used, used)
         if not active:
@@ -84,6 +126,7 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
             continue
         bt.run_round([a[1] for a in active], group)
         rounds += 1
+        dev_peak = max(dev_peak, _device_used_bytes(torch) - dev0)
         if on_round:
             on_round(rounds, len(active))
         still = []
@@ -91,7 +134,7 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
             if task.done:
                 res = task.result
                 done.append(Served(r, t_adm, task.t_done - t0, bool((res.bits == task.circuit.peak).all()),
-                                   float(res.prob), res.bond_updates))
+                                   float(res.prob), res.bond_updates, res.bits, task.lams))
                 used -= need
             else:
                 still.append((r, task, t_adm, need))
@@ -99,10 +142,11 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
     secs = time.perf_counter() - t0
     group.close()
     ttp = np.array([d.time_to_peak for d in done]) if done else np.zeros(1)
-    return dict(served=done, seconds=secs, rounds=rounds, circuits_per_s=len(done) / secs if secs else 0.0,
+    return dict(served=done, refused=refused, seconds=secs, rounds=rounds,
+                circuits_per_s=len(done) / secs if secs else 0.0,
                 p50=float(np.percentile(ttp, 50)), p99=float(np.percentile(ttp, 99)),
                 all_peaks_ok=all(d.bits_ok for d in done), peak_projected_bytes=peak_used,
-                bond_updates=sum(d.updates for d in done))
+                peak_device_bytes=dev_peak, bond_updates=sum(d.updates for d in done))
 
 
 def poisson_requests(rate: float, duration: float, seed: int = 4000, sizes=(24, 40, 56),
@@ -130,11 +174,12 @@ def serve_sequential(requests: Sequence[Request], cfg: dr.RunConfig, reading: st
     queue is then exact for a single server: a request starts when it has
     arrived and the previous one has finished."""
     reqs = sorted(requests, key=lambda r: r.t_arrival)
+    prepare(reqs, reading)
     service = []
     ok = []
     updates = 0
     for r in reqs:
-        circ = cg.mirrored_peaked_circuit(r.n, r.depth, r.seed, reading=reading)
+        circ = r.circuit
         t0 = time.perf_counter()
         res = dr.contract(circ, cfg)
         service.append(time.perf_counter() - t0)

@@ -54,6 +54,25 @@ def test_invalid_config_rejected_without_device():
     assert lib.mpo_init_identity(ctypes.byref(bad), None, ctypes.byref(h)) == -1
     assert lib.mpo_unswap_sweep(None, None, None, 0, None) == -1
     assert lib.mpo_extract_peak(None, None, None, None) == -1
+    assert lib.mpo_tau_reached(None, None, None) == -1
+    assert lib.mpo_trial_swap(None, 0, 0, None) == -1
+    assert lib.mpo_counters(None, None, 0) == -1
+
+
+def test_admission_by_projected_memory():
+    """Serving admission (first come first served, n chi^2 16 B per request):
+    the head is admitted while it fits, later requests never overtake it, and
+    a request larger than the whole budget is refused."""
+    from paper_2604_21908_amd import serve as sv
+    R = sv.Request
+    q = [R(0.0, 24, 6, 1), R(0.1, 56, 14, 2), R(0.2, 24, 6, 3), R(0.3, 200, 50, 4)]
+    budget = sv.projected_bytes(24, 512) + sv.projected_bytes(40, 512)
+    adm, ref, wait = sv.admit(q, 0, budget, 8, 512)
+    assert [r.seed for r in adm] == [1] and [r.seed for r in ref] == [4] and [r.seed for r in wait] == [2, 3]
+    adm, ref, wait = sv.admit(wait, 0, budget, 8, 512)
+    assert [r.seed for r in adm] == [2] and [r.seed for r in wait] == [3]
+    adm, ref, wait = sv.admit([R(0, 24, 6, 5), R(0, 24, 6, 6)], 0, budget, 1, 512)
+    assert [r.seed for r in adm] == [5] and [r.seed for r in wait] == [6]
 
 
 # ------------------------------------------------------------ host logic

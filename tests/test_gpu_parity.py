@@ -312,7 +312,9 @@ _FULL = {}
 
 
 def _full_size_oracle():
-    """Singular values of the chi = 1024 update (theta 4096 x 4096), once."""
+    """The chi = 1024 update (theta 4096 x 4096) in the oracle, once: its
+    singular values, discarded weight, the untruncated theta (with the left
+    bond values) and the truncated operator U_k S_k V_k^dag."""
     if not _FULL:
         import bench
         n, sites, lams, bond = bench.micro_state(1024)
@@ -321,28 +323,50 @@ def _full_size_oracle():
         m = mo.OracleMPO(n)
         m.B = [s.copy() for s in sites]
         m.lam = [l.copy() for l in lams]
-        r = mo.bond_update(m, bond, go, gi, 1024, 1e-8, "weight", vectors=False)
-        _FULL.update(n=n, sites=sites, lams=lams, bond=bond, go=go, gi=gi, r=r)
+        r = mo.bond_update(m, bond, go, gi, 1024, 1e-8, "weight", vectors=True)
+        chil, chir = sites[bond].shape[0], sites[bond + 1].shape[2]
+        th = mo.apply_gates_to_theta(np.tensordot(sites[bond], sites[bond + 1], axes=([2], [0])), go, gi)
+        theta = (th * lams[bond - 1][:, None, None, None]).reshape(4 * chil, 4 * chir)
+        _FULL.update(n=n, sites=sites, lams=lams, bond=bond, go=go, gi=gi, r=r, theta=theta)
     return _FULL
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+@pytest.mark.parametrize("prec", ["mixed", "fp32", "fp64"])
 def test_full_size_chi1024_update(lib, prec):
-    """The benchmarked update itself (chi_max = 1024 binds) against the
-    oracle's singular values, discarded weight and the orthonormality of
-    the new right tensor."""
+    """The benchmarked update itself (theta 4096 x 4096, chi_max = 1024 binds)
+    against the oracle: kept rank, singular values (normwise), discarded weight,
+    orthonormal rows of the new right tensor, and the written two-site operator.
+    With the left bond values applied, lambda B_i' B_i+1' is a rank-k
+    approximation of theta; it must be a best one (Eckart-Young): its squared
+    distance to the oracle's theta equals the oracle's discarded weight up to the
+    tolerance times the total weight, and it lies within 2 sqrt(w) + tol of the
+    oracle's U_k S_k V_k^dag.  A wrong row chunk of V_k, a wrong left tensor or a
+    lost conjugate would show an O(1) excess."""
     f = _full_size_oracle()
     r = f["r"]
+    tol = TOL[prec]
     g = lib.MPO(f["n"], 1024, 1e-8, 1, PREC[prec])
     g.load_state(f["sites"], f["lams"])
     info = g.absorb(f["bond"], f["go"], f["gi"])
-    s_gpu = g.singular_values(f["bond"])
-    right = g.read_site(f["bond"] + 1).reshape(info["k"], -1)
+    b = f["bond"]
+    s_gpu = g.singular_values(b)
+    left = g.read_site(b)
+    right = g.read_site(b + 1)
     g.close()
-    assert info["k"] == r.k == 1024
-    assert sv_err(s_gpu, r.s[:r.k]) <= TOL[prec]
-    assert abs(info["discarded"] - r.discarded) <= 1e-4 * r.total
-    assert np.max(np.abs(right @ right.conj().T - np.eye(info["k"]))) <= 1e-4
+    k = info["k"]
+    assert k == r.k == 1024
+    assert sv_err(s_gpu, r.s[:r.k]) <= tol
+    assert abs(info["discarded"] - r.discarded) <= max(tol, 1e-12) * r.total
+    rr = right.reshape(k, -1)
+    assert np.max(np.abs(rr @ rr.conj().T - np.eye(k))) <= (1e-4 if prec != "fp64" else 1e-10)
+    lam = f["lams"][b - 1]
+    op = (left * lam[:, None, None]).reshape(-1, k) @ rr
+    theta = f["theta"]
+    w_eff = np.linalg.norm(theta - op) ** 2
+    assert w_eff >= r.discarded * (1 - 1e-9)
+    assert w_eff - r.discarded <= max(tol, 1e-12) * r.total
+    ref_op = (r.new_left * lam[:, None, None]).reshape(-1, k) @ r.new_right.reshape(k, -1)
+    assert np.linalg.norm(op - ref_op) <= 2 * np.sqrt(r.discarded) + tol * np.sqrt(r.total)
 
 
 def test_fp64_update_on_tall_panels(lib):

@@ -297,6 +297,61 @@ def test_workload_peaks_are_greedy_readable(config):
     assert 1e-5 < p < 1
 
 
+def test_batching_workload_peaks_are_greedy_readable():
+    """All 128 circuits of the batching workload: every prefix conditional of
+    K|0> along 0...0 exceeds 1/2 (the oracle's own computation), so the greedy
+    readout lands on the planted b."""
+    work = cg.batch_workload()
+    assert len(work) == 128
+    for c, chi in work:
+        assert chi in (128, 256, 512)
+        assert bf.k_state_margins(c.n, c.k_gates).min() > 0.5
+
+
+@pytest.mark.parametrize("rate", [1, 4, 16])
+def test_serving_workload_peaks_are_greedy_readable(rate):
+    """The first arrivals of each serving rate (n in {24, 40, 56})."""
+    from paper_2604_21908_amd import serve
+    reqs = serve.poisson_requests(rate, 600)[:12]
+    serve.prepare(reqs)
+    for r in reqs:
+        assert r.circuit.n == r.n and r.n in (24, 40, 56)
+        assert bf.k_state_margins(r.n, r.circuit.k_gates).min() > 0.5
+
+
+@pytest.mark.parametrize("n", [2, 3, 6, 9, 12])
+def test_generator_admission_check_matches_oracle(n):
+    """The generator's own prefix conditionals of K|0> (an exact chain rewrite)
+    equal the oracle's (truncation-free splits and environments) and, for
+    n <= 12, the statevector's."""
+    c = cg.mirrored_peaked_circuit(n, 2, 90 + n, min_margin=0.0)
+    layers = [[g for g in c.k_gates if g[0] % 2 == 0], [g for g in c.k_gates if g[0] % 2 == 1]]
+    got = cg.k_prefix_conditionals(n, layers)
+    assert np.max(np.abs(got - bf.k_state_margins(n, c.k_gates))) < 1e-12
+    psi = np.abs(bf.circuit_state(n, c.k_gates).reshape([2] * n)) ** 2
+    for i in range(n):
+        marg = psi[(0,) * i].reshape(2, -1).sum(axis=1)
+        assert abs(got[i] - marg[0] / marg.sum()) < 1e-12
+
+
+def test_generator_redraws_k_below_the_margin():
+    """A margin no K can meet makes the generator give up loudly; a seed whose
+    first K fails the 1/2 margin gets a different, admissible K."""
+    with pytest.raises(RuntimeError):
+        cg.mirrored_peaked_circuit(6, 2, 5, min_margin=1.0, max_k_draws=3)
+    n, kw = 24, dict(with_swaps=False, dress=False)
+    first_fail = None
+    for seed in range(40):
+        c0 = cg.mirrored_peaked_circuit(n, 1, seed, min_margin=0.0, **kw)
+        if bf.k_state_margins(n, c0.k_gates).min() <= 0.5:
+            first_fail = seed
+            break
+    assert first_fail is not None
+    c = cg.mirrored_peaked_circuit(n, 1, first_fail, **kw)
+    assert bf.k_state_margins(n, c.k_gates).min() > 0.5
+    assert c.digest() != c0.digest()
+
+
 # ------------------------------------------------ planted mistakes must fail
 def test_planted_mistakes_are_caught(monkeypatch):
     """A transposed input gate, a dropped Lambda or a dropped conjugate in the
