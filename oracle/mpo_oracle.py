@@ -24,6 +24,11 @@ What it follows:
   re-routing to the line is done lazily by SWAPs absorbed on the same side.
 * Sec. II.C (sampling): the MPO applied to |0...0> is an MPS; the peak is
   read out by a greedy left-to-right conditional argmax.
+* App. A.3 (side selection): besides Alg. 1's alternation (a layer of C_L,
+  then a layer of C_R, per absorption step), an adaptive mode that absorbs
+  the next layer of each side into its own copy of the MPO and keeps the
+  copy with the smaller size(M), and a fixed-frequency mode that takes f_L
+  layers of C_L, then f_R layers of C_R, in turn.
 
 Representation: site i is B_i[a, s, b] with s = 2*o + p (o output bit,
 p input bit); the MPO is kept as a vectorised MPS in Vidal/Hastings form:
@@ -225,6 +230,40 @@ def extract_peak(m: OracleMPO) -> Tuple[np.ndarray, float, float]:
     return bits, float(np.exp(logp)), norm2
 
 
+def sample(m: OracleMPO, uniforms: np.ndarray, with_q: bool = False):
+    """Sec. II.C sampling of M|0...0>: one sample per row of ``uniforms``
+    (shape count x n, values in [0, 1)).  From the left, site i's bit is 0
+    when u_i < P(0 | bits so far) = p_0 / (p_0 + p_1), with
+    p_o = w_o E_{i+1} w_o^dag, w_o = v A_i[:, o, :] and v the normalised left
+    vector of the bits chosen so far; E are the exact right environments of
+    extract_peak.  Returns (site bits, count x n; probability of each sampled
+    string, the product of its conditionals) and, with ``with_q``, the
+    thresholds P(0 | prefix) each decision compared u_i with (count x n)."""
+    n = m.n
+    u = np.asarray(uniforms, dtype=np.float64)
+    A = [m.B[i][:, 0::2, :] for i in range(n)]
+    env = [None] * (n + 1)
+    env[n] = np.ones((1, 1), dtype=np.complex128)
+    for i in range(n - 1, -1, -1):
+        env[i] = sum(A[i][:, o, :] @ env[i + 1] @ A[i][:, o, :].conj().T for o in range(2))
+    bits = np.zeros(u.shape, dtype=np.uint8)
+    probs = np.zeros(u.shape[0])
+    qs = np.zeros(u.shape)
+    for s in range(u.shape[0]):
+        v = np.ones((1,), dtype=np.complex128)
+        logp = 0.0
+        for i in range(n):
+            w = [v @ A[i][:, o, :] for o in range(2)]
+            p = [float((w[o] @ env[i + 1] @ w[o].conj()).real) for o in range(2)]
+            qs[s, i] = p[0] / (p[0] + p[1])
+            o = 0 if u[s, i] < qs[s, i] else 1
+            bits[s, i] = o
+            logp += np.log(p[o] / (p[0] + p[1]))
+            v = w[o] / np.sqrt(p[o])
+        probs[s] = np.exp(logp)
+    return (bits, probs, qs) if with_q else (bits, probs)
+
+
 # --------------------------------------------------------------------------
 # unswapping (Sec. II.B.2, Eq. (1); App. A.1, A.2)
 # --------------------------------------------------------------------------
@@ -329,6 +368,8 @@ class OracleConfig:
     unswap: str = "parallel"        # "parallel" (App. A.1), "sequential" (Alg. 1) or "none"
     relaxed: bool = False           # App. A.2
     max_unswap_iters: int = 20      # App. A.4
+    side: str = "both"              # "both" (Alg. 1), "adaptive" or "fixed" (App. A.3)
+    fixed_freq: Tuple[int, int] = (1, 1)   # fixed mode: layers of C_L, then of C_R, per period
 
 
 class Layout:
@@ -394,9 +435,10 @@ class Contraction:
         self.lay_r = Layout(n)
         self.trace: List[Dict] = []
         self.updates = 0
+        self.steps = 0                  # absorption steps taken (fixed-frequency phase)
 
     # ------------------------------------------------------------- updates
-    def _update(self, i, g_out, g_in, stage):
+    def _update(self, i, g_out, g_in, stage, fused=False):
         cfg = self.cfg
         chil, chir = self.m.B[i].shape[0], self.m.B[i + 1].shape[2]
         chi_old = self.m.chi(i)
@@ -405,7 +447,7 @@ class Contraction:
         self.updates += 1
         self.trace.append(dict(stage=stage, bond=i, chi_l=chil, chi=chi_old, chi_r=chir, k=r.k,
                                discarded=r.discarded, total=r.total, size=self.m.size(),
-                               s=r.s[:r.k].copy()))
+                               s=r.s[:r.k].copy(), fused=fused))
 
     def _route(self, lay: Layout, a: int, b: int, side: str) -> Tuple[int, int]:
         sa, sb = lay.site_of[a], lay.site_of[b]
@@ -419,8 +461,60 @@ class Contraction:
         return lay.site_of[a], lay.site_of[b]
 
     def absorb_step(self):
-        lgates = self.left.pop(0) if self.left else []
-        rgates = self.right.pop(0) if self.right else []
+        """One absorption step under the configured side selection."""
+        mode = self.cfg.side
+        if mode == "both" or not (self.left and self.right):
+            taken = "L" if self.left else "R"
+            self.absorb_layers(self.left.pop(0) if self.left else [],
+                               self.right.pop(0) if self.right else [])
+            if mode == "fixed":                # one side is used up
+                self.trace.append(dict(stage="layer", taken=taken))
+        elif mode == "fixed":
+            fl, fr = self.cfg.fixed_freq
+            if self.steps % (fl + fr) < fl:
+                self.absorb_layers(self.left.pop(0), [])
+                self.trace.append(dict(stage="layer", taken="L"))
+            else:
+                self.absorb_layers([], self.right.pop(0))
+                self.trace.append(dict(stage="layer", taken="R"))
+        elif mode == "adaptive":
+            self.absorb_adaptive()
+        else:
+            raise ValueError(mode)
+        self.steps += 1
+
+    def absorb_adaptive(self):
+        """App. A.3: the next C_L layer and the next C_R layer are each
+        absorbed into a copy of the current state; the copy with the smaller
+        size(M) is kept (equal sizes: the left one) and the other layer stays
+        pending.  Updates of the discarded copy are counted as trials."""
+        cands = []
+        for side in ("L", "R"):
+            c = Contraction.__new__(Contraction)
+            c.n, c.cfg = self.n, self.cfg
+            c.left, c.right = list(self.left), list(self.right)
+            c.m = self.m.copy()
+            c.lay_l, c.lay_r = Layout(self.n), Layout(self.n)
+            c.lay_l.site_of, c.lay_l.logical_at = list(self.lay_l.site_of), list(self.lay_l.logical_at)
+            c.lay_r.site_of, c.lay_r.logical_at = list(self.lay_r.site_of), list(self.lay_r.logical_at)
+            c.trace, c.updates, c.steps = [], 0, self.steps
+            if side == "L":
+                c.absorb_layers(c.left.pop(0), [])
+            else:
+                c.absorb_layers([], c.right.pop(0))
+            cands.append(c)
+        sizes = [c.m.size() for c in cands]
+        keep = cands[0] if sizes[0] <= sizes[1] else cands[1]
+        other = cands[1] if keep is cands[0] else cands[0]
+        self.left, self.right, self.m = keep.left, keep.right, keep.m
+        self.lay_l, self.lay_r = keep.lay_l, keep.lay_r
+        self.trace.extend(keep.trace)
+        self.updates += keep.updates
+        self.trial_absorb_updates = getattr(self, "trial_absorb_updates", 0) + other.updates
+        self.trace.append(dict(stage="side", side="L" if keep is cands[0] else "R",
+                               size_left=sizes[0], size_right=sizes[1]))
+
+    def absorb_layers(self, lgates, rgates):
         pending = list(rgates)
         for (a, b, u) in lgates:
             sa, sb = self._route(self.lay_l, a, b, "L")
@@ -434,7 +528,7 @@ class Contraction:
             if fused is not None:
                 ra, rb, ru = pending.pop(fused)
                 _, ur = orient(ru, self.lay_r.site_of[ra], self.lay_r.site_of[rb])
-                self._update(i, ul, ur, "absorb")
+                self._update(i, ul, ur, "absorb", fused=True)
             else:
                 self._update(i, ul, None, "absorb")
         for (a, b, u) in pending:

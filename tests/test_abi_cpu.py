@@ -104,7 +104,7 @@ def test_plan_step_matches_the_oracle_update_sequence():
                 ct.lay_r.swap_sites(j)
         ups = dr.plan_step(lg, rg, out_w, in_w)
         seen = []
-        ct._update = lambda i, go, gi, stage: seen.append((i, go, gi, stage))
+        ct._update = lambda i, go, gi, stage, fused=False: seen.append((i, go, gi, stage))
         ct.left, ct.right = [lg], [rg]
         ct.absorb_step()
         assert len(seen) == len(ups)

@@ -225,6 +225,57 @@ def test_unswap_reconstructs_operator_and_rewiring_is_exact(schedule, relaxed):
     assert np.allclose(full, bf.circuit_unitary(c.n, c.gates), atol=1e-9)
 
 
+@pytest.mark.parametrize("side,freq", [("adaptive", (1, 1)), ("fixed", (2, 1)), ("fixed", (1, 3))])
+def test_side_selection_reproduces_dense_unitary(side, freq):
+    """App. A.3: whichever side each step takes, and with unswapping and
+    rewiring between the phases, the contracted operator P_L M~ P_R is the
+    circuit's unitary (no truncation); every gate is absorbed exactly once."""
+    c = cg.mirrored_peaked_circuit(8, 3, 41, reading="B")
+    cfg = mo.OracleConfig(chi_max=256, cutoff=1e-12, tau=300, unswap="parallel", side=side, fixed_freq=freq)
+    ct = mo.Contraction(c.n, c.gates, cfg)
+    res = ct.run()
+    full = mo.full_operator(res) * 2 ** (c.n / 2)
+    assert np.allclose(full, bf.circuit_unitary(c.n, c.gates), atol=1e-9)
+    absorbed = sum(1 for t in res.trace if t.get("stage") == "absorb")
+    fused = sum(1 for t in res.trace if t.get("stage") == "absorb" and t.get("fused"))
+    assert absorbed + fused == len(c.gates)
+    if side == "fixed":
+        # while both sides have layers, the period is f_L steps of C_L then f_R of C_R
+        sides = [t["taken"] for t in res.trace if t.get("stage") == "layer"]
+        fl, fr = freq
+        nl = nr = len(mo.asap_layers(c.gates, c.n)) // 2
+        left = right = 0
+        for j, x in enumerate(sides):
+            if left >= nl or right >= nr:
+                break
+            assert x == ("L" if j % (fl + fr) < fl else "R")
+            left += x == "L"
+            right += x == "R"
+        assert j >= fl + fr
+
+
+def test_adaptive_keeps_the_smaller_copy_and_changes_the_path():
+    """App. A.3: each adaptive step keeps the copy with the smaller size(M)
+    (ties: the left one), and the kept size is the MPO's size after the step;
+    on this circuit the adaptive path differs from Alg. 1's alternation but
+    ends at the same operator."""
+    c = cg.mirrored_peaked_circuit(8, 3, 43, reading="B")
+    base = dict(chi_max=256, cutoff=1e-12, tau=400, unswap="parallel")
+    ct = mo.Contraction(c.n, c.gates, mo.OracleConfig(side="adaptive", **base))
+    res = ct.run()
+    picks = [t for t in res.trace if t.get("stage") == "side"]
+    assert picks and any(t["side"] == "R" for t in picks) and any(t["side"] == "L" for t in picks)
+    for j, t in enumerate(res.trace):
+        if t.get("stage") != "side":
+            continue
+        kept = min(t["size_left"], t["size_right"])
+        assert t["side"] == ("L" if t["size_left"] <= t["size_right"] else "R")
+        prev = [u for u in res.trace[:j] if "size" in u and u.get("stage") != "unswap"]
+        assert prev and prev[-1]["size"] == kept
+    alt = mo.contract(c.n, c.gates, mo.OracleConfig(side="both", **base))
+    assert np.allclose(mo.full_operator(res), mo.full_operator(alt), atol=1e-10)
+
+
 def test_unswap_removes_a_bare_swap_layer():
     n = 7
     m = mo.OracleMPO(n)
@@ -252,6 +303,36 @@ def test_extraction_matches_statevector_brute_force(seed):
     assert (res.bits == c.peak).all()
     assert abs(res.prob - prob[best]) < 1e-10
     assert abs(res.norm2 - 2.0 ** -c.n) < 1e-12 * 2.0 ** -c.n * 100
+
+
+@pytest.mark.parametrize("seed", [3, 8])
+def test_sampling_is_inverse_cdf_of_the_statevector(seed):
+    """Sec. II.C sampling, pinned by brute force: with the same uniforms, the
+    oracle's sampled strings equal those of sequential inverse-CDF sampling
+    from the dense state's marginals (bit i = 0 iff u_i < P(x_i = 0 | x_<i)),
+    and each returned probability is |<x|psi>|^2 / <psi|psi>."""
+    c = cg.mirrored_peaked_circuit(8, 3, 60 + seed, reading="B")
+    res = mo.contract(c.n, c.gates, mo.OracleConfig(chi_max=256, cutoff=1e-12, tau=300, unswap="parallel"))
+    psi = bf.circuit_state(c.n, c.gates)
+    # the MPS's site i carries the output leg of logical qubit logical_at[i]
+    logical_at = np.argsort(res.layout_left)
+    assert not np.array_equal(logical_at, np.arange(c.n))        # unswapping moved qubits
+    pr = (np.abs(psi) ** 2).reshape([2] * c.n).transpose(logical_at).reshape(-1)   # axes in site order
+    pr = pr / pr.sum()
+    rng = np.random.default_rng(seed)
+    u = rng.random((200, c.n))
+    bits, probs = mo.sample(res.mpo, u)
+    for s in range(u.shape[0]):
+        prefix = ()
+        for i in range(c.n):
+            marg = pr.reshape([2] * c.n)[prefix].reshape(2, -1).sum(axis=1)
+            x = 0 if u[s, i] < marg[0] / marg.sum() else 1
+            assert bits[s, i] == x
+            prefix = prefix + (x,)
+        idx = int("".join(map(str, bits[s])), 2)
+        assert abs(probs[s] - pr[idx]) <= 1e-10
+    # the peak is the most frequent string for a peaked state
+    assert len({tuple(b) for b in bits}) > 1
 
 
 def test_extraction_probability_of_returned_string_is_exact():
