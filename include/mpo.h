@@ -147,6 +147,20 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
 mpo_status_t mpo_absorb_gate_pair(mpo_handle_t h, int32_t bond, const double* g_out,
                                   const double* g_in, mpo_update_info_t* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * absorption as mpo_absorb_gate_pair, same kernels and same result, with
+ * every SVD workspace carved out of a static device array of 64 MiB (one copy
+ * per GPU, held until the process ends) instead of being allocated.  The call
+ * makes no hipMalloc/hipFree and no call of the alloc hook.  An update whose
+ * workspace does not fit (roughly theta above 512 x 512 in FP64, 724 x 724 in
+ * FP32, less in the mixed form) fails with MPO_EINVAL and the MPO unchanged.
+ * Kernel timing must be off.  The call synchronises the handle's stream
+ * before it returns.  All calls on one GPU share the array: calls that
+ * overlap in time on one GPU (from different host threads) race. */
+mpo_status_t mpo_absorb_gate_pair_noalloc(mpo_handle_t h, int32_t bond, const double* g_out,
+                                          const double* g_in, mpo_update_info_t* info);
+
 /* Batched absorption of `count` updates on pairwise non-adjacent bonds
  * (|bond_a - bond_b| >= 2), which are independent in Vidal form.  g_out / g_in
  * hold `count` gates of 32 doubles each; a NULL array means identity for all,

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -53,6 +54,38 @@ inline void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw HipError{e, what};
 }
 struct NoMem {};
+// The allocation-free absorption asked for more workspace than the static
+// scratch array holds.
+struct ScratchFull {
+  size_t need, cap;
+};
+
+// Workspace of mpo_absorb_gate_pair_noalloc: a fixed device array, one copy
+// per GPU, held until the process ends.  Host code never passes `scratch`
+// itself to a kernel (in host code the name is only a stand-in); it uses the
+// address returned by hipGetSymbolAddress for the current device.
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+void* scratch_address() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) throw HipError{e, "hipGetDevice"};
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) throw HipError{hipErrorInvalidDevice, "device index"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) throw HipError{e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch symbol address"};
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
 
 // Workspace of one problem in a batch; grows on demand, never shrinks.
 struct Slot {
@@ -162,6 +195,14 @@ struct mpo_ctx {
   // per-commit backups of the two sites and the bond vector of an unswap commit
   std::vector<void*> bk;
   std::vector<size_t> bk_cap;
+  // Allocation-free absorption: `scratch_dev` is the device address of the
+  // static scratch array on this handle's device (looked up at init).  While
+  // `carve_base` is set, every workspace request is carved out of it instead
+  // of being allocated; `scratch_slots` (sized at init) stand in for `slots`.
+  void* scratch_dev = nullptr;
+  char* carve_base = nullptr;
+  size_t carve_off = 0, carve_cap = 0;
+  std::vector<Slot> scratch_slots;
 };
 
 namespace {
@@ -169,7 +210,7 @@ namespace {
 // Device memory of a handle: through the caller's hooks when mpo_config_t
 // provides them (e.g. PyTorch's caching allocator), else hipMalloc / hipFree.
 void dfree(mpo_ctx* h, void* p) {
-  if (!p) return;
+  if (!p || h->carve_base) return;
   if (h->cfg.free) h->cfg.free(p, h->cfg.alloc_ctx);
   else (void)hipFree(p);
 }
@@ -177,6 +218,12 @@ void* dalloc(mpo_ctx* h, size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 16;
   bytes = (bytes + 255) / 256 * 256;
+  if (h->carve_base) {
+    if (h->carve_off + bytes > h->carve_cap) throw ScratchFull{h->carve_off + bytes, h->carve_cap};
+    p = h->carve_base + h->carve_off;
+    h->carve_off += bytes;
+    return p;
+  }
   if (h->cfg.alloc) {
     p = h->cfg.alloc(bytes, h->cfg.alloc_ctx);
     if (!p) throw NoMem{};
@@ -295,7 +342,7 @@ void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY, size_t nwp, size_t nw2)
   if (!s.qcnt) {
     s.qpart = (double*)dalloc(h, 2 * QMW_MAXWG * QMW_VALS * sizeof(double));
     s.qcnt = (unsigned*)dalloc(h, sizeof(unsigned));
-    hip_check(hipMemset(s.qcnt, 0, sizeof(unsigned)), "QR barrier counter");
+    hip_check(hipMemsetAsync(s.qcnt, 0, sizeof(unsigned), h->stream), "QR barrier counter");
     s.qbase = 0;
   }
   if (s.cap_r < r) {
@@ -700,6 +747,10 @@ mpo_status_t guarded(mpo_ctx* h, F&& f) {
     return fail(h, MPO_EHIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
   } catch (const NoMem&) {
     return fail(h, MPO_ENOMEM, "device allocation failed");
+  } catch (const ScratchFull& e) {
+    return fail(h, MPO_EINVAL, "update needs more than the " + std::to_string(e.cap >> 20) +
+                                   " MiB of static scratch (at least " + std::to_string((e.need + 1048575) >> 20) +
+                                   " MiB)");
   } catch (const std::bad_alloc&) {
     return fail(h, MPO_ENOMEM, "host allocation failed");
   } catch (...) {
@@ -1018,6 +1069,7 @@ int64_t pow4_capped(int e, int64_t cap) {
 void init_workspace(mpo_ctx* h) {
   h->ones = (double*)dalloc(h, sizeof(double));
   h->slots.assign(MAXB, Slot{});
+  h->scratch_slots.assign(MAXB, Slot{});
   h->states = (JacState*)dalloc(h, MAXB * sizeof(JacState));
   h->results = (TruncResult*)dalloc(h, MAXB * sizeof(TruncResult));
   h->d_gates = (double*)dalloc(h, MAXB * 64 * sizeof(double));
@@ -1128,6 +1180,7 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
     }
     for (int b = 0; b < n - 1; ++b) h->lam[b] = (double*)dalloc(h, h->bond_cap[b] * sizeof(double));
     init_workspace(h);
+    h->scratch_dev = scratch_address();
     const double one = 1.0;
     const double hv = 0.70710678118654752440;
     const double idd[8] = {hv, 0, 0, 0, 0, 0, hv, 0};
@@ -1317,6 +1370,44 @@ static mpo_status_t absorb_common(mpo_handle_t h, int32_t count, const int32_t* 
 mpo_status_t mpo_absorb_gate_pair(mpo_handle_t h, int32_t bond, const double* g_out, const double* g_in,
                                   mpo_update_info_t* info) {
   return absorb_common(h, 1, &bond, g_out, g_in, info, false);
+}
+
+mpo_status_t mpo_absorb_gate_pair_noalloc(mpo_handle_t h, int32_t bond, const double* g_out, const double* g_in,
+                                          mpo_update_info_t* info) {
+  if (!h) return MPO_EINVAL;
+  if (h->prof_on) return fail(h, MPO_EINVAL, "kernel timing is on (it creates events); switch it off first");
+  if (!h->scratch_dev) return fail(h, MPO_EHIP, "no scratch address for this handle's device");
+  // Every workspace request of the update is carved out of the static
+  // scratch array; the handle's own grown workspaces are set aside meanwhile.
+  struct Carve {
+    mpo_ctx* h;
+    void* ns[4];
+    size_t cap_ns, cap_l;
+    explicit Carve(mpo_ctx* x) : h(x) {
+      std::swap(h->slots, h->scratch_slots);
+      for (Slot& s : h->slots) s = Slot{};
+      ns[0] = h->ns_x, ns[1] = h->ns_s, ns[2] = h->ns_y, ns[3] = h->lbuf;
+      h->ns_x = h->ns_s = h->ns_y = h->lbuf = nullptr;
+      cap_ns = h->cap_ns, cap_l = h->cap_l;
+      h->cap_ns = h->cap_l = 0;
+      h->carve_base = (char*)h->scratch_dev;
+      h->carve_off = 0;
+      h->carve_cap = SCRATCH_BYTES;
+    }
+    ~Carve() {
+      h->carve_base = nullptr;
+      h->carve_off = h->carve_cap = 0;
+      h->ns_x = ns[0], h->ns_s = ns[1], h->ns_y = ns[2], h->lbuf = ns[3];
+      h->cap_ns = cap_ns, h->cap_l = cap_l;
+      std::swap(h->slots, h->scratch_slots);
+    }
+  } carve(h);
+  mpo_status_t s = absorb_common(h, 1, &bond, g_out, g_in, info, false);
+  // The write-back kernels read the scratch array: they finish before the
+  // call returns, so that the next call may reuse it.
+  const hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess && s >= 0) s = fail(h, MPO_EHIP, std::string("stream sync: ") + hipGetErrorString(e));
+  return s;
 }
 
 mpo_status_t mpo_absorb_batch(mpo_handle_t h, int32_t count, const int32_t* bonds, const double* g_out,

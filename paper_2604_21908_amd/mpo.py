@@ -21,7 +21,7 @@ STATUS = {0: "MPO_OK", 1: "MPO_WARN_NOCONV", -1: "MPO_EINVAL", -2: "MPO_ENOMEM",
           -4: "MPO_ENUMERIC", -5: "MPO_EOVERFLOW"}
 SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
 
-EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_batch", "mpo_unswap_sweep",
+EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_gate_pair_noalloc", "mpo_absorb_batch", "mpo_unswap_sweep",
             "mpo_extract_peak", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
             "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_tau_reached", "mpo_trial_swap", "mpo_counters",
             "mpo_profile", "mpo_last_error", "mpo_version",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     dp = ctypes.POINTER(ctypes.c_double)
     lib.mpo_init_identity.argtypes = [ctypes.POINTER(MpoConfig), P, ctypes.POINTER(P)]
     lib.mpo_absorb_gate_pair.argtypes = [P, I32, dp, dp, ctypes.POINTER(UpdateInfo)]
+    lib.mpo_absorb_gate_pair_noalloc.argtypes = [P, I32, dp, dp, ctypes.POINTER(UpdateInfo)]
     lib.mpo_absorb_batch.argtypes = [P, I32, ctypes.POINTER(I32), dp, dp, ctypes.POINTER(UpdateInfo)]
     lib.mpo_unswap_sweep.argtypes = [P, ctypes.POINTER(UnswapOpts), ctypes.POINTER(SwapEntry), I32,
                                      ctypes.POINTER(I32)]
@@ -236,6 +237,17 @@ class MPO:
         info = UpdateInfo()
         s = self.lib.mpo_absorb_gate_pair(self.h, bond, po, pi, ctypes.byref(info))
         self._check(s, "mpo_absorb_gate_pair", ok=(0, 1))
+        return dict(k=info.chi_new, sweeps=info.sweeps, discarded=info.discarded_weight,
+                    total=info.total_weight, rotations=info.panel_rotations, noconv=(s == 1))
+
+    def absorb_noalloc(self, bond: int, g_out=None, g_in=None) -> dict:
+        """mpo_absorb_gate_pair_noalloc: the same update with its workspace
+        in the library's static scratch array (no device allocation)."""
+        ko, po = _gate_ptr(g_out)
+        ki, pi = _gate_ptr(g_in)
+        info = UpdateInfo()
+        s = self.lib.mpo_absorb_gate_pair_noalloc(self.h, bond, po, pi, ctypes.byref(info))
+        self._check(s, "mpo_absorb_gate_pair_noalloc", ok=(0, 1))
         return dict(k=info.chi_new, sweeps=info.sweeps, discarded=info.discarded_weight,
                     total=info.total_weight, rotations=info.panel_rotations, noconv=(s == 1))
 
