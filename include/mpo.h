@@ -99,7 +99,11 @@ typedef struct {
   int32_t cutoff_mode;    /* mpo_cutoff_mode_t                                  */
   int32_t precision;      /* mpo_precision_t                                    */
   int32_t max_sweeps;     /* Jacobi sweep cap per SVD; 0 = default (30)          */
-  double jacobi_tol;      /* off-diagonal tolerance; 0 = default for precision */
+  double jacobi_tol;      /* Jacobi off-diagonal tolerance |g_ij| <= tol sqrt(g_ii g_jj);
+                             0 = default: 8 sqrt(m) eps of the working precision
+                             (FP64, FP32), 1e-3 for the split-BF16 sweeps of
+                             the mixed form (whose values are re-derived to
+                             second order in it)                             */
   int64_t tau_elems;      /* Alg. 1 threshold tau on size(M) (App. A.4), read by
                              mpo_tau_reached; <= 0 = never reached            */
   /* Device-memory hooks.  When `alloc` is non-NULL every device buffer of the
@@ -195,6 +199,19 @@ mpo_status_t mpo_unswap_sweep(mpo_handle_t h, const mpo_unswap_opts_t* opts, mpo
  * that string) and *norm2 = <psi|psi>.  Either pointer may be NULL. */
 mpo_status_t mpo_extract_peak(mpo_handle_t h, uint8_t* bits_per_site, double* prob, double* norm2);
 
+/* Sec. II.C (sampling the output state): M|0...0> as an MPS, `count`
+ * samples drawn from the left, site i's bit of sample s being 0 when
+ * uniforms[s * n + i] < P(bit 0 | the sample's bits at sites < i), the
+ * conditionals computed exactly in FP64 from the right environments.  The
+ * random numbers are the caller's (count x n doubles in [0, 1), row-major),
+ * so a sample is a deterministic function of its row.  site_bits[count * n]
+ * receives the bits per site (row s = sample s); probs[count] (may be NULL)
+ * the normalised probability of each sampled string.  MPO_ENUMERIC when a
+ * conditional weight is not finite.  Device workspace: the environments
+ * (sum_i chi_i^2 complex128) plus about 5 * count * max chi complex128. */
+mpo_status_t mpo_sample(mpo_handle_t h, int32_t count, const double* uniforms, uint8_t* site_bits,
+                        double* probs);
+
 /* ---- helpers ------------------------------------------------------------ */
 void mpo_free(mpo_handle_t h);
 /* dims[n-1] receives chi_0 .. chi_{n-2}. */
@@ -214,6 +231,13 @@ mpo_status_t mpo_read_site(mpo_handle_t h, int32_t site, double* out, int64_t ca
 mpo_status_t mpo_load_state(mpo_handle_t h, const int32_t* dims, const double* sites,
                             const double* lams);
 mpo_status_t mpo_sync(mpo_handle_t h);
+/* App. A.3 (adaptive side selection absorbs the next layer of each side into
+ * its own copy of the MPO and keeps the smaller): makes dst an exact copy of
+ * src's state (bond dimensions, site tensors, bond vectors).  Both handles
+ * must have the same n, precision and chi_max.  Waits for src's stream, copies
+ * device to device on dst's stream and returns when the copy is complete.
+ * dst's counters are kept; its unswap-trial memo no longer applies. */
+mpo_status_t mpo_copy_state(mpo_handle_t dst, mpo_handle_t src);
 /* Alg. 1's test "size(M) >= tau" with tau = cfg.tau_elems: *reached = 1 when
  * it holds (never when tau_elems <= 0); *size (may be NULL) gets size(M). */
 mpo_status_t mpo_tau_reached(mpo_handle_t h, int32_t* reached, int64_t* size);

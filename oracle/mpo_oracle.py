@@ -557,19 +557,30 @@ class Contraction:
                                size=self.m.size(), log=list(log)))
         return log
 
+    def gates_absorbed(self) -> int:
+        return sum(2 if t.get("fused") else 1 for t in self.trace if t.get("stage") == "absorb")
+
     def run(self) -> OracleResult:
         cfg = self.cfg
+        # size(M) against gates absorbed after every absorption step and
+        # unswapping stage: the sawtooth of Sec. III.A
+        self.sizes = []
         while self.left or self.right:
             # every absorption phase takes at least one layer pair, so the loop
             # progresses even when unswapping cannot bring size(M) below tau
             self.absorb_step()
+            self.sizes.append(("absorb", self.gates_absorbed(), self.m.size()))
             while self.m.size() < cfg.tau and (self.left or self.right):
                 self.absorb_step()
+                self.sizes.append(("absorb", self.gates_absorbed(), self.m.size()))
             self.unswap()
+            self.sizes.append(("unswap", self.gates_absorbed(), self.m.size()))
         site_bits, p, norm2 = extract_peak(self.m)
         bits = np.array([site_bits[self.lay_l.site_of[q]] for q in range(self.n)], dtype=np.uint8)
-        return OracleResult(bits, p, norm2, site_bits, list(self.lay_l.site_of),
-                            list(self.lay_r.site_of), self.trace, self.m)
+        res = OracleResult(bits, p, norm2, site_bits, list(self.lay_l.site_of),
+                           list(self.lay_r.site_of), self.trace, self.m)
+        res.sizes = list(self.sizes)
+        return res
 
 
 def contract(n: int, gates, cfg: OracleConfig) -> OracleResult:

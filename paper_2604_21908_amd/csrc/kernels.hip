@@ -8,6 +8,7 @@
 //   k_colnorms     singular values as column norms (FP64)
 //   k_sort_trunc   descending sort + truncation decision (FP64)
 //   k_env / k_greedy  peak readout of M|0...0> (FP64)
+//   k_sample_pick  one site of conditional sampling of M|0...0> for many samples (FP64)
 #include "common.h"
 
 namespace mpo {
@@ -508,6 +509,61 @@ __global__ __launch_bounds__(1024) void k_greedy(const cx<T>* site, int chil, in
   for (int b = tid; b < chir; b += blockDim.x) vout[b] = cx<double>{w[b].re * inv, w[b].im * inv};
 }
 
+// Sampling (one workgroup per sample s): with X_o = L A_o and Y_o = X_o E
+// (row s of each, cr entries), p_o = Re sum_c Y_o[c] conj(X_o[c]); the bit is
+// 0 when u < p_0 / (p_0 + p_1); the log of the chosen conditional is added to
+// logp[s] and the next left vector is X_o / sqrt(p_o).  The sums run in a
+// fixed order (strided per thread, then a tree), so a sample's decisions do
+// not depend on the launch.  A non-finite or non-positive p_0 + p_1 sets
+// *bad.
+__global__ __launch_bounds__(256) void k_sample_pick(const cx<double>* X, const cx<double>* Y, int count, int cr,
+                                                     const double* u, int ustride, cx<double>* Lout, double* logp,
+                                                     unsigned char* bits, int bstride, int* bad) {
+  __shared__ double red[2][256];
+  __shared__ int choice;
+  __shared__ double scale;
+  const int s = blockIdx.x, tid = threadIdx.x;
+  if (s >= count) return;
+  const size_t plane = (size_t)count * cr;
+  const cx<double>* x0 = X + (size_t)s * cr;
+  const cx<double>* y0 = Y + (size_t)s * cr;
+  double p0 = 0, p1 = 0;
+  for (int c = tid; c < cr; c += 256) {
+    const cx<double> a0 = x0[c], b0 = y0[c], a1 = x0[plane + c], b1 = y0[plane + c];
+    p0 += b0.re * a0.re + b0.im * a0.im;
+    p1 += b1.re * a1.re + b1.im * a1.im;
+  }
+  red[0][tid] = p0;
+  red[1][tid] = p1;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double q0 = red[0][0], q1 = red[1][0], tot = q0 + q1;
+    int o = 0;
+    if (!(tot > 0) || !isfinite(tot) || q0 < 0 || q1 < 0) {
+      *bad = 1;
+      scale = 0;
+    } else {
+      o = (u[(size_t)s * ustride] < q0 / tot) ? 0 : 1;
+      const double q = o ? q1 : q0;
+      logp[s] += log(q / tot);
+      scale = q > 0 ? 1.0 / sqrt(q) : 0.0;
+    }
+    choice = o;
+    bits[(size_t)s * bstride] = (unsigned char)o;
+  }
+  __syncthreads();
+  const cx<double>* xs = x0 + (choice ? plane : 0);
+  const double f = scale;
+  for (int c = tid; c < cr; c += 256) Lout[(size_t)s * cr + c] = cx<double>{xs[c].re * f, xs[c].im * f};
+}
+
 template <typename TD, typename TS>
 __global__ void k_convert(cx<TD>* dst, const cx<TS>* src, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -553,6 +609,11 @@ template <typename T>
 void launch_greedy(const cx<T>* site, int chil, int chir, const cx<double>* E, const cx<double>* v,
                    cx<double>* vout, cx<double>* work, unsigned char* bit, double* logp, hipStream_t s) {
   hipLaunchKernelGGL(k_greedy<T>, dim3(1), dim3(1024), 0, s, site, chil, chir, E, v, vout, work, bit, logp);
+}
+void launch_sample_pick(const cx<double>* X, const cx<double>* Y, int count, int cr, const double* u, int ustride,
+                        cx<double>* Lout, double* logp, unsigned char* bits, int bstride, int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_pick, dim3(count), dim3(256), 0, s, X, Y, count, cr, u, ustride, Lout, logp, bits,
+                     bstride, bad);
 }
 template <typename TD, typename TS>
 void launch_convert(cx<TD>* d, const cx<TS>* src, size_t n, hipStream_t s) {

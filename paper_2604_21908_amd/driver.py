@@ -38,6 +38,8 @@ class RunConfig:
     relaxed: bool = False
     max_unswap_iters: int = 20
     waves: bool = True                # batch independent updates
+    side: str = "both"                # "both" (Alg. 1), "adaptive" or "fixed" (App. A.3)
+    fixed_freq: Tuple[int, int] = (1, 1)   # fixed mode: layers of C_L, then of C_R, per period
 
 
 @dataclasses.dataclass
@@ -82,6 +84,12 @@ class Wires:
     def __init__(self, n: int):
         self.site_of = np.arange(n)
         self.logical_at = np.arange(n)
+
+    def copy(self) -> "Wires":
+        w = Wires.__new__(Wires)
+        w.site_of = self.site_of.copy()
+        w.logical_at = self.logical_at.copy()
+        return w
 
     def exchange(self, bond: int) -> None:
         a, b = self.logical_at[bond], self.logical_at[bond + 1]
@@ -162,26 +170,40 @@ class Contractor:
             raise ValueError("tau must be positive (or inf for no unswapping)")
         # size(M) is an integer, so size >= ceil(tau) exactly when size >= tau
         tau_elems = int(np.ceil(cfg.tau)) if np.isfinite(cfg.tau) else 0
-        self.m = _mpo.MPO(self.n, cfg.chi_max, cfg.cutoff, mode, _mpo.PRECISIONS[cfg.precision], stream=stream,
-                          tau_elems=tau_elems)
+        self._mk = lambda: _mpo.MPO(self.n, cfg.chi_max, cfg.cutoff, mode, _mpo.PRECISIONS[cfg.precision],
+                                    stream=stream, tau_elems=tau_elems)
+        self.m = self._mk()
+        self.m2 = None                  # the second copy of adaptive side selection
+        self.steps = 0
+        self.trial_absorb_updates = 0
+        self.gates_absorbed = 0
+        self.sizes: List[Tuple[str, int, int]] = []
+        if cfg.side not in ("both", "adaptive", "fixed"):
+            raise ValueError(f"side must be both, adaptive or fixed, not {cfg.side!r}")
 
     def close(self):
         self.m.close()
+        if self.m2 is not None:
+            self.m2.close()
 
-    def _execute(self, ups: List[Update]):
-        if not ups:
-            return
+    def _run_updates(self, m, ups: List[Update]) -> List[dict]:
         infos: List[Optional[dict]] = [None] * len(ups)
+        if not ups:
+            return infos
         if self.cfg.waves:
             for wave in wave_split([u.bond for u in ups]):
-                res = self.m.absorb_batch([ups[i].bond for i in wave], [ups[i].g_out for i in wave],
-                                          [ups[i].g_in for i in wave])
+                res = m.absorb_batch([ups[i].bond for i in wave], [ups[i].g_out for i in wave],
+                                     [ups[i].g_in for i in wave])
                 for i, r in zip(wave, res):
                     infos[i] = r
         else:
             for i, u in enumerate(ups):
-                infos[i] = self.m.absorb(u.bond, u.g_out, u.g_in)
-        self.record(ups, infos)
+                infos[i] = m.absorb(u.bond, u.g_out, u.g_in)
+        return infos
+
+    def _execute(self, ups: List[Update]):
+        if ups:
+            self.record(ups, self._run_updates(self.m, ups))
 
     def plan_absorb(self) -> List[Update]:
         """Pops the innermost layer of each side and returns the ordered
@@ -194,10 +216,63 @@ class Contractor:
         for u, r in zip(ups, infos):
             self.trace.append(dict(stage=u.stage, bond=u.bond, k=r["k"], discarded=r["discarded"],
                                    total=r["total"], sweeps=r["sweeps"]))
+            if u.stage == "absorb":      # a fused update absorbs one gate of each half
+                self.gates_absorbed += (u.g_out is not None) + (u.g_in is not None)
         self.bond_updates += len(ups)
 
+    def note_size(self, stage: str) -> None:
+        """size(M) against the circuit gates absorbed so far (the sawtooth
+        of Sec. III.A): one point after every absorption step and unswap stage."""
+        self.sizes.append((stage, self.gates_absorbed, self.m.total_elements()))
+
     def absorb_step(self):
-        self._execute(self.plan_absorb())
+        """One absorption step under the configured side selection (App. A.3):
+        Alg. 1's alternation takes a layer of each side; the fixed mode takes
+        f_L layers of C_L, then f_R of C_R, in turn; the adaptive mode
+        absorbs the next layer of each side into its own copy of the MPO and
+        keeps the copy with the smaller size(M) (equal: the left one).  Once
+        one side has no layers left, every mode takes the other."""
+        mode = self.cfg.side
+        if mode == "both" or not (self.c_left and self.c_right):
+            taken = "L" if self.c_left else "R"
+            self._execute(self.plan_absorb())
+            if mode == "fixed":                # one side is used up
+                self.trace.append(dict(stage="layer", taken=taken))
+        elif mode == "fixed":
+            fl, fr = self.cfg.fixed_freq
+            if self.steps % (fl + fr) < fl:
+                self._execute(plan_step(self.c_left.pop(0), [], self.out_w, self.in_w))
+                self.trace.append(dict(stage="layer", taken="L"))
+            else:
+                self._execute(plan_step([], self.c_right.pop(0), self.out_w, self.in_w))
+                self.trace.append(dict(stage="layer", taken="R"))
+        else:
+            self._absorb_adaptive()
+        self.steps += 1
+
+    def _absorb_adaptive(self):
+        if self.m2 is None:
+            self.m2 = self._mk()
+        self.m2.copy_from(self.m)
+        wl = (self.out_w.copy(), self.in_w.copy())
+        ups_l = plan_step(self.c_left[0], [], *wl)
+        inf_l = self._run_updates(self.m, ups_l)
+        wr = (self.out_w.copy(), self.in_w.copy())
+        ups_r = plan_step([], self.c_right[0], *wr)
+        inf_r = self._run_updates(self.m2, ups_r)
+        sl, sr = self.m.total_elements(), self.m2.total_elements()
+        if sl <= sr:
+            self.c_left.pop(0)
+            self.out_w, self.in_w = wl
+            self.record(ups_l, inf_l)
+            self.trial_absorb_updates += len(ups_r)
+        else:
+            self.c_right.pop(0)
+            self.out_w, self.in_w = wr
+            self.m, self.m2 = self.m2, self.m
+            self.record(ups_r, inf_r)
+            self.trial_absorb_updates += len(ups_l)
+        self.trace.append(dict(stage="side", side="L" if sl <= sr else "R", size_left=sl, size_right=sr))
 
     def finish(self) -> RunResult:
         site_bits, p, n2 = self.m.extract_peak()
@@ -231,9 +306,12 @@ class Contractor:
         t0 = time.perf_counter()
         while self.c_left or self.c_right:
             self.absorb_step()
+            self.note_size("absorb")
             while not self.m.tau_reached() and (self.c_left or self.c_right):
                 self.absorb_step()
+                self.note_size("absorb")
             self.unswap()
+            self.note_size("unswap")
         site_bits, p, n2 = self.m.extract_peak()
         secs = time.perf_counter() - t0
         bits = site_bits[self.out_w.site_of]

@@ -83,9 +83,81 @@ def _load_state(path, c):
     return steps, float(z["seconds"]), int(z["max_k"])
 
 
+def sample_report(c, circ, count, p_exact, seed=2026):
+    """Sec. II.C / Fig. 4 on a contracted circuit: `count` samples of the
+    output state (mpo_sample, seeded uniforms), mapped to logical qubits by
+    the output layout; the 20 most frequent strings with their counts, the
+    planted peak's sampled weight and its exact probability p*."""
+    rng = np.random.default_rng(seed)
+    u = rng.random((count, c.n))
+    t0 = time.perf_counter()
+    site_bits, probs = c.m.sample(u)
+    secs = time.perf_counter() - t0
+    logical = site_bits[:, c.out_w.site_of]               # column q = logical qubit q
+    keys = ["".join(map(str, row)) for row in logical]
+    hist = {}
+    for k in keys:
+        hist[k] = hist.get(k, 0) + 1
+    top = sorted(hist.items(), key=lambda kv: (-kv[1], kv[0]))[:20]
+    peak = "".join(map(str, circ.peak))
+    return {"samples": count, "seed": seed, "seconds": round(secs, 3),
+            "top20": [[k, v] for k, v in top], "peak": peak, "peak_count": hist.get(peak, 0),
+            "sampled_peak_weight": hist.get(peak, 0) / count, "exact_p_peak": p_exact,
+            "distinct": len(hist)}
+
+
+def sawtooth(a):
+    """Sec. III.A / Fig. 3 and App. A.1-A.2 on one seeded circuit: for every
+    tau, unswapping schedule (sequential, parallel) and acceptance (strict,
+    relaxed), size(M) after each absorption step and each unswapping stage
+    against the gates absorbed, with time-to-peak, bond updates, SWAP-trial
+    SVDs and the peak check.  One JSON line per run, then a summary."""
+    circ = cg.config_circuit(a.config, reading=a.reading)
+    prec = a.precision or "fp32"
+    runs = []
+    for tau in [float(x) for x in a.taus.split(",")]:
+        for sched in ("sequential", "parallel"):
+            for relaxed in (False, True):
+                c = dr.Contractor(circ, dr.RunConfig(chi_max=a.chi, cutoff=1e-8, cutoff_mode="weight",
+                                                     precision=prec, tau=tau, unswap=sched, relaxed=relaxed,
+                                                     side=a.side))
+                t0 = time.perf_counter()
+                try:
+                    res = c.run()
+                    secs = time.perf_counter() - t0
+                    cnt = c.m.counters()
+                finally:
+                    c.close()
+                stages = [(g, sz) for st, g, sz in c.sizes if st == "unswap"]
+                pre = [sz for st, g, sz in c.sizes]
+                drops = []
+                for j, (st, g, sz) in enumerate(c.sizes):
+                    if st == "unswap" and j > 0:
+                        drops.append(c.sizes[j - 1][2] - sz)
+                run = {"tau": tau, "schedule": sched, "relaxed": relaxed, "precision": prec,
+                       "seconds": round(secs, 3), "bond_updates": res.bond_updates,
+                       "trial_svds": cnt["trials"], "trials_reused": cnt["trials_reused"],
+                       "unswap_stages": len(stages), "max_size": max(pre) if pre else 0,
+                       "mean_unswap_drop": round(float(np.mean(drops)), 1) if drops else 0.0,
+                       "peak_ok": bool((res.bits == circ.peak).all()), "p_peak": res.prob,
+                       "sizes": [[st[0], g, sz] for st, g, sz in c.sizes]}
+                runs.append(run)
+                print(json.dumps(run), flush=True)
+    best = min(runs, key=lambda r: r["seconds"])
+    print(json.dumps({"form": "sawtooth", "config": a.config, "n": circ.n, "reading": a.reading,
+                      "chi_max": a.chi, "side": a.side, "runs": len(runs),
+                      "fastest": {k: best[k] for k in ("tau", "schedule", "relaxed", "seconds")},
+                      "all_peaks_ok": all(r["peak_ok"] for r in runs),
+                      "table": [{k: r[k] for k in ("tau", "schedule", "relaxed", "seconds", "bond_updates",
+                                                   "trial_svds", "unswap_stages", "max_size", "peak_ok")}
+                                for r in runs]}), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("form", choices=["batch", "serve", "peak"])
+    ap.add_argument("form", choices=["batch", "serve", "peak", "sawtooth"])
+    ap.add_argument("--taus", default="5e3,2e4,1e5", help="sawtooth: the tau values to run")
+    ap.add_argument("--reading", default="A", choices=["A", "B"], help="sawtooth/peak: circuit reading")
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--chi", type=int, default=256)
     ap.add_argument("--time-limit", type=float, default=0.0,
@@ -101,6 +173,11 @@ def main(argv=None):
     ap.add_argument("--state", default="", help="peak: checkpoint file (.npz)")
     ap.add_argument("--resume", action="store_true", help="peak: continue from --state")
     ap.add_argument("--precisions", default="fp32,mixed")
+    ap.add_argument("--side", default="both", choices=["both", "adaptive", "fixed"],
+                    help="peak: side selection of the absorption stage (Alg. 1 alternation, or App. A.3)")
+    ap.add_argument("--samples", type=int, default=0,
+                    help="peak: after the contraction draw this many seeded samples of the output state (Sec. II.C) "
+                         "and report the top-20 histogram and the sampled peak weight beside p*")
     ap.add_argument("--count", type=int, default=16)
     ap.add_argument("--tau", type=float, default=1e5)
     ap.add_argument("--rate", type=float, default=1.0)
@@ -110,14 +187,17 @@ def main(argv=None):
     ap.add_argument("--max-n", type=int, default=64, help="skip workload circuits wider than this")
     ap.add_argument("--chi-cap", type=int, default=1024, help="clip the workload's chi_max to this")
     a = ap.parse_args(argv)
+    if a.form == "sawtooth":
+        sawtooth(a)
+        return
     if a.form == "peak":
         import time as _t
-        circ = cg.config_circuit(a.config, reading="A")
+        circ = cg.config_circuit(a.config, reading=a.reading)
         tau = a.tau if a.tau != 1e5 else 2e4
         out = {"form": "peak", "config": a.config, "n": circ.n, "chi_max": a.chi, "tau": tau, "runs": []}
         for prec in a.precisions.split(","):
             c = dr.Contractor(circ, dr.RunConfig(chi_max=a.chi, cutoff=1e-8, cutoff_mode="weight", precision=prec,
-                                                 tau=tau, unswap="parallel"))
+                                                 tau=tau, unswap="parallel", side=a.side))
             steps = [0]
             done_s, max_k0 = 0.0, 1
             if a.resume:
@@ -182,14 +262,20 @@ def main(argv=None):
                 c.close()
                 print(json.dumps(out["runs"][-1]), flush=True)
                 continue
+            sampled = None
+            if a.samples:
+                sampled = sample_report(c, circ, a.samples, res.prob)
             c.close()
             ks = [x["k"] for x in res.trace if "k" in x]
             secs = done_s + res.seconds
-            out["runs"].append({"precision": prec, "finished": True, "time_to_peak_s": round(secs, 3),
+            out["runs"].append({"precision": prec, "side": a.side, "finished": True, "time_to_peak_s": round(secs, 3),
                                 "resumed": bool(a.resume), "bond_updates": res.bond_updates,
+                                "trial_absorb_updates": c.trial_absorb_updates,
                                 "max_chi": max([max_k0] + ks),
                                 "peak_ok": bool((res.bits == circ.peak).all()), "p_peak": res.prob,
                                 "updates_per_s": round(res.bond_updates / secs, 1)})
+            if sampled:
+                out["runs"][-1]["sampling"] = sampled
             print(json.dumps(out["runs"][-1]), flush=True)
         print(json.dumps(out), flush=True)
         return

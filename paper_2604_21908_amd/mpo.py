@@ -22,8 +22,8 @@ STATUS = {0: "MPO_OK", 1: "MPO_WARN_NOCONV", -1: "MPO_EINVAL", -2: "MPO_ENOMEM",
 SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
 
 EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_gate_pair_noalloc", "mpo_absorb_batch", "mpo_unswap_sweep",
-            "mpo_extract_peak", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
-            "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_tau_reached", "mpo_trial_swap", "mpo_counters",
+            "mpo_extract_peak", "mpo_sample", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
+            "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_copy_state", "mpo_tau_reached", "mpo_trial_swap", "mpo_counters",
             "mpo_profile", "mpo_last_error", "mpo_version",
             "mpo_group_create", "mpo_group_free", "mpo_group_absorb", "mpo_group_unswap", "mpo_group_profile",
             "mpo_group_last_error"]
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mpo_unswap_sweep.argtypes = [P, ctypes.POINTER(UnswapOpts), ctypes.POINTER(SwapEntry), I32,
                                      ctypes.POINTER(I32)]
     lib.mpo_extract_peak.argtypes = [P, ctypes.POINTER(ctypes.c_uint8), dp, dp]
+    lib.mpo_sample.argtypes = [P, I32, dp, ctypes.POINTER(ctypes.c_uint8), dp]
     lib.mpo_free.argtypes = [P]
     lib.mpo_free.restype = None
     lib.mpo_bond_dims.argtypes = [P, ctypes.POINTER(I32)]
@@ -97,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mpo_read_site.argtypes = [P, I32, dp, I64, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.mpo_load_state.argtypes = [P, ctypes.POINTER(I32), dp, dp]
     lib.mpo_sync.argtypes = [P]
+    lib.mpo_copy_state.argtypes = [P, P]
     lib.mpo_tau_reached.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I64)]
     lib.mpo_trial_swap.argtypes = [P, I32, I32, ctypes.POINTER(UpdateInfo)]
     lib.mpo_counters.argtypes = [P, ctypes.POINTER(I64), I32]
@@ -287,6 +289,21 @@ class MPO:
         self._check(s, "mpo_extract_peak")
         return np.array(bits[:], dtype=np.uint8), p.value, n2.value
 
+    def sample(self, uniforms: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+        """mpo_sample: one sample per row of `uniforms` (count x n in [0, 1));
+        returns (site bits, count x n; probability of each sampled string)."""
+        u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
+        if u.ndim != 2 or u.shape[1] != self.n:
+            raise ValueError("uniforms must have shape (count, n)")
+        cnt = u.shape[0]
+        bits = np.zeros((cnt, self.n), dtype=np.uint8)
+        probs = np.zeros(cnt)
+        dp = ctypes.POINTER(ctypes.c_double)
+        s = self.lib.mpo_sample(self.h, cnt, u.ctypes.data_as(dp), bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                probs.ctypes.data_as(dp))
+        self._check(s, "mpo_sample")
+        return bits, probs
+
     def bond_dims(self) -> List[int]:
         d = (ctypes.c_int32 * (self.n - 1))()
         self._check(self.lib.mpo_bond_dims(self.h, d), "mpo_bond_dims")
@@ -328,6 +345,10 @@ class MPO:
 
     def sync(self):
         self._check(self.lib.mpo_sync(self.h), "mpo_sync")
+
+    def copy_from(self, other: "MPO") -> None:
+        """mpo_copy_state: this MPO becomes an exact copy of `other`."""
+        self._check(self.lib.mpo_copy_state(self.h, other.h), "mpo_copy_state")
 
     def tau_reached(self) -> bool:
         r = ctypes.c_int32()

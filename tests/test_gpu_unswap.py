@@ -34,6 +34,22 @@ def swap_mixed_state(n, seed, chi_max):
     return m
 
 
+def layered_swap_state(n, seed, chi_max=64):
+    """Haar gate pairs on every third bond, then four SWAP layers (left on
+    even bonds, right on odd, left on odd, right on even): the SWAPs raise
+    the bond dimensions to 16 and unswapping takes most of them back out over
+    several cycles."""
+    rng = np.random.default_rng(seed)
+    m = mo.OracleMPO(n)
+    for b in range(0, n - 1, 3):
+        mo.commit(m, mo.bond_update(m, b, cg.haar_su4(rng), cg.haar_su4(rng), chi_max, 1e-13, "rel_sv"))
+    for side, par in (("L", 0), ("R", 1), ("L", 1), ("R", 0)):
+        go, gi = mo.swap_gates(side)
+        for i in range(par, n - 1, 2):
+            mo.commit(m, mo.bond_update(m, i, go, gi, chi_max, 1e-13, "rel_sv"))
+    return m
+
+
 def gray(s, k, chi_max, cutoff, rel):
     """True when the discarded-weight decision k sits within relative `rel` of
     its threshold (the tail at k or at k - 1 is that close to cutoff * total);
@@ -56,7 +72,7 @@ def test_trial_rank_matches_oracle_outside_gray_zone(lib, prec):
     oracle's (full SVD of the same SWAP-gated theta) wherever the oracle's
     decision is not within the gray zone of the cutoff (1e-3 relative for
     FP32 and mixed, 1e-6 for FP64); kept weights agree to the tolerance."""
-    cutoff, chi_max = 1e-6, 48
+    cutoff, chi_max = 1e-6, 64
     rel = 1e-6 if prec == "fp64" else 1e-3
     tol = 1e-10 if prec == "fp64" else 1e-4
     checked = 0
@@ -87,7 +103,7 @@ def test_accepted_swaps_lower_their_bonds(lib, prec, schedule):
     and touches no other, so the sum of bond dimensions falls by at least the
     number of accepted swaps; the accepted swaps reproduce the oracle's log on
     this state (its decisions are far from the cutoff's gray zone)."""
-    m = swap_mixed_state(9, 7, 64)
+    m = layered_swap_state(9, 7)
     g = lib.MPO(m.n, 64, 1e-8, 1, PREC[prec])
     g.load_state(m.B, m.lam)
     before = sum(g.bond_dims())
@@ -108,11 +124,7 @@ def test_trial_reuse_is_exact(lib, prec, monkeypatch):
     """Reusing the result of a trial whose B_b, B_b+1 and lambda_b-1 are
     unchanged is bit-identical to running it again: logs, bond values and
     tensors equal bit for bit with the memo on and off; the memo is used."""
-    m = swap_mixed_state(10, 4, 64)
-    for sd in ("L", "R"):                      # two more SWAP layers: several cycles
-        for i in range(1, m.n - 1, 2):
-            go, gi = mo.swap_gates(sd)
-            mo.commit(m, mo.bond_update(m, i, go, gi, 64, 1e-13, "rel_sv"))
+    m = layered_swap_state(10, 4)
 
     def run(reuse):
         monkeypatch.setenv("MPO_TRIAL_REUSE", "1" if reuse else "0")
