@@ -247,7 +247,9 @@ mpo_status_t mpo_tau_reached(mpo_handle_t h, int32_t* reached, int64_t* size);
 mpo_status_t mpo_trial_swap(mpo_handle_t h, int32_t bond, int32_t side, mpo_update_info_t* info);
 /* Counters since init: out[0] committed bond updates, out[1] SWAP-trial SVDs
  * run, out[2] trials served from the unchanged-input memo, out[3] unswap
- * commits undone, out[4] device allocations made through the alloc hook.
+ * commits undone, out[4] device allocations made through the alloc hook,
+ * out[5] Jacobi sweeps replayed from a captured graph, out[6] sweep graphs
+ * captured.
  * Up to `cap` entries are written. */
 mpo_status_t mpo_counters(mpo_handle_t h, int64_t* out, int32_t cap);
 
@@ -304,6 +306,22 @@ enum {
   MPO_PROF_CLASSES = 11
 };
 mpo_status_t mpo_profile(mpo_handle_t h, int32_t on, double* ms_out, int64_t* launches_out);
+/* Launch choices of the Jacobi sweeps (batching form): per bucket (precision,
+ * operand width rounded up to a power of two, batch size class) the rotation's
+ * row chunk (64, 128 or 256 rows) and whether a sweep is captured as a HIP
+ * graph and replayed.  An autotuner in the library measures every choice on
+ * the batches it runs (wall time per round-robin step) and keeps the fastest;
+ * the choices never change results (bit-identical).  MPO_AUTOTUNE=0 turns it
+ * off; MPO_TUNE_CACHE=<file> loads earlier decisions and appends new ones,
+ * one line per bucket: "gfx950 <precision> r<width> b<class> rrc=<rows>
+ * graph=<0|1> us_per_step=<t>".  Writes the current table (decided buckets
+ * and buckets still being measured) into out[0..cap) as text and returns its
+ * full length. */
+int32_t mpo_tuning_report(char* out, int32_t cap);
+/* Sets the sweep launch choices process-wide: -1 = the autotuner, -2 = fixed
+ * defaults (no tuning), 0..5 = one choice for every batch (row chunk 64, 128,
+ * 256 without capture, then the same three with capture). */
+mpo_status_t mpo_tuning_set(int32_t mode);
 const char* mpo_last_error(mpo_handle_t h);
 /* Library build string (kernels compiled for, precision variants). */
 const char* mpo_version(void);

@@ -370,6 +370,7 @@ class OracleConfig:
     max_unswap_iters: int = 20      # App. A.4
     side: str = "both"              # "both" (Alg. 1), "adaptive" or "fixed" (App. A.3)
     fixed_freq: Tuple[int, int] = (1, 1)   # fixed mode: layers of C_L, then of C_R, per period
+    rewire: str = "lazy"            # "lazy" or "eager" (Alg. 1 / Sec. II.B.3 taken literally)
 
 
 class Layout:
@@ -392,6 +393,34 @@ def orient(u: np.ndarray, sa: int, sb: int) -> Tuple[int, np.ndarray]:
         return sa, u
     assert sa == sb + 1
     return sb, SWAP4 @ u @ SWAP4
+
+
+def transpile_linear(gates, lay: "Layout") -> List[list]:
+    """Alg. 1 "transpile C to linear connectivity" for the gates of one half
+    (in the order they are absorbed), starting from layout `lay` (left as
+    is).  Before each gate, SWAPs on consecutive sites carry the qubit on
+    the lower site up until the two are neighbours; the resulting gate
+    sequence is then layered as soon as possible by the sites each entry
+    touches.  Entries: (a, b, u, is_swap, gate id) on logical qubits."""
+    site_of, logical_at = list(lay.site_of), list(lay.logical_at)
+    seq = []                                  # (lower site, entry)
+    for (a, b, u, gid) in gates:
+        while abs(site_of[a] - site_of[b]) > 1:
+            j = min(site_of[a], site_of[b])
+            x, y = logical_at[j], logical_at[j + 1]
+            seq.append((j, (x, y, SWAP4, True, None)))
+            logical_at[j], logical_at[j + 1] = y, x
+            site_of[x], site_of[y] = j + 1, j
+        seq.append((min(site_of[a], site_of[b]), (a, b, u, False, gid)))
+    busy = [0] * (len(site_of) + 1)
+    layers: List[list] = []
+    for j, e in seq:
+        depth = max(busy[j], busy[j + 1])
+        if depth == len(layers):
+            layers.append([])
+        layers[depth].append(e)
+        busy[j] = busy[j + 1] = depth + 1
+    return layers
 
 
 @dataclasses.dataclass
@@ -436,6 +465,22 @@ class Contraction:
         self.trace: List[Dict] = []
         self.updates = 0
         self.steps = 0                  # absorption steps taken (fixed-frequency phase)
+        if cfg.rewire == "eager":
+            # Alg. 1 taken literally: each half is transpiled to the line, and
+            # after every unswapping stage its remaining circuit gates (the
+            # transpilation SWAPs stripped) are reindexed by the layouts and
+            # transpiled again
+            ids = iter(range(len(gates)))
+            self.half_l = [(a, b, u, next(ids)) for layer in self.left for (a, b, u) in layer]
+            self.half_r = [(a, b, u, next(ids)) for layer in self.right for (a, b, u) in layer]
+            self.done_ids = set()
+            self._retranspile()
+        elif cfg.rewire != "lazy":
+            raise ValueError(cfg.rewire)
+
+    def _retranspile(self):
+        self.left = transpile_linear([g for g in self.half_l if g[3] not in self.done_ids], self.lay_l)
+        self.right = transpile_linear([g for g in self.half_r if g[3] not in self.done_ids], self.lay_r)
 
     # ------------------------------------------------------------- updates
     def _update(self, i, g_out, g_in, stage, fused=False):
@@ -498,6 +543,8 @@ class Contraction:
             c.lay_l.site_of, c.lay_l.logical_at = list(self.lay_l.site_of), list(self.lay_l.logical_at)
             c.lay_r.site_of, c.lay_r.logical_at = list(self.lay_r.site_of), list(self.lay_r.logical_at)
             c.trace, c.updates, c.steps = [], 0, self.steps
+            if self.cfg.rewire == "eager":
+                c.half_l, c.half_r, c.done_ids = self.half_l, self.half_r, set(self.done_ids)
             if side == "L":
                 c.absorb_layers(c.left.pop(0), [])
             else:
@@ -508,6 +555,8 @@ class Contraction:
         other = cands[1] if keep is cands[0] else cands[0]
         self.left, self.right, self.m = keep.left, keep.right, keep.m
         self.lay_l, self.lay_r = keep.lay_l, keep.lay_r
+        if self.cfg.rewire == "eager":
+            self.done_ids = keep.done_ids
         self.trace.extend(keep.trace)
         self.updates += keep.updates
         self.trial_absorb_updates = getattr(self, "trial_absorb_updates", 0) + other.updates
@@ -515,26 +564,58 @@ class Contraction:
                                size_left=sizes[0], size_right=sizes[1]))
 
     def absorb_layers(self, lgates, rgates):
+        """One absorption step's updates.  Entries of eager (transpiled)
+        layers carry a flag: a transpilation SWAP is absorbed as a SWAP update
+        on its side and exchanges the two sites in that side's layout; a
+        circuit gate's id is noted as absorbed."""
+        def flag(g):
+            return (g[3], g[4]) if len(g) == 5 else (False, None)
+
         pending = list(rgates)
-        for (a, b, u) in lgates:
+        for g in lgates:
+            a, b, u = g[:3]
+            is_swap, gid = flag(g)
+            if is_swap:
+                i = min(self.lay_l.site_of[a], self.lay_l.site_of[b])
+                assert abs(self.lay_l.site_of[a] - self.lay_l.site_of[b]) == 1
+                self._update(i, SWAP4, None, "route")
+                self.lay_l.swap_sites(i)
+                continue
             sa, sb = self._route(self.lay_l, a, b, "L")
             i, ul = orient(u, sa, sb)
             fused = None
-            for idx, (ra, rb, ru) in enumerate(pending):
-                xa, xb = self.lay_r.site_of[ra], self.lay_r.site_of[rb]
+            for idx, rg in enumerate(pending):
+                if flag(rg)[0]:
+                    continue
+                xa, xb = self.lay_r.site_of[rg[0]], self.lay_r.site_of[rg[1]]
                 if abs(xa - xb) == 1 and min(xa, xb) == i:
                     fused = idx
                     break
             if fused is not None:
-                ra, rb, ru = pending.pop(fused)
-                _, ur = orient(ru, self.lay_r.site_of[ra], self.lay_r.site_of[rb])
+                rg = pending.pop(fused)
+                _, ur = orient(rg[2], self.lay_r.site_of[rg[0]], self.lay_r.site_of[rg[1]])
                 self._update(i, ul, ur, "absorb", fused=True)
+                self._note_done(gid, flag(rg)[1])
             else:
                 self._update(i, ul, None, "absorb")
-        for (a, b, u) in pending:
+                self._note_done(gid)
+        for g in pending:
+            a, b, u = g[:3]
+            is_swap, gid = flag(g)
+            if is_swap:
+                i = min(self.lay_r.site_of[a], self.lay_r.site_of[b])
+                assert abs(self.lay_r.site_of[a] - self.lay_r.site_of[b]) == 1
+                self._update(i, None, SWAP4, "route")
+                self.lay_r.swap_sites(i)
+                continue
             sa, sb = self._route(self.lay_r, a, b, "R")
             i, ur = orient(u, sa, sb)
             self._update(i, None, ur, "absorb")
+            self._note_done(gid)
+
+    def _note_done(self, *gids):
+        if self.cfg.rewire == "eager":
+            self.done_ids.update(x for x in gids if x is not None)
 
     def unswap(self):
         cfg = self.cfg
@@ -555,6 +636,8 @@ class Contraction:
                 self.lay_r.swap_sites(i)
         self.trace.append(dict(stage="unswap", accepted=len(log), size_before=before,
                                size=self.m.size(), log=list(log)))
+        if cfg.rewire == "eager":
+            self._retranspile()
         return log
 
     def gates_absorbed(self) -> int:
@@ -567,9 +650,16 @@ class Contraction:
         self.sizes = []
         while self.left or self.right:
             # every absorption phase takes at least one layer pair, so the loop
-            # progresses even when unswapping cannot bring size(M) below tau
+            # progresses even when unswapping cannot bring size(M) below tau;
+            # with eager rewiring a phase goes on until it has absorbed a circuit
+            # gate (its first layers may hold only transpilation SWAPs, which
+            # unswapping would take out again, and rewiring put back)
+            before = self.gates_absorbed()
             self.absorb_step()
             self.sizes.append(("absorb", self.gates_absorbed(), self.m.size()))
+            while cfg.rewire == "eager" and self.gates_absorbed() == before and (self.left or self.right):
+                self.absorb_step()
+                self.sizes.append(("absorb", self.gates_absorbed(), self.m.size()))
             while self.m.size() < cfg.tau and (self.left or self.right):
                 self.absorb_step()
                 self.sizes.append(("absorb", self.gates_absorbed(), self.m.size()))

@@ -38,6 +38,8 @@ class CircuitTask:
         self.keep_lams = keep_lams
         self.lams: Optional[List[np.ndarray]] = None
         self.group_unswap = group_unswap and cfg.unswap == "parallel"
+        if cfg.rewire != "lazy":
+            raise ValueError("the lockstep runner uses lazy rewiring")
         self.c = dr.Contractor(circuit, cfg)
         self.phase_started = False
         self.result: Optional[dr.RunResult] = None
@@ -49,9 +51,11 @@ class CircuitTask:
         return self.result is not None
 
     def next_step(self):
-        """Updates of the next absorption step; runs the unswap stage (or, with
-        group unswapping, returns UNSWAP and waits for unswap_done) and the
-        final readout when Alg. 1 reaches them.  None once finished."""
+        """(MPO handle, updates) candidates of the next absorption step (two
+        for an adaptive step, Contractor.step_candidates); runs the unswap
+        stage (or, with group unswapping, returns UNSWAP and waits for
+        unswap_done) and the final readout when Alg. 1 reaches them.  None
+        once finished."""
         c = self.c
         while True:
             if not (c.c_left or c.c_right):
@@ -68,9 +72,9 @@ class CircuitTask:
                 return None
             if not self.phase_started:
                 self.phase_started = True
-                return c.plan_absorb()
+                return c.step_candidates()
             if not c.m.tau_reached():
-                return c.plan_absorb()
+                return c.step_candidates()
             if self.group_unswap:
                 return UNSWAP
             c.unswap()
@@ -109,52 +113,61 @@ def run_round(tasks: Sequence[CircuitTask], group: Optional[_mpo.Group], per_upd
                 t.unswap_done(log, b0)
     issued = 0
     if per_update:
-        for t, ups in steps:
-            infos = [t.c.m.absorb(u.bond, u.g_out, u.g_in) for u in ups]
-            t.c.record(ups, infos)
-            issued += len(ups)
+        for t, cands in steps:
+            infos = [[m.absorb(u.bond, u.g_out, u.g_in) for u in ups] for m, ups in cands]
+            t.c.step_commit(cands, infos)
+            issued += sum(len(ups) for m, ups in cands)
         return issued
-    # merge the per-circuit waves, shape-sorted, into group launches
-    results: Dict[int, List[Optional[dict]]] = {id(t): [None] * len(ups) for t, ups in steps}
+    # merge the waves of every candidate of every circuit, shape-sorted, into
+    # group launches (the candidates of an adaptive step act on different MPOs)
+    results = {(id(t), c): [None] * len(ups) for t, cands in steps for c, (m, ups) in enumerate(cands)}
     waves: List[list] = []
-    for t, ups in steps:
-        for w, idxs in enumerate(dr.wave_split([u.bond for u in ups])):
-            while len(waves) <= w:
-                waves.append([])
-            dims = t.c.m.bond_dims()
-            for i in idxs:
-                b = ups[i].bond
-                key = (1 if b == 0 else dims[b - 1], dims[b + 1] if b + 1 < len(dims) else 1)
-                waves[w].append((key, t, ups, i))
+    for t, cands in steps:
+        for c, (m, ups) in enumerate(cands):
+            dims = m.bond_dims()
+            for w, idxs in enumerate(dr.wave_split([u.bond for u in ups])):
+                while len(waves) <= w:
+                    waves.append([])
+                for i in idxs:
+                    b = ups[i].bond
+                    key = (1 if b == 0 else dims[b - 1], dims[b + 1] if b + 1 < len(dims) else 1)
+                    waves[w].append((key, (id(t), c), m, ups[i], i))
     for wave in waves:
         wave.sort(key=lambda x: x[0])
         for j in range(0, len(wave), GROUP_MAX):
             chunk = wave[j:j + GROUP_MAX]
-            infos = group.absorb([x[1].c.m for x in chunk], [x[2][x[3]].bond for x in chunk],
-                                 [x[2][x[3]].g_out for x in chunk], [x[2][x[3]].g_in for x in chunk])
-            for (key, t, ups, i), inf in zip(chunk, infos):
-                results[id(t)][i] = inf
+            infos = group.absorb([x[2] for x in chunk], [x[3].bond for x in chunk], [x[3].g_out for x in chunk],
+                                 [x[3].g_in for x in chunk])
+            for (key, rk, m, u, i), inf in zip(chunk, infos):
+                results[rk][i] = inf
             issued += len(chunk)
-    for t, ups in steps:
-        t.c.record(ups, results[id(t)])
+    for t, cands in steps:
+        t.c.step_commit(cands, [results[(id(t), c)] for c in range(len(cands))])
     return issued
 
 
-def run_batched(circuits_cfgs, precision: str = "fp32", per_update: bool = False, keep_lams: bool = False) -> dict:
+def run_batched(circuits_cfgs, precision: str = "fp32", per_update: bool = False, keep_lams: bool = False,
+                max_rounds: int = 0) -> dict:
     """Contracts (circuit, RunConfig) pairs in lockstep; returns results and
     aggregate throughput (with keep_lams, also every circuit's final bond
-    vectors, read after its peak readout)."""
+    vectors, read after its peak readout).  With max_rounds > 0 it stops after
+    that many rounds (the same work in the grouped and the per-update way);
+    unfinished circuits have result None."""
     group = None if per_update else _mpo.Group(_mpo.PRECISIONS[precision])
     t0 = time.perf_counter()
     tasks = [CircuitTask(c, cfg, tag=i, group_unswap=not per_update, keep_lams=keep_lams)
              for i, (c, cfg) in enumerate(circuits_cfgs)]
     updates = 0
     rounds = 0
-    while not all(t.done for t in tasks):
+    while not all(t.done for t in tasks) and not (max_rounds and rounds >= max_rounds):
         updates += run_round(tasks, group, per_update)
         rounds += 1
     secs = time.perf_counter() - t0
+    for t in tasks:
+        if not t.done:
+            t.c.close()
     if group is not None:
         group.close()
     return dict(results=[t.result for t in tasks], seconds=secs, bond_updates=updates, rounds=rounds,
-                updates_per_s=updates / secs if secs > 0 else 0.0, lams=[t.lams for t in tasks])
+                updates_per_s=updates / secs if secs > 0 else 0.0, lams=[getattr(t, "lams", None) for t in tasks],
+                finished=sum(1 for t in tasks if t.done))

@@ -165,6 +165,30 @@ def oets_swaps(arr: np.ndarray) -> List[List[Tuple[int, int]]]:
     return rounds
 
 
+def transposition_swaps(arr: np.ndarray) -> List[List[Tuple[int, int]]]:
+    """A selection sort of ``arr`` as SWAPs on arbitrary pairs (all-to-all
+    connectivity): for position i in order, the value i is swapped in from
+    wherever it sits.  One SWAP per round; the pair is (i, j), i < j."""
+    a = list(int(x) for x in arr)
+    where = {v: k for k, v in enumerate(a)}
+    rounds = []
+    for i in range(len(a)):
+        j = where[i]
+        if j != i:
+            vi = a[i]
+            a[i], a[j] = a[j], a[i]
+            where[vi], where[i] = j, i
+            rounds.append([(i, j)])
+    return rounds
+
+
+def matching_pairs(rng: np.random.Generator, n: int) -> List[Tuple[int, int]]:
+    """A random perfect matching of the n qubits (one qubit idle when n is
+    odd), each pair in random order: one layer of an all-to-all circuit."""
+    q = rng.permutation(n)
+    return [(int(q[2 * j]), int(q[2 * j + 1])) for j in range(n // 2)]
+
+
 def embed_1q(u: np.ndarray, which: int) -> np.ndarray:
     """4x4 matrix of a single-qubit u on the first (which=0, MSB) or second qubit."""
     return np.kron(u, np.eye(2)) if which == 0 else np.kron(np.eye(2), u)
@@ -222,18 +246,32 @@ def mirrored_peaked_circuit(n: int, depth: int, seed: int, *, reading: str = "B"
                             k_std: float = 0.1, with_k: bool = True,
                             with_peak: bool = True, with_swaps: bool = True,
                             fuse_swaps: bool = True, dress: bool = True,
-                            min_margin: float = 0.5, max_k_draws: int = 64) -> Circuit:
+                            min_margin: float = 0.5, max_k_draws: int = 64,
+                            connectivity: str = "line") -> Circuit:
     """Build C = X^b K R^dag S_inv S R (see the module docstring).  K is
-    redrawn until every prefix conditional of K|0^n> exceeds `min_margin`."""
+    redrawn until every prefix conditional of K|0^n> exceeds `min_margin`.
+
+    connectivity "all": an all-to-all stand-in for circuits that are not
+    nearest-neighbour (the paper's input before transpilation, Sec. II.A):
+    R's layers are random perfect matchings and S, S_inv are selection-sort
+    SWAP sequences on arbitrary pairs; K stays a nearest-neighbour brickwork
+    (so the closed form of the peak is unchanged)."""
     if n < 2:
         raise ValueError("need at least two qubits")
     if reading not in ("A", "B"):
         raise ValueError("reading must be 'A' or 'B'")
+    if connectivity not in ("line", "all"):
+        raise ValueError("connectivity must be 'line' or 'all'")
     rng = np.random.Generator(np.random.PCG64(seed))
 
     perm = rng.permutation(n) if with_swaps else np.arange(n)
-    r_layers = [[(q0, q1, haar_su4(rng)) for (q0, q1) in brickwork_pairs(n, l)]
-                for l in range(depth)]
+    if connectivity == "line":
+        r_layers = [[(q0, q1, haar_su4(rng)) for (q0, q1) in brickwork_pairs(n, l)]
+                    for l in range(depth)]
+    else:
+        r_layers = [[(q0, q1, haar_su4(rng)) for (q0, q1) in matching_pairs(rng, n)]
+                    for _ in range(depth)]
+    sort_net = oets_swaps if connectivity == "line" else transposition_swaps
     k_layers = []
     if with_k:
         # K is drawn again (same stream) until the planted peak is readable by
@@ -251,11 +289,11 @@ def mirrored_peaked_circuit(n: int, depth: int, seed: int, *, reading: str = "B"
     seq: List[list] = []          # mutable [q0, q1, U, is_bare_swap]
     for layer in r_layers:
         seq += [[q0, q1, u.copy(), False] for (q0, q1, u) in layer]
-    s_rounds = oets_swaps(perm)
+    s_rounds = sort_net(perm)
     if reading == "B":
         inv = np.empty(n, dtype=np.int64)
         inv[perm] = np.arange(n)
-        sinv_rounds = oets_swaps(inv)
+        sinv_rounds = sort_net(inv)
     else:
         sinv_rounds = [list(reversed(r)) for r in reversed(s_rounds)]
     for rnd in s_rounds + sinv_rounds:
@@ -308,7 +346,7 @@ def mirrored_peaked_circuit(n: int, depth: int, seed: int, *, reading: str = "B"
 
     gates = [(int(g[0]), int(g[1]), np.ascontiguousarray(g[2])) for g in seq]
     k_gates = [(q0, q1, u.copy()) for layer in k_layers for (q0, q1, u) in layer]
-    meta = dict(n=n, depth=depth, seed=seed, reading=reading, k_std=k_std,
+    meta = dict(n=n, depth=depth, seed=seed, reading=reading, k_std=k_std, connectivity=connectivity,
                 with_k=with_k, with_peak=with_peak, with_swaps=with_swaps,
                 fuse_swaps=fuse_swaps, dress=dress,
                 swaps_s=sum(len(r) for r in s_rounds),

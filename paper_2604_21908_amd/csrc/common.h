@@ -18,7 +18,7 @@ constexpr int MAXB = 32;
 constexpr int JB = 16;
 // Rows per workgroup of the Jacobi Gram and rotation kernels.
 constexpr int GRC = 512;
-constexpr int RRC = 256;
+constexpr int RRC = 256;   // default rotation row chunk (the launch passes its own)
 // Panel rotation launch: every row on FP MFMA, or (mixed form) theta's rows
 // on split-BF16 products and V's rows on FP32 MFMA in the same launch.
 constexpr int ROT_FP = 0, ROT_MIXED = 1;
@@ -70,6 +70,9 @@ struct JacState {
   int rot;        // block pairs rotated in the current sweep
   int sweeps;     // sweeps run
   int rot_total;  // block pairs rotated over all sweeps
+  int epoch;      // sweeps launched (converged or not): the step stamp of step s
+                  // of the current sweep is epoch * nblk + s + 1, so stamps
+                  // grow without host arguments (a captured sweep replays as is)
 };
 struct JacProb {
   void* A;        // column-major, lda rows allocated, m used, ncol_pad columns

@@ -165,7 +165,7 @@ __device__ __forceinline__ bool jac_angle(double app, double aqq, cx<double> g, 
 constexpr int EVD_LD = 33;                       // row stride of G and W (entries)
 constexpr int EVD_ROWB = EVD_LD * 16;            // ... in bytes (cx<double>)
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inner_sweeps, int stamp) {
+__global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inner_sweeps) {
   const int pi = blockIdx.y;
   if (pi >= jb.count) return;
   const JacProb P = jb.p[pi];
@@ -184,6 +184,7 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   // state flag, the pair-skip stamps and all partial Gram matrices (read even
   // for a pair that turns out skipped; their sum is then discarded).
   const int active = P.st->active;
+  const int stamp = P.st->epoch * P.nblk + step + 1;
   const int chk = P.pchk[bi * P.nblk + bj], mod_i = P.bmod[bi], mod_j = P.bmod[bj];
   const int nch = (P.m + GRC - 1) / GRC;
   const cx<double>* gp = P.gpart + (size_t)blockIdx.x * P.ngchunk * 1024 + gi * 32 + gj0;
@@ -428,16 +429,16 @@ void launch_jac_gram(const JacBatch& b, int maxpairs, int maxgch, int step, int 
     hipLaunchKernelGGL(k_jac_gram<T>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
 }
 template <typename T>
-void launch_jac_evd(const JacBatch& b, int maxpairs, int step, int inner_sweeps, int stamp, hipStream_t s) {
-  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, inner_sweeps, stamp);
+void launch_jac_evd(const JacBatch& b, int maxpairs, int step, int inner_sweeps, hipStream_t s) {
+  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, inner_sweeps);
 }
 template <>
 void launch_jac_gram<double>(const JacBatch& b, int maxpairs, int maxgch, int step, int, hipStream_t s) {
   hipLaunchKernelGGL(k_jac_gram<double>, dim3(maxpairs, maxgch, b.count), dim3(256), 0, s, b, step);
 }
 template void launch_jac_gram<float>(const JacBatch&, int, int, int, int, hipStream_t);
-template void launch_jac_evd<float>(const JacBatch&, int, int, int, int, hipStream_t);
-template void launch_jac_evd<double>(const JacBatch&, int, int, int, int, hipStream_t);
+template void launch_jac_evd<float>(const JacBatch&, int, int, int, hipStream_t);
+template void launch_jac_evd<double>(const JacBatch&, int, int, int, hipStream_t);
 template void launch_ns_corr<float>(const cx<double>*, cx<float>*, int, hipStream_t);
 template void launch_ns_corr<double>(const cx<double>*, cx<double>*, int, hipStream_t);
 

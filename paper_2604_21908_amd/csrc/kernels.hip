@@ -235,6 +235,7 @@ __global__ void k_jac_init(JacBatch jb) {
     P.st->rot = 0;
     P.st->sweeps = 0;
     P.st->rot_total = 0;
+    P.st->epoch = 0;
   }
   // pair-skip bookkeeping starts empty
   const size_t nb = (size_t)P.nblk;
@@ -262,6 +263,7 @@ __global__ void k_jac_sweep_end(JacBatch jb) {
   const int i = threadIdx.x;
   if (i >= jb.count) return;
   JacState* s = jb.p[i].st;
+  s->epoch += 1;
   if (s->active) {
     s->sweeps += 1;
     s->rot_total += s->rot;

@@ -1,6 +1,6 @@
 // Panel rotation of the block one-sided Jacobi SVD (gfx950): P <- P + P D
 // for the 32-column panels of a round-robin step, D = W - I from the panel
-// EVD (jacobi.hip), over row chunks of RRC rows of theta's operand and of the
+// EVD (jacobi.hip), over row chunks (a launch argument) of theta's operand and of the
 // accumulated rotations V.
 //
 //   k_jac_rot        FP MFMA (f32 16x16x4 or f64 16x16x4), computed as
@@ -115,7 +115,7 @@ __device__ __forceinline__ void rot_rows(const JacProb& P, int bi, int bj, int c
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step, int part) {
+__global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step, int part, int rrc) {
   const int pi = blockIdx.z;
   if (pi >= jb.count) return;
   const JacProb P = jb.p[pi];
@@ -124,9 +124,9 @@ __global__ __launch_bounds__(256) void k_jac_rot(JacBatch jb, int step, int part
   if (P.pflag[blockIdx.x] == 0) return;
   const int nv = P.V ? P.ncol : 0;
   const int rows = (part == 1) ? P.m : P.m + nv;
-  const int c0 = (part == 2 ? P.m : 0) + blockIdx.y * RRC;
+  const int c0 = (part == 2 ? P.m : 0) + blockIdx.y * rrc;
   if (c0 >= rows) return;
-  const int c1 = min(rows, c0 + RRC);
+  const int c1 = min(rows, c0 + rrc);
   int bi, bj;
   rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
   __shared__ cx<T> Ds[32][33];
@@ -224,7 +224,7 @@ __device__ __forceinline__ void rot_rows_bf16(const JacProb& P, int bi, int bj, 
 // One launch for both row sets of the mixed form: row chunks y < ny_theta
 // rotate theta's rows on split-BF16, the others V's rows on FP32, so the
 // memory-bound and the MFMA-bound workgroups share the machine.
-__global__ __launch_bounds__(256) void k_jac_rot_mixed(JacBatch jb, int step, int ny_theta) {
+__global__ __launch_bounds__(256) void k_jac_rot_mixed(JacBatch jb, int step, int ny_theta, int rrc) {
   const int pi = blockIdx.z;
   if (pi >= jb.count) return;
   const JacProb P = jb.p[pi];
@@ -234,14 +234,14 @@ __global__ __launch_bounds__(256) void k_jac_rot_mixed(JacBatch jb, int step, in
   const bool theta = (int)blockIdx.y < ny_theta;
   int c0, c1;
   if (theta) {
-    c0 = blockIdx.y * RRC;
+    c0 = blockIdx.y * rrc;
     if (c0 >= P.m) return;
-    c1 = min(P.m, c0 + RRC);
+    c1 = min(P.m, c0 + rrc);
   } else {
     const int nv = P.V ? P.ncol : 0;
-    c0 = P.m + (blockIdx.y - ny_theta) * RRC;
+    c0 = P.m + (blockIdx.y - ny_theta) * rrc;
     if (c0 >= P.m + nv) return;
-    c1 = min(P.m + nv, c0 + RRC);
+    c1 = min(P.m + nv, c0 + rrc);
   }
   int bi, bj;
   rr_pair2(P.nblk, step, blockIdx.x, bi, bj);
@@ -254,19 +254,24 @@ __global__ __launch_bounds__(256) void k_jac_rot_mixed(JacBatch jb, int step, in
   else rot_rows<float>(P, bi, bj, c0, c1, Ds, Sw[threadIdx.x >> 6]);
 }
 
+// Row chunks of rrc rows (a multiple of 64: four waves of 16-row strips):
+// maxrch_a chunks of theta's rows, then maxrch_v of V's.
 template <typename T>
-void launch_jac_rot(const JacBatch& b, int maxpairs, int maxrch_a, int maxrch_v, int step, int mode, hipStream_t s) {
+void launch_jac_rot(const JacBatch& b, int maxpairs, int maxrch_a, int maxrch_v, int step, int mode, int rrc,
+                    hipStream_t s) {
   if (mode == ROT_MIXED)
     hipLaunchKernelGGL(k_jac_rot_mixed, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step,
-                       maxrch_a);
+                       maxrch_a, rrc);
   else
-    hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step, 0);
+    hipLaunchKernelGGL(k_jac_rot<T>, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step, 0,
+                       rrc);
 }
 template <>
-void launch_jac_rot<double>(const JacBatch& b, int maxpairs, int maxrch_a, int maxrch_v, int step, int,
+void launch_jac_rot<double>(const JacBatch& b, int maxpairs, int maxrch_a, int maxrch_v, int step, int, int rrc,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_jac_rot<double>, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step, 0);
+  hipLaunchKernelGGL(k_jac_rot<double>, dim3(maxpairs, maxrch_a + maxrch_v, b.count), dim3(256), 0, s, b, step, 0,
+                     rrc);
 }
-template void launch_jac_rot<float>(const JacBatch&, int, int, int, int, int, hipStream_t);
+template void launch_jac_rot<float>(const JacBatch&, int, int, int, int, int, int, hipStream_t);
 
 }  // namespace mpo

@@ -2,6 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -20,8 +23,8 @@ template <typename T> void launch_gemm(const GemmBatch&, int, int, hipStream_t);
 template <typename T> void launch_gate(const GateBatch&, int, hipStream_t);
 template <typename T> void launch_jac_init(const JacBatch&, hipStream_t);
 template <typename T> void launch_jac_gram(const JacBatch&, int, int, int, int, hipStream_t);
-template <typename T> void launch_jac_evd(const JacBatch&, int, int, int, int, hipStream_t);
-template <typename T> void launch_jac_rot(const JacBatch&, int, int, int, int, int, hipStream_t);
+template <typename T> void launch_jac_evd(const JacBatch&, int, int, int, hipStream_t);
+template <typename T> void launch_jac_rot(const JacBatch&, int, int, int, int, int, int, hipStream_t);
 template <typename T> void launch_ns_corr(const cx<double>*, cx<T>*, int, hipStream_t);
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
@@ -156,6 +159,15 @@ struct mpo_ctx {
   double* h_gates = nullptr;
   std::string err;
   size_t bytes_allocated = 0;
+  // Captured Jacobi sweeps: a sweep's launches (Gram, panel EVD, rotation per
+  // round-robin step, then the convergence update) recorded once on a private
+  // capture stream and replayed on `stream` with one hipGraphLaunch while the
+  // batch's shapes and buffers stay the same.  Keyed by everything the
+  // launches read from the host; at most GRAPH_CACHE kept (oldest dropped).
+  hipStream_t cap_stream = nullptr;
+  std::map<std::string, hipGraphExec_t> graphs;
+  std::deque<std::string> graph_order;
+  int64_t graph_replays = 0, graph_captures = 0;
   // kernel timing (mpo_profile): launches bracketed by events on `stream`
   bool trace = false;   // MPO_TRACE=1: per-batch sweep counts on stderr
   bool prof_on = false;
@@ -490,6 +502,170 @@ void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStrea
   }
 }
 
+constexpr size_t GRAPH_CACHE = 64;
+
+// ---- launch choices of the Jacobi sweeps, and their autotuner ---------------
+// A batch's sweeps can split the panel rotation into row chunks of 64, 128 or
+// 256 rows (more, shorter workgroups for small operands) and can be captured
+// as a graph and replayed (one launch per sweep instead of three per step).
+// Neither changes any arithmetic: every choice gives bit-identical results.
+// The tuner measures each choice on the batches it sees, per bucket (the
+// precision, the operand width r rounded up to a power of two and the batch
+// size class), by the wall time per round-robin step of sweeps that did not
+// capture a graph; once every choice has two samples the fastest median wins
+// for that bucket.  Operands wider than 1024 columns are not tuned (their
+// launches are long and full; 256-row chunks, no capture).  MPO_AUTOTUNE=0
+// turns it off (fixed defaults);
+// MPO_TUNE_CACHE=<file> loads decisions at start and appends new ones as lines
+//   gfx950 <precision> r<bucket> b<class> rrc=<rows> graph=<0|1> us_per_step=<t>
+struct SweepPlan {
+  int rrc = RRC;
+  bool graph = false;
+};
+constexpr int TUNE_RRC[3] = {64, 128, 256};
+constexpr int TUNE_CHOICES = 6;   // rrc x {no graph, graph}
+struct TuneEntry {
+  std::vector<double> us[TUNE_CHOICES];
+  int chosen = -1;
+  double best_us = 0;
+};
+struct Tuner {
+  std::mutex mu;
+  bool loaded = false, on = true;
+  int forced = -1;   // mpo_tuning_set: a fixed choice for every batch
+  std::string cache_path;
+  std::map<std::string, TuneEntry> table;
+};
+Tuner g_tuner;
+
+SweepPlan plan_of(int choice) {
+  SweepPlan p;
+  p.rrc = TUNE_RRC[choice % 3];
+  p.graph = choice >= 3;
+  return p;
+}
+int default_choice(int r) { return r <= 512 ? 4 : 2; }   // (128, graph) small; (256, none) large
+std::string tune_key(int prec, int r, int count) {
+  int b = 32;
+  while (b < r) b *= 2;
+  const int cls = count <= 1 ? 1 : count <= 8 ? 8 : 32;
+  static const char* pn[3] = {"fp64", "fp32", "mixed"};
+  return std::string(pn[prec]) + " r" + std::to_string(b) + " b" + std::to_string(cls);
+}
+void tuner_load() {
+  if (g_tuner.loaded) return;
+  g_tuner.loaded = true;
+  const char* a = std::getenv("MPO_AUTOTUNE");
+  g_tuner.on = !(a && a[0] == '0');
+  const char* c = std::getenv("MPO_TUNE_CACHE");
+  if (!c || !c[0]) return;
+  g_tuner.cache_path = c;
+  FILE* f = std::fopen(c, "r");
+  if (!f) return;
+  char arch[32], prec[16], rb[16], cb[16];
+  int rrc = 0, graph = 0;
+  double us = 0;
+  while (std::fscanf(f, "%31s %15s %15s %15s rrc=%d graph=%d us_per_step=%lf", arch, prec, rb, cb, &rrc, &graph,
+                     &us) == 7) {
+    if (std::string(arch) != "gfx950") continue;
+    int choice = -1;
+    for (int j = 0; j < TUNE_CHOICES; ++j)
+      if (plan_of(j).rrc == rrc && plan_of(j).graph == (graph != 0)) choice = j;
+    if (choice < 0) continue;
+    TuneEntry& e = g_tuner.table[std::string(prec) + " " + rb + " " + cb];
+    e.chosen = choice;
+    e.best_us = us;
+  }
+  std::fclose(f);
+}
+// The choice for this batch, and the tuning slot it measures (-1: none).
+SweepPlan plan_sweeps(mpo_ctx* h, int r, int count, int* measure, std::string* key) {
+  std::lock_guard<std::mutex> lk(g_tuner.mu);
+  tuner_load();
+  *measure = -1;
+  *key = tune_key(h->prec, r, count);
+  // wide operands: 128+ pairs and thousands of workgroups per launch, the
+  // launches' cost is noise; only narrower ones are tuned
+  if (g_tuner.forced >= 0) return plan_of(g_tuner.forced);
+  if (!g_tuner.on || r > 1024) return plan_of(default_choice(r));
+  TuneEntry& e = g_tuner.table[*key];
+  if (e.chosen >= 0) return plan_of(e.chosen);
+  int pick = 0;
+  for (int j = 1; j < TUNE_CHOICES; ++j)
+    if (e.us[j].size() < e.us[pick].size()) pick = j;
+  *measure = pick;
+  return plan_of(pick);
+}
+void tuner_report(const std::string& key, int choice, double us_per_step) {
+  std::lock_guard<std::mutex> lk(g_tuner.mu);
+  TuneEntry& e = g_tuner.table[key];
+  if (e.chosen >= 0 || choice < 0) return;
+  e.us[choice].push_back(us_per_step);
+  for (int j = 0; j < TUNE_CHOICES; ++j)
+    if (e.us[j].size() < 2) return;
+  double best = 1e300;
+  for (int j = 0; j < TUNE_CHOICES; ++j) {
+    std::vector<double> v = e.us[j];
+    std::sort(v.begin(), v.end());
+    const double med = v[v.size() / 2];
+    if (med < best) {
+      best = med;
+      e.chosen = j;
+    }
+  }
+  e.best_us = best;
+  if (!g_tuner.cache_path.empty()) {
+    FILE* f = std::fopen(g_tuner.cache_path.c_str(), "a");
+    if (f) {
+      const SweepPlan p = plan_of(e.chosen);
+      std::fprintf(f, "gfx950 %s rrc=%d graph=%d us_per_step=%.3f\n", key.c_str(), p.rrc, p.graph ? 1 : 0, best);
+      std::fclose(f);
+    }
+  }
+}
+
+template <typename V>
+void key_put(std::string& k, const V& v) {
+  k.append((const char*)&v, sizeof(V));
+}
+
+// The executable graph of one Jacobi sweep for this exact batch, captured on
+// first use.  `record(stream)` enqueues the sweep's launches on `stream`.
+// The capture stream never runs anything itself; errors during the capture
+// end it before they propagate.
+template <typename F>
+hipGraphExec_t sweep_graph(mpo_ctx* h, const std::string& key, F&& record) {
+  auto it = h->graphs.find(key);
+  if (it != h->graphs.end()) return it->second;
+  if (!h->cap_stream) hip_check(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "capture stream");
+  if (h->graphs.size() >= GRAPH_CACHE) {   // every earlier replay has completed: each sweep ends in a sync
+    auto old = h->graphs.find(h->graph_order.front());
+    if (old != h->graphs.end()) {
+      (void)hipGraphExecDestroy(old->second);
+      h->graphs.erase(old);
+    }
+    h->graph_order.pop_front();
+  }
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
+  try {
+    record(h->cap_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(h->cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(h->cap_stream, &g), "end capture");
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(e, "graph instantiate");
+  h->graphs[key] = ex;
+  h->graph_order.push_back(key);
+  h->graph_captures += 1;
+  return ex;
+}
+
 // One batch (<= MAXB problems): theta-build, gate, QR-preconditioned Jacobi
 // SVD, truncation; with `commit` the new tensors are written (bonds must be
 // pairwise non-adjacent).  Returns per-problem results.  Throws HipError / NoMem.
@@ -501,7 +677,6 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   };
   Shape sh[MAXB];
   int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0, maxgch = 1;
-  int maxrch_a = 1, maxrch_v = 1;   // row chunks of theta's rows, of V's rows
   auto O = [&](int p) -> mpo_ctx* { return reqs[p].owner ? reqs[p].owner : h; };
   for (int p = 0; p < count; ++p) {
     Shape& s = sh[p];
@@ -530,8 +705,6 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
               (size_t)((s.n + QRC1 - 1) / QRC1) * QNB * s.m, (size_t)QNB * s.m);
     ensure_jac(h, sl, (size_t)(s.nblk / 2), (size_t)((s.m + GRC - 1) / GRC));
     maxgch = std::max(maxgch, (s.m + GRC - 1) / GRC);
-    maxrch_a = std::max(maxrch_a, (s.m + RRC - 1) / RRC);
-    if (commit) maxrch_v = std::max(maxrch_v, (s.r + RRC - 1) / RRC);
   }
   // gates -> pinned staging -> device (the staging buffer is free: every
   // call ends with a stream synchronisation)
@@ -624,22 +797,61 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   }
   timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
   const bool mixed = (h->prec == MPO_MIXED_SPLITBF16);
-  int stamp = 0;   // step stamps of the pair-skip bookkeeping (cleared by k_jac_init)
+  // rotation row chunk and sweep capture for this batch (see SweepPlan)
+  int measure = -1;
+  std::string tkey;
+  const SweepPlan plan = plan_sweeps(h, maxr, count, &measure, &tkey);
+  const int rrc = plan.rrc;
+  int nrch_a = 1, nrch_v = 0;
+  for (int p = 0; p < count; ++p) {
+    nrch_a = std::max(nrch_a, (sh[p].m + rrc - 1) / rrc);
+    if (commit) nrch_v = std::max(nrch_v, (sh[p].r + rrc - 1) / rrc);
+  }
+  const bool use_graph = plan.graph && !h->prof_on;
   auto sweeps = [&](int bf16, int budget) {
     bool active_left = true;
-    for (int sw = 0; sw < budget && active_left; ++sw) {
+    auto record = [&](hipStream_t s) {
       for (int step = 0; step < maxblk - 1; ++step) {
-        timed(h, MPO_PROF_JACOBI_GRAM, [&] { launch_jac_gram<T>(jb, maxpairs, maxgch, step, bf16, st); });
-        ++stamp;
-        timed(h, MPO_PROF_JACOBI_EVD, [&] { launch_jac_evd<T>(jb, maxpairs, step, bf16 ? 1 : 2, stamp, st); });
+        timed(h, MPO_PROF_JACOBI_GRAM, [&] { launch_jac_gram<T>(jb, maxpairs, maxgch, step, bf16, s); });
+        timed(h, MPO_PROF_JACOBI_EVD, [&] { launch_jac_evd<T>(jb, maxpairs, step, bf16 ? 1 : 2, s); });
         timed(h, MPO_PROF_JACOBI_ROT, [&] {
-          launch_jac_rot<T>(jb, maxpairs, maxrch_a, commit ? maxrch_v : 0, step, bf16 ? ROT_MIXED : ROT_FP, st);
+          launch_jac_rot<T>(jb, maxpairs, nrch_a, nrch_v, step, bf16 ? ROT_MIXED : ROT_FP, rrc, s);
         });
       }
-      launch_jac_sweep_end(jb, st);
+      launch_jac_sweep_end(jb, s);
+    };
+    std::string key;
+    if (use_graph) {
+      key.reserve(64 + count * sizeof(JacProb));
+      key_put(key, count), key_put(key, maxblk), key_put(key, maxpairs), key_put(key, maxgch);
+      key_put(key, nrch_a), key_put(key, nrch_v), key_put(key, rrc), key_put(key, bf16), key_put(key, sizeof(T));
+      for (int p = 0; p < count; ++p) {
+        const JacProb& q = jb.p[p];
+        key_put(key, q.A), key_put(key, q.V), key_put(key, q.st), key_put(key, q.norms), key_put(key, q.gpart);
+        key_put(key, q.dmat), key_put(key, q.pflag), key_put(key, q.bmod), key_put(key, q.pchk), key_put(key, q.tol);
+        key_put(key, q.m), key_put(key, q.lda), key_put(key, q.ncol), key_put(key, q.ncol_pad), key_put(key, q.nblk);
+        key_put(key, q.ngchunk);
+      }
+    }
+    for (int sw = 0; sw < budget && active_left; ++sw) {
+      const auto t0 = std::chrono::steady_clock::now();
+      bool captured = false;
+      if (use_graph) {
+        const int64_t before = h->graph_captures;
+        hipGraphExec_t ex = sweep_graph(h, key, record);
+        captured = h->graph_captures != before;
+        hip_check(hipGraphLaunch(ex, st), "graph launch");
+        h->graph_replays += 1;
+      } else {
+        record(st);
+      }
       hip_check(hipMemcpyAsync(h->h_states, h->states, count * sizeof(JacState), hipMemcpyDeviceToHost, st),
                 "state readback");
       hip_check(hipStreamSynchronize(st), "sweep sync");
+      if (measure >= 0 && !captured && !h->prof_on && maxblk > 1) {
+        const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+        tuner_report(tkey, measure, us / (maxblk - 1));
+      }
       drain_events(h);
       active_left = false;
       for (int p = 0; p < count; ++p) active_left |= (h->h_states[p].active != 0);
@@ -662,7 +874,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     // ... then the FP64 re-orthogonalisation of the accumulated rotations
     // and A = L W.  The columns of L W are orthogonal to the BF16 phase's
     // tolerance, so their norms equal the singular values to second order in
-    // it (about 1e-8 relative); no FP32 sweep is needed afterwards.  Values-
+    // it; no FP32 sweep is needed afterwards.  Values-
     // only trials keep the BF16-rotated norms (relative drift ~1e-4), which
     // decide ranks only.
     if (commit) timed(h, MPO_PROF_REORTH, [&] { reorthogonalise<T>(h, sh_r(sh, count), jb, st); });
@@ -1206,6 +1418,8 @@ void destroy(mpo_ctx* h) {
     (void)hipEventDestroy(p.b);
   }
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (void* p : h->bk) dfree(h, p);
   dfree(h, h->ns_x);
   dfree(h, h->ns_s);
@@ -1703,8 +1917,9 @@ mpo_status_t mpo_trial_swap(mpo_handle_t h, int32_t bond, int32_t side, mpo_upda
 
 mpo_status_t mpo_counters(mpo_handle_t h, int64_t* out, int32_t cap) {
   if (!h || cap < 0 || (cap > 0 && !out)) return MPO_EINVAL;
-  const int64_t v[5] = {h->n_updates, h->n_trials, h->n_trials_reused, h->n_reverted, h->hook_allocs};
-  for (int j = 0; j < cap && j < 5; ++j) out[j] = v[j];
+  const int64_t v[7] = {h->n_updates,   h->n_trials,     h->n_trials_reused, h->n_reverted,
+                        h->hook_allocs, h->graph_replays, h->graph_captures};
+  for (int j = 0; j < cap && j < 7; ++j) out[j] = v[j];
   return MPO_OK;
 }
 
@@ -1730,6 +1945,41 @@ mpo_status_t mpo_profile(mpo_handle_t h, int32_t on, double* ms_out, int64_t* la
     h->prof_on = on != 0;
     return MPO_OK;
   });
+}
+
+mpo_status_t mpo_tuning_set(int32_t mode) {
+  if (mode < -2 || mode >= TUNE_CHOICES) return MPO_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tuner.mu);
+  tuner_load();
+  g_tuner.forced = mode >= 0 ? mode : -1;
+  g_tuner.on = mode != -2;
+  return MPO_OK;
+}
+
+int32_t mpo_tuning_report(char* out, int32_t cap) {
+  std::string txt;
+  {
+    std::lock_guard<std::mutex> lk(g_tuner.mu);
+    tuner_load();
+    for (const auto& kv : g_tuner.table) {
+      const TuneEntry& e = kv.second;
+      int samples = 0;
+      for (const auto& v : e.us) samples += (int)v.size();
+      if (e.chosen >= 0) {
+        const SweepPlan p = plan_of(e.chosen);
+        txt += "gfx950 " + kv.first + " rrc=" + std::to_string(p.rrc) + " graph=" + (p.graph ? "1" : "0") +
+               " us_per_step=" + std::to_string(e.best_us) + "\n";
+      } else {
+        txt += "gfx950 " + kv.first + " tuning samples=" + std::to_string(samples) + "\n";
+      }
+    }
+  }
+  if (out && cap > 0) {
+    const size_t n = std::min(txt.size(), (size_t)cap - 1);
+    std::memcpy(out, txt.data(), n);
+    out[n] = 0;
+  }
+  return (int32_t)txt.size();
 }
 
 const char* mpo_last_error(mpo_handle_t h) { return h ? h->err.c_str() : "null handle"; }

@@ -40,6 +40,8 @@ class RunConfig:
     waves: bool = True                # batch independent updates
     side: str = "both"                # "both" (Alg. 1), "adaptive" or "fixed" (App. A.3)
     fixed_freq: Tuple[int, int] = (1, 1)   # fixed mode: layers of C_L, then of C_R, per period
+    rewire: str = "lazy"              # "lazy" routing per absorbed layer, or "eager" (Alg. 1: transpile,
+                                      # strip transpilation SWAPs, reindex, re-transpile after unswapping)
 
 
 @dataclasses.dataclass
@@ -48,6 +50,7 @@ class Update:
     g_out: Optional[np.ndarray]
     g_in: Optional[np.ndarray]
     stage: str
+    gids: Tuple[int, ...] = ()        # circuit gates this update absorbs (eager rewiring bookkeeping)
 
 
 @dataclasses.dataclass
@@ -106,8 +109,16 @@ def _on_bond(u: np.ndarray, sa: int, sb: int) -> Tuple[int, np.ndarray]:
     raise ValueError("gate is not nearest-neighbour on the sites")
 
 
+def _kind(g) -> Tuple[bool, Optional[int]]:
+    """(is a transpilation SWAP, circuit gate id) of a layer entry: plain
+    (a, b, u) circuit gates, or (a, b, u, is_swap, gid) from transpile()."""
+    return (bool(g[3]), g[4]) if len(g) > 3 else (False, None)
+
+
 def plan_step(lgates, rgates, out_w: Wires, in_w: Wires) -> List[Update]:
-    """Ordered updates of one absorption step; routing changes the layouts."""
+    """Ordered updates of one absorption step; routing changes the layouts.
+    Entries flagged as transpilation SWAPs (eager rewiring) are absorbed as
+    SWAP updates on their side and exchange the two sites in the layout."""
     ups: List[Update] = []
 
     def route(w: Wires, a: int, b: int, side: str):
@@ -116,27 +127,72 @@ def plan_step(lgates, rgates, out_w: Wires, in_w: Wires) -> List[Update]:
             ups.append(Update(j, SWAP if side == "L" else None, SWAP if side == "R" else None, "route"))
             w.exchange(j)
 
+    def tswap(w: Wires, a: int, b: int, side: str):
+        bond, _ = _on_bond(SWAP, int(w.site_of[a]), int(w.site_of[b]))
+        ups.append(Update(bond, SWAP if side == "L" else None, SWAP if side == "R" else None, "route"))
+        w.exchange(bond)
+
     waiting = list(rgates)
-    for (a, b, u) in lgates:
+    for g in lgates:
+        a, b, u = g[0], g[1], g[2]
+        is_swap, gid = _kind(g)
+        if is_swap:
+            tswap(out_w, a, b, "L")
+            continue
         route(out_w, a, b, "L")
         bond, gl = _on_bond(u, int(out_w.site_of[a]), int(out_w.site_of[b]))
         partner = None
-        for j, (ra, rb, _) in enumerate(waiting):
-            sa, sb = int(in_w.site_of[ra]), int(in_w.site_of[rb])
+        for j, rg in enumerate(waiting):
+            if _kind(rg)[0]:
+                continue
+            sa, sb = int(in_w.site_of[rg[0]]), int(in_w.site_of[rg[1]])
             if abs(sa - sb) == 1 and min(sa, sb) == bond:
                 partner = j
                 break
         if partner is None:
-            ups.append(Update(bond, gl, None, "absorb"))
+            ups.append(Update(bond, gl, None, "absorb", (gid,) if gid is not None else ()))
         else:
-            ra, rb, ru = waiting.pop(partner)
-            _, gr = _on_bond(ru, int(in_w.site_of[ra]), int(in_w.site_of[rb]))
-            ups.append(Update(bond, gl, gr, "absorb"))
-    for (a, b, u) in waiting:
+            rg = waiting.pop(partner)
+            _, gr = _on_bond(rg[2], int(in_w.site_of[rg[0]]), int(in_w.site_of[rg[1]]))
+            rid = _kind(rg)[1]
+            ups.append(Update(bond, gl, gr, "absorb", tuple(x for x in (gid, rid) if x is not None)))
+    for g in waiting:
+        a, b, u = g[0], g[1], g[2]
+        is_swap, gid = _kind(g)
+        if is_swap:
+            tswap(in_w, a, b, "R")
+            continue
         route(in_w, a, b, "R")
         bond, gr = _on_bond(u, int(in_w.site_of[a]), int(in_w.site_of[b]))
-        ups.append(Update(bond, None, gr, "absorb"))
+        ups.append(Update(bond, None, gr, "absorb", (gid,) if gid is not None else ()))
     return ups
+
+
+def transpile(gates, w: Wires) -> List[list]:
+    """Alg. 1 "transpile to linear connectivity", for one half of the
+    circuit from the layout `w` (not changed): the gates, in absorption order,
+    each preceded by the SWAPs that bring its qubits next to each other (the
+    qubit on the lower site moves up, as in lazy routing), then layered as
+    soon as possible by the sites they touch.  Entries are
+    (a, b, u, is_swap, gid) on logical qubits: a SWAP carries the two qubits
+    it exchanges and gid None; a circuit gate its id."""
+    w = w.copy()
+    items = []
+    for (a, b, u, gid) in gates:
+        lo, hi = sorted((int(w.site_of[a]), int(w.site_of[b])))
+        for j in range(lo, hi - 1):
+            items.append((j, (int(w.logical_at[j]), int(w.logical_at[j + 1]), SWAP, True, None)))
+            w.exchange(j)
+        items.append((min(int(w.site_of[a]), int(w.site_of[b])), (a, b, u, False, gid)))
+    front = np.zeros(len(w.site_of) + 1, dtype=np.int64)
+    layers: List[list] = []
+    for lo, it in items:
+        l = int(max(front[lo], front[lo + 1]))
+        while len(layers) <= l:
+            layers.append([])
+        layers[l].append(it)
+        front[lo] = front[lo + 1] = l + 1
+    return layers
 
 
 def wave_split(bonds: Sequence[int]) -> List[List[int]]:
@@ -180,6 +236,20 @@ class Contractor:
         self.sizes: List[Tuple[str, int, int]] = []
         if cfg.side not in ("both", "adaptive", "fixed"):
             raise ValueError(f"side must be both, adaptive or fixed, not {cfg.side!r}")
+        if cfg.rewire not in ("lazy", "eager"):
+            raise ValueError(f"rewire must be lazy or eager, not {cfg.rewire!r}")
+        if cfg.rewire == "eager":
+            # the halves as circuit gates with ids, in absorption order; the
+            # absorption queues become their transpiled layers
+            gid = 0
+            self.gates_left, self.gates_right = [], []
+            for dst, layers in ((self.gates_left, self.c_left), (self.gates_right, self.c_right)):
+                for layer in layers:
+                    for (a, b, u) in layer:
+                        dst.append((a, b, u, gid))
+                        gid += 1
+            self.absorbed = set()
+            self.retranspile()
 
     def close(self):
         self.m.close()
@@ -212,12 +282,23 @@ class Contractor:
         rg = self.c_right.pop(0) if self.c_right else []
         return plan_step(lg, rg, self.out_w, self.in_w)
 
+    def retranspile(self) -> None:
+        """Rewiring of Alg. 1 in the eager mode: the circuit gates not yet
+        absorbed (transpilation SWAPs stripped), on the current layouts (the
+        accepted swaps reindex the qubits), transpiled again."""
+        left = [g for g in self.gates_left if g[3] not in self.absorbed]
+        right = [g for g in self.gates_right if g[3] not in self.absorbed]
+        self.c_left = transpile(left, self.out_w)
+        self.c_right = transpile(right, self.in_w)
+
     def record(self, ups: List[Update], infos: List[dict]) -> None:
         for u, r in zip(ups, infos):
             self.trace.append(dict(stage=u.stage, bond=u.bond, k=r["k"], discarded=r["discarded"],
                                    total=r["total"], sweeps=r["sweeps"]))
             if u.stage == "absorb":      # a fused update absorbs one gate of each half
                 self.gates_absorbed += (u.g_out is not None) + (u.g_in is not None)
+            if self.cfg.rewire == "eager":
+                self.absorbed.update(u.gids)
         self.bond_updates += len(ups)
 
     def note_size(self, stage: str) -> None:
@@ -225,54 +306,66 @@ class Contractor:
         of Sec. III.A): one point after every absorption step and unswap stage."""
         self.sizes.append((stage, self.gates_absorbed, self.m.total_elements()))
 
-    def absorb_step(self):
-        """One absorption step under the configured side selection (App. A.3):
-        Alg. 1's alternation takes a layer of each side; the fixed mode takes
-        f_L layers of C_L, then f_R of C_R, in turn; the adaptive mode
-        absorbs the next layer of each side into its own copy of the MPO and
-        keeps the copy with the smaller size(M) (equal: the left one).  Once
-        one side has no layers left, every mode takes the other."""
+    def step_candidates(self) -> List[Tuple[object, List[Update]]]:
+        """The updates of the next absorption step under the configured side
+        selection (App. A.3), as (MPO handle, ordered updates) pairs: one pair,
+        or for an adaptive step two -- the next C_L layer on this MPO and the
+        next C_R layer on a fresh copy of it.  Alg. 1's alternation takes a
+        layer of each side; the fixed mode takes f_L layers of C_L, then f_R
+        of C_R, in turn.  Once one side has no layers left, every mode takes
+        the other.  step_commit() must follow with the updates' results."""
         mode = self.cfg.side
         if mode == "both" or not (self.c_left and self.c_right):
-            taken = "L" if self.c_left else "R"
-            self._execute(self.plan_absorb())
-            if mode == "fixed":                # one side is used up
-                self.trace.append(dict(stage="layer", taken=taken))
-        elif mode == "fixed":
+            self._pending = ("plain", "L" if self.c_left else "R", None)
+            return [(self.m, self.plan_absorb())]
+        if mode == "fixed":
             fl, fr = self.cfg.fixed_freq
             if self.steps % (fl + fr) < fl:
-                self._execute(plan_step(self.c_left.pop(0), [], self.out_w, self.in_w))
-                self.trace.append(dict(stage="layer", taken="L"))
-            else:
-                self._execute(plan_step([], self.c_right.pop(0), self.out_w, self.in_w))
-                self.trace.append(dict(stage="layer", taken="R"))
-        else:
-            self._absorb_adaptive()
-        self.steps += 1
-
-    def _absorb_adaptive(self):
+                self._pending = ("plain", "L", None)
+                return [(self.m, plan_step(self.c_left.pop(0), [], self.out_w, self.in_w))]
+            self._pending = ("plain", "R", None)
+            return [(self.m, plan_step([], self.c_right.pop(0), self.out_w, self.in_w))]
         if self.m2 is None:
             self.m2 = self._mk()
         self.m2.copy_from(self.m)
         wl = (self.out_w.copy(), self.in_w.copy())
         ups_l = plan_step(self.c_left[0], [], *wl)
-        inf_l = self._run_updates(self.m, ups_l)
         wr = (self.out_w.copy(), self.in_w.copy())
         ups_r = plan_step([], self.c_right[0], *wr)
-        inf_r = self._run_updates(self.m2, ups_r)
-        sl, sr = self.m.total_elements(), self.m2.total_elements()
-        if sl <= sr:
-            self.c_left.pop(0)
-            self.out_w, self.in_w = wl
-            self.record(ups_l, inf_l)
-            self.trial_absorb_updates += len(ups_r)
+        self._pending = ("adaptive", None, (wl, wr))
+        return [(self.m, ups_l), (self.m2, ups_r)]
+
+    def step_commit(self, cands, infos) -> None:
+        """Records the step planned by step_candidates(); an adaptive step
+        keeps the copy with the smaller size(M) (equal: the left one), the
+        other layer stays pending."""
+        kind, taken, extra = self._pending
+        self._pending = None
+        if kind == "plain":
+            self.record(cands[0][1], infos[0])
+            if self.cfg.side == "fixed":
+                self.trace.append(dict(stage="layer", taken=taken))
         else:
-            self.c_right.pop(0)
-            self.out_w, self.in_w = wr
-            self.m, self.m2 = self.m2, self.m
-            self.record(ups_r, inf_r)
-            self.trial_absorb_updates += len(ups_l)
-        self.trace.append(dict(stage="side", side="L" if sl <= sr else "R", size_left=sl, size_right=sr))
+            (ups_l, ups_r), (inf_l, inf_r), (wl, wr) = (cands[0][1], cands[1][1]), infos, extra
+            sl, sr = self.m.total_elements(), self.m2.total_elements()
+            if sl <= sr:
+                self.c_left.pop(0)
+                self.out_w, self.in_w = wl
+                self.record(ups_l, inf_l)
+                self.trial_absorb_updates += len(ups_r)
+            else:
+                self.c_right.pop(0)
+                self.out_w, self.in_w = wr
+                self.m, self.m2 = self.m2, self.m
+                self.record(ups_r, inf_r)
+                self.trial_absorb_updates += len(ups_l)
+            self.trace.append(dict(stage="side", side="L" if sl <= sr else "R", size_left=sl, size_right=sr))
+        self.steps += 1
+
+    def absorb_step(self):
+        """One absorption step (step_candidates, the updates, step_commit)."""
+        cands = self.step_candidates()
+        self.step_commit(cands, [self._run_updates(m, ups) for m, ups in cands])
 
     def finish(self) -> RunResult:
         site_bits, p, n2 = self.m.extract_peak()
@@ -301,12 +394,22 @@ class Contractor:
                 self.in_w.exchange(b)
         self.trace.append(dict(stage="unswap", accepted=len(log), size_before=before,
                                size=self.m.total_elements(), log=list(log)))
+        if self.cfg.rewire == "eager":
+            self.retranspile()
 
     def run(self) -> RunResult:
         t0 = time.perf_counter()
         while self.c_left or self.c_right:
+            # at least one layer pair per phase (so the loop progresses when
+            # unswapping cannot get below tau); with eager rewiring, until a
+            # circuit gate is absorbed (leading layers of only transpilation
+            # SWAPs would be unswapped and put back by rewiring, forever)
+            before = self.gates_absorbed
             self.absorb_step()
             self.note_size("absorb")
+            while self.cfg.rewire == "eager" and self.gates_absorbed == before and (self.c_left or self.c_right):
+                self.absorb_step()
+                self.note_size("absorb")
             while not self.m.tau_reached() and (self.c_left or self.c_right):
                 self.absorb_step()
                 self.note_size("absorb")

@@ -122,19 +122,47 @@ def sawtooth(a):
                                                      precision=prec, tau=tau, unswap=sched, relaxed=relaxed,
                                                      side=a.side))
                 t0 = time.perf_counter()
+                last = [t0]
+                orig_step, orig_unswap = c.absorb_step, c.unswap
+
+                def guard(fn, c=c, tag=f"tau {tau:g} {sched}{' relaxed' if relaxed else ''}"):
+                    def run_it():
+                        now = time.perf_counter()
+                        if a.run_limit and now - t0 > a.run_limit:
+                            raise _TimeLimit()
+                        if now - last[0] > 15:
+                            last[0] = now
+                            print(f"  [{tag}] {c.gates_absorbed} gates absorbed, size {c.m.total_elements()}, "
+                                  f"t = {now - t0:.1f} s", flush=True)
+                        return fn()
+                    return run_it
+                c.absorb_step, c.unswap = guard(orig_step), guard(orig_unswap)
+                finished = True
                 try:
                     res = c.run()
-                    secs = time.perf_counter() - t0
-                    cnt = c.m.counters()
-                finally:
-                    c.close()
+                except _TimeLimit:
+                    finished, res = False, None
+                secs = time.perf_counter() - t0
+                cnt = c.m.counters()
+                c.close()
+                if not finished:
+                    run = {"tau": tau, "schedule": sched, "relaxed": relaxed, "precision": prec, "finished": False,
+                           "seconds": round(secs, 3), "bond_updates": c.bond_updates,
+                           "gates_absorbed": c.gates_absorbed, "of_gates": len(circ.gates),
+                           "trial_svds": cnt["trials"], "trials_reused": cnt["trials_reused"],
+                           "unswap_stages": sum(1 for st, g, sz in c.sizes if st == "unswap"),
+                           "max_size": max([sz for st, g, sz in c.sizes] or [0]), "peak_ok": None,
+                           "sizes": [[st[0], g, sz] for st, g, sz in c.sizes]}
+                    runs.append(run)
+                    print(json.dumps(run), flush=True)
+                    continue
                 stages = [(g, sz) for st, g, sz in c.sizes if st == "unswap"]
                 pre = [sz for st, g, sz in c.sizes]
                 drops = []
                 for j, (st, g, sz) in enumerate(c.sizes):
                     if st == "unswap" and j > 0:
                         drops.append(c.sizes[j - 1][2] - sz)
-                run = {"tau": tau, "schedule": sched, "relaxed": relaxed, "precision": prec,
+                run = {"tau": tau, "schedule": sched, "relaxed": relaxed, "precision": prec, "finished": True,
                        "seconds": round(secs, 3), "bond_updates": res.bond_updates,
                        "trial_svds": cnt["trials"], "trials_reused": cnt["trials_reused"],
                        "unswap_stages": len(stages), "max_size": max(pre) if pre else 0,
@@ -143,13 +171,15 @@ def sawtooth(a):
                        "sizes": [[st[0], g, sz] for st, g, sz in c.sizes]}
                 runs.append(run)
                 print(json.dumps(run), flush=True)
-    best = min(runs, key=lambda r: r["seconds"])
+    best = min([r for r in runs if r["finished"]] or runs, key=lambda r: r["seconds"])
     print(json.dumps({"form": "sawtooth", "config": a.config, "n": circ.n, "reading": a.reading,
                       "chi_max": a.chi, "side": a.side, "runs": len(runs),
                       "fastest": {k: best[k] for k in ("tau", "schedule", "relaxed", "seconds")},
-                      "all_peaks_ok": all(r["peak_ok"] for r in runs),
-                      "table": [{k: r[k] for k in ("tau", "schedule", "relaxed", "seconds", "bond_updates",
-                                                   "trial_svds", "unswap_stages", "max_size", "peak_ok")}
+                      "all_finished_peaks_ok": all(r["peak_ok"] for r in runs if r["finished"]),
+                      "run_limit_s": a.run_limit,
+                      "table": [{k: r.get(k) for k in ("tau", "schedule", "relaxed", "finished", "seconds",
+                                                       "bond_updates", "trial_svds", "unswap_stages", "max_size",
+                                                       "peak_ok", "p_peak")}
                                 for r in runs]}), flush=True)
 
 
@@ -157,6 +187,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("form", choices=["batch", "serve", "peak", "sawtooth"])
     ap.add_argument("--taus", default="5e3,2e4,1e5", help="sawtooth: the tau values to run")
+    ap.add_argument("--run-limit", type=float, default=60.0,
+                    help="sawtooth: stop a run after this many seconds and report it unfinished")
     ap.add_argument("--reading", default="A", choices=["A", "B"], help="sawtooth/peak: circuit reading")
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--chi", type=int, default=256)
@@ -178,7 +210,12 @@ def main(argv=None):
     ap.add_argument("--samples", type=int, default=0,
                     help="peak: after the contraction draw this many seeded samples of the output state (Sec. II.C) "
                          "and report the top-20 histogram and the sampled peak weight beside p*")
+    ap.add_argument("--verbose", action="store_true", help="peak: a line for every absorption step over 1 s")
+    ap.add_argument("--n", type=int, default=0, help="peak: a circuit of this width instead of the config's")
+    ap.add_argument("--depth", type=int, default=0, help="peak: R depth with --n (default n/4)")
     ap.add_argument("--count", type=int, default=16)
+    ap.add_argument("--rounds", type=int, default=0,
+                    help="batch: stop both ways after this many lockstep rounds (0: run every circuit to its peak)")
     ap.add_argument("--tau", type=float, default=1e5)
     ap.add_argument("--rate", type=float, default=1.0)
     ap.add_argument("--duration", type=float, default=10.0)
@@ -192,7 +229,10 @@ def main(argv=None):
         return
     if a.form == "peak":
         import time as _t
-        circ = cg.config_circuit(a.config, reading=a.reading)
+        if a.n:
+            circ = cg.mirrored_peaked_circuit(a.n, a.depth or a.n // 4, 1000 * a.config, reading=a.reading)
+        else:
+            circ = cg.config_circuit(a.config, reading=a.reading)
         tau = a.tau if a.tau != 1e5 else 2e4
         out = {"form": "peak", "config": a.config, "n": circ.n, "chi_max": a.chi, "tau": tau, "runs": []}
         for prec in a.precisions.split(","):
@@ -209,14 +249,22 @@ def main(argv=None):
             def step(orig=orig):
                 if a.time_limit and _t.perf_counter() - t0 > a.time_limit:
                     raise _TimeLimit()
+                ts, tr = _t.perf_counter(), c.trial_absorb_updates
                 orig()
                 steps[0] += 1
                 now = _t.perf_counter()
-                if steps[0] % 5 == 0 or now - last[0] > 20:
+                if steps[0] % 5 == 0 or now - last[0] > 20 or (a.verbose and now - ts > 1.0):
                     last[0] = now
+                    side = ""
+                    if c.trace and c.trace[-1].get("stage") == "side":
+                        x = c.trace[-1]
+                        side = (f", took {x['side']} (sizes L {x['size_left']}, R {x['size_right']}), "
+                                f"trial updates {c.trial_absorb_updates - tr}")
                     print(f"  [{prec}] step {steps[0]} of {total_steps}, max chi {max(c.m.bond_dims())}, "
-                          f"updates {c.bond_updates}, t = {done_s + now - t0:.1f} s", flush=True)
-            total_steps = steps[0] + max(len(c.c_left), len(c.c_right))
+                          f"updates {c.bond_updates}{side}, step {now - ts:.1f} s, t = {done_s + now - t0:.1f} s",
+                          flush=True)
+            total_steps = steps[0] + (len(c.c_left) + len(c.c_right) if a.side != "both"
+                                      else max(len(c.c_left), len(c.c_right)))
             c.absorb_step = step
 
             def unswap_by_cycle(c=c, prec=prec):
@@ -289,7 +337,7 @@ def main(argv=None):
                 continue
             circ = cg.mirrored_peaked_circuit(circ.n, circ.meta["depth"], circ.meta["seed"], reading="A")
             work.append((circ, dr.RunConfig(chi_max=min(chi, a.chi_cap), cutoff=1e-8, cutoff_mode="weight",
-                                            precision=prec, tau=a.tau)))
+                                            precision=prec, tau=a.tau, side=a.side)))
         print(f"  batch of {len(work)} circuits, n = {[c.n for c, _ in work]}, "
               f"chi_max = {[c.chi_max for _, c in work]}", flush=True)
         orig = bt.run_round
@@ -301,19 +349,22 @@ def main(argv=None):
                 print(f"  round {rounds[0]} ({'per-update' if per_update else 'grouped'})", flush=True)
             return orig(tasks, group, per_update)
         bt.run_round = counted
-        g = bt.run_batched(work, precision=prec)
+        g = bt.run_batched(work, precision=prec, max_rounds=a.rounds)
         rounds[0] = 0
-        p = bt.run_batched(work, precision=prec, per_update=True)
-        ok = all((r.bits == c.peak).all() for r, (c, _) in zip(g["results"], work))
-        same = all((x.bits == y.bits).all() and x.prob == y.prob for x, y in zip(g["results"], p["results"]))
-        print(json.dumps({"form": "batch", "circuits": len(work), "precision": prec, "tau": a.tau,
-                          "n": [c.n for c, _ in work], "chi_max": [c.chi_max for _, c in work],
+        p = bt.run_batched(work, precision=prec, per_update=True, max_rounds=a.rounds)
+        done = [(r, q, c) for r, q, (c, _) in zip(g["results"], p["results"], work) if r is not None and q is not None]
+        ok = all((r.bits == c.peak).all() for r, q, c in done)
+        same = all((r.bits == q.bits).all() and r.prob == q.prob for r, q, c in done)
+        print(json.dumps({"form": "batch", "circuits": len(work), "precision": prec, "tau": a.tau, "side": a.side,
+                          "rounds_cap": a.rounds, "n": [c.n for c, _ in work], "chi_max": [c.chi_max for _, c in work],
                           "grouped": {"seconds": round(g["seconds"], 3), "bond_updates": g["bond_updates"],
+                                      "rounds": g["rounds"], "finished": g["finished"],
                                       "updates_per_s": round(g["updates_per_s"], 1)},
                           "per_update_launch": {"seconds": round(p["seconds"], 3), "bond_updates": p["bond_updates"],
+                                                "rounds": p["rounds"], "finished": p["finished"],
                                                 "updates_per_s": round(p["updates_per_s"], 1)},
-                          "speedup": round(p["seconds"] / g["seconds"], 3), "peaks_ok": bool(ok),
-                          "grouped_equals_per_update": bool(same)}), flush=True)
+                          "speedup": round(p["seconds"] / g["seconds"], 3), "finished_both": len(done),
+                          "peaks_ok": bool(ok), "grouped_equals_per_update": bool(same)}), flush=True)
     else:
         prec = a.precision or "mixed"
         cfg = dr.RunConfig(chi_max=min(512, a.chi_cap), cutoff=1e-8, cutoff_mode="weight", precision=prec,

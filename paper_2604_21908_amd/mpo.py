@@ -24,10 +24,11 @@ SIDE_NAMES = {0: "L", 1: "R", 2: "B"}
 EXPORTED = ["mpo_init_identity", "mpo_absorb_gate_pair", "mpo_absorb_gate_pair_noalloc", "mpo_absorb_batch", "mpo_unswap_sweep",
             "mpo_extract_peak", "mpo_sample", "mpo_free", "mpo_bond_dims", "mpo_total_elements", "mpo_singular_values",
             "mpo_read_site", "mpo_load_state", "mpo_sync", "mpo_copy_state", "mpo_tau_reached", "mpo_trial_swap", "mpo_counters",
-            "mpo_profile", "mpo_last_error", "mpo_version",
+            "mpo_profile", "mpo_tuning_report", "mpo_tuning_set", "mpo_last_error", "mpo_version",
             "mpo_group_create", "mpo_group_free", "mpo_group_absorb", "mpo_group_unswap", "mpo_group_profile",
             "mpo_group_last_error"]
-COUNTERS = ["updates", "trials", "trials_reused", "commits_undone", "hook_allocs"]
+COUNTERS = ["updates", "trials", "trials_reused", "commits_undone", "hook_allocs", "graph_replays",
+            "graph_captures"]
 PROF_CLASSES = ["theta_gemm", "gate", "jacobi_init", "jacobi_gram", "finalize", "writeback", "writeback_gemm", "qr",
                 "reorth", "jacobi_evd", "jacobi_rot"]
 
@@ -103,6 +104,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mpo_trial_swap.argtypes = [P, I32, I32, ctypes.POINTER(UpdateInfo)]
     lib.mpo_counters.argtypes = [P, ctypes.POINTER(I64), I32]
     lib.mpo_profile.argtypes = [P, I32, dp, ctypes.POINTER(I64)]
+    lib.mpo_tuning_report.argtypes = [ctypes.c_char_p, I32]
+    lib.mpo_tuning_report.restype = ctypes.c_int32
+    lib.mpo_tuning_set.argtypes = [I32]
     lib.mpo_last_error.argtypes = [P]
     lib.mpo_last_error.restype = ctypes.c_char_p
     lib.mpo_version.argtypes = []
@@ -450,6 +454,22 @@ class Group:
         if s != 0:
             raise MpoError(s, "mpo_group_profile")
         return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(PROF_CLASSES)}
+
+
+def tuning_report() -> str:
+    """The sweep autotuner's table (mpo_tuning_report)."""
+    lib = load_library()
+    n = lib.mpo_tuning_report(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib.mpo_tuning_report(buf, n + 1)
+    return buf.value.decode()
+
+
+def tuning_set(mode: int) -> None:
+    """mpo_tuning_set: -1 autotuner, -2 fixed defaults, 0..5 one choice."""
+    s = load_library().mpo_tuning_set(int(mode))
+    if s != 0:
+        raise MpoError(s, "mpo_tuning_set")
 
 
 def version() -> str:

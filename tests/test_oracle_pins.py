@@ -457,3 +457,75 @@ def test_planted_mistakes_are_caught(monkeypatch):
     assert not run()
     monkeypatch.setattr(mo, "apply_gates_to_theta", lambda t, a, b: orig(t, b, a))
     assert not run()
+
+
+# ---------------------------------------------- all-to-all input, eager rewiring
+@pytest.mark.parametrize("reading", ["A", "B"])
+def test_all_to_all_generator_is_planted(reading):
+    """Gates on arbitrary pairs (random matchings, selection-sort SWAPs):
+    the circuit operator is still X^b K, so the statevector's argmax is b
+    with the closed-form probability."""
+    c = cg.mirrored_peaked_circuit(8, 3, 5, reading=reading, connectivity="all")
+    assert sum(1 for q0, q1, _ in c.gates if abs(q0 - q1) > 1) > 5
+    psi = bf.circuit_state(c.n, c.gates)
+    idx = int(np.argmax(np.abs(psi) ** 2))
+    assert np.array_equal(bf.bits_of(idx, c.n), c.peak)
+    assert abs(abs(psi[idx]) ** 2 - bf.peak_probability_closed_form(c.n, c.k_gates)) < 1e-12
+
+
+def test_transpile_linear_is_nearest_neighbour_and_exact():
+    """Alg. 1 step 1: the transpiled half is nearest-neighbour on the sites,
+    and replaying it on a dense state (circuit gates on their logical qubits,
+    SWAPs exchanging the two logical qubits' sites) equals the original
+    gates followed by the permutation the SWAPs made."""
+    rng = np.random.default_rng(4)
+    n = 6
+    gates = [(int(a), int(b), cg.haar_su4(rng), j)
+             for j, (a, b) in enumerate(rng.permuted(np.tile(np.arange(n), (8, 1)), axis=1)[:, :2])]
+    lay = mo.Layout(n)
+    layers = mo.transpile_linear(gates, lay)
+    site_of, logical_at = list(range(n)), list(range(n))
+    seen = []
+    for layer in layers:
+        used = set()
+        for (a, b, u, is_swap, gid) in layer:
+            sa, sb = site_of[a], site_of[b]
+            assert abs(sa - sb) == 1 and not ({sa, sb} & used)
+            used |= {sa, sb}
+            if is_swap:
+                logical_at[sa], logical_at[sb] = b, a
+                site_of[a], site_of[b] = sb, sa
+            else:
+                seen.append(gid)
+    assert sorted(seen) == list(range(len(gates)))       # every gate once (ASAP may reorder commuting ones)
+    # dense check: apply the entries in layer order on site-indexed qubits
+    psi = bf.circuit_state(n, [])
+    site_of = list(range(n))
+    for layer in layers:
+        for (a, b, u, is_swap, gid) in layer:
+            sa, sb = site_of[a], site_of[b]
+            if is_swap:
+                psi = bf.apply_gate_state(psi.reshape([2] * n), n, sa, sb, mo.SWAP4).reshape(-1)
+                site_of[a], site_of[b] = sb, sa
+            else:
+                psi = bf.apply_gate_state(psi.reshape([2] * n), n, sa, sb, u).reshape(-1)
+    ref = bf.circuit_state(n, [(a, b, u) for (a, b, u, _) in gates])
+    # ref is on logical qubits; psi on sites: logical q sits at site site_of[q]
+    ref_sites = ref.reshape([2] * n).transpose(np.argsort(site_of)).reshape(-1)
+    assert np.allclose(psi, ref_sites, atol=1e-12)
+
+
+@pytest.mark.parametrize("side", ["both", "adaptive"])
+@pytest.mark.parametrize("reading", ["A", "B"])
+def test_eager_rewiring_reproduces_dense_unitary(side, reading):
+    """Alg. 1 with eager rewiring (transpile, strip the transpilation SWAPs
+    after unswapping, reindex, re-transpile) on an all-to-all circuit: the
+    contracted operator is the circuit's unitary, the peak is b."""
+    c = cg.mirrored_peaked_circuit(6, 2, 5, reading=reading, connectivity="all")
+    for rewire in ("lazy", "eager"):
+        res = mo.contract(c.n, c.gates, mo.OracleConfig(chi_max=256, cutoff=1e-12, tau=200, unswap="parallel",
+                                                        rewire=rewire, side=side))
+        full = mo.full_operator(res) * 2 ** (c.n / 2)
+        assert np.allclose(full, bf.circuit_unitary(c.n, c.gates), atol=1e-9), rewire
+        assert np.array_equal(res.bits, c.peak)
+        assert any(t.get("stage") == "unswap" and t["accepted"] for t in res.trace)
