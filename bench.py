@@ -325,13 +325,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
-    ap.add_argument("--compare", default="fp32", help="second precision timed in the same run ('' for none)")
+    ap.add_argument("--compare", default="fp32", help="second precision timed in the same run ('' or none: no second)")
     ap.add_argument("--chi", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mirrored", action="store_true", help="skip the mirrored-pair (G_in = G_out^dag) leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
+    if args.compare == "none":
+        args.compare = ""
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the bond update runs on a "
               f"single GPU and there is no multi-GPU path", file=sys.stderr)
@@ -388,6 +391,15 @@ def main():
         precs = [args.precision] + ([args.compare] if args.compare and args.compare != args.precision else [])
         out["accuracy_vs_fp64_oracle"] = {p: accuracy(mpolib, p, n, sites, lams, bond, chi, gates[0], ref)
                                           for p in precs}
+    if not args.no_mirrored:
+        # the same update with mirrored pairs (G_in = G_out^dag, the structure of
+        # the circuits' two halves), headline precision, no per-launch events
+        mgates = [(g, g.conj().T.copy()) for g, _ in gates]
+        mrun = run_precision(mpolib, torch, args.precision, args, n, sites, lams, bond, mgates, events=False)
+        out["mirrored_pair"] = {"value": round(args.steps / mrun["secs"], 4),
+                                "ms_per_step": round(1e3 * mrun["secs"] / args.steps, 3),
+                                "jacobi_sweeps": [i["sweeps"] for i in mrun["infos"]],
+                                "kept_rank": [i["k"] for i in mrun["infos"]]}
     out["paper_context"] = {"value": 4059, "unit": "s", "hardware": "1x NVIDIA A100 80 GB",
                             "what": "the paper's whole contraction and peak readout of its 56-qubit, 1,917-gate "
                                     "circuit (Sec. III); another workload and machine, not comparable to the "

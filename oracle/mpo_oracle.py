@@ -371,6 +371,7 @@ class OracleConfig:
     side: str = "both"              # "both" (Alg. 1), "adaptive" or "fixed" (App. A.3)
     fixed_freq: Tuple[int, int] = (1, 1)   # fixed mode: layers of C_L, then of C_R, per period
     rewire: str = "lazy"            # "lazy" or "eager" (Alg. 1 / Sec. II.B.3 taken literally)
+    router: str = "up"              # "up": the lower qubit climbs; "middle": both meet halfway
 
 
 class Layout:
@@ -395,7 +396,7 @@ def orient(u: np.ndarray, sa: int, sb: int) -> Tuple[int, np.ndarray]:
     return sb, SWAP4 @ u @ SWAP4
 
 
-def transpile_linear(gates, lay: "Layout") -> List[list]:
+def transpile_linear(gates, lay: "Layout", router: str = "up") -> List[list]:
     """Alg. 1 "transpile C to linear connectivity" for the gates of one half
     (in the order they are absorbed), starting from layout `lay` (left as
     is).  Before each gate, SWAPs on consecutive sites carry the qubit on
@@ -405,8 +406,15 @@ def transpile_linear(gates, lay: "Layout") -> List[list]:
     site_of, logical_at = list(lay.site_of), list(lay.logical_at)
     seq = []                                  # (lower site, entry)
     for (a, b, u, gid) in gates:
+        climb = None
         while abs(site_of[a] - site_of[b]) > 1:
-            j = min(site_of[a], site_of[b])
+            lo, hi = min(site_of[a], site_of[b]), max(site_of[a], site_of[b])
+            if climb is None:               # SWAPs the lower qubit makes ("middle": half the gap)
+                climb = hi - lo - 1 if router == "up" else (hi - lo) // 2
+            if climb > 0:
+                j, climb = lo, climb - 1
+            else:
+                j = hi - 1
             x, y = logical_at[j], logical_at[j + 1]
             seq.append((j, (x, y, SWAP4, True, None)))
             logical_at[j], logical_at[j + 1] = y, x
@@ -479,8 +487,9 @@ class Contraction:
             raise ValueError(cfg.rewire)
 
     def _retranspile(self):
-        self.left = transpile_linear([g for g in self.half_l if g[3] not in self.done_ids], self.lay_l)
-        self.right = transpile_linear([g for g in self.half_r if g[3] not in self.done_ids], self.lay_r)
+        self.left = transpile_linear([g for g in self.half_l if g[3] not in self.done_ids], self.lay_l, self.cfg.router)
+        self.right = transpile_linear([g for g in self.half_r if g[3] not in self.done_ids], self.lay_r,
+                                      self.cfg.router)
 
     # ------------------------------------------------------------- updates
     def _update(self, i, g_out, g_in, stage, fused=False):
@@ -497,7 +506,14 @@ class Contraction:
     def _route(self, lay: Layout, a: int, b: int, side: str) -> Tuple[int, int]:
         sa, sb = lay.site_of[a], lay.site_of[b]
         lo, hi = min(sa, sb), max(sa, sb)
-        for j in range(lo, hi - 1):
+        if self.cfg.router == "up":
+            bonds = list(range(lo, hi - 1))
+        else:
+            # the lower qubit climbs ceil((gap - 1) / 2) sites, the upper one
+            # comes down the rest
+            up = (hi - lo) // 2
+            bonds = [lo + t for t in range(up)] + [hi - 1 - t for t in range(hi - lo - 1 - up)]
+        for j in bonds:
             if side == "L":
                 self._update(j, SWAP4, None, "route")
             else:

@@ -42,6 +42,7 @@ class RunConfig:
     fixed_freq: Tuple[int, int] = (1, 1)   # fixed mode: layers of C_L, then of C_R, per period
     rewire: str = "lazy"              # "lazy" routing per absorbed layer, or "eager" (Alg. 1: transpile,
                                       # strip transpilation SWAPs, reindex, re-transpile after unswapping)
+    router: str = "up"                # routing of non-adjacent gates: "up" or "middle" (see route_bonds)
 
 
 @dataclasses.dataclass
@@ -115,7 +116,17 @@ def _kind(g) -> Tuple[bool, Optional[int]]:
     return (bool(g[3]), g[4]) if len(g) > 3 else (False, None)
 
 
-def plan_step(lgates, rgates, out_w: Wires, in_w: Wires) -> List[Update]:
+def route_bonds(lo: int, hi: int, router: str = "up") -> List[int]:
+    """Bonds of the SWAPs that make sites lo < hi neighbours, in order.
+    "up": the qubit on the lower site climbs to hi - 1.  "middle": it climbs
+    half the gap (rounded up), then the upper qubit descends the rest."""
+    if router == "up":
+        return list(range(lo, hi - 1))
+    k = (hi - lo) // 2
+    return list(range(lo, lo + k)) + list(range(hi - 1, lo + k, -1))
+
+
+def plan_step(lgates, rgates, out_w: Wires, in_w: Wires, router: str = "up") -> List[Update]:
     """Ordered updates of one absorption step; routing changes the layouts.
     Entries flagged as transpilation SWAPs (eager rewiring) are absorbed as
     SWAP updates on their side and exchange the two sites in the layout."""
@@ -123,7 +134,7 @@ def plan_step(lgates, rgates, out_w: Wires, in_w: Wires) -> List[Update]:
 
     def route(w: Wires, a: int, b: int, side: str):
         lo, hi = sorted((int(w.site_of[a]), int(w.site_of[b])))
-        for j in range(lo, hi - 1):
+        for j in route_bonds(lo, hi, router):
             ups.append(Update(j, SWAP if side == "L" else None, SWAP if side == "R" else None, "route"))
             w.exchange(j)
 
@@ -168,7 +179,7 @@ def plan_step(lgates, rgates, out_w: Wires, in_w: Wires) -> List[Update]:
     return ups
 
 
-def transpile(gates, w: Wires) -> List[list]:
+def transpile(gates, w: Wires, router: str = "up") -> List[list]:
     """Alg. 1 "transpile to linear connectivity", for one half of the
     circuit from the layout `w` (not changed): the gates, in absorption order,
     each preceded by the SWAPs that bring its qubits next to each other (the
@@ -180,7 +191,7 @@ def transpile(gates, w: Wires) -> List[list]:
     items = []
     for (a, b, u, gid) in gates:
         lo, hi = sorted((int(w.site_of[a]), int(w.site_of[b])))
-        for j in range(lo, hi - 1):
+        for j in route_bonds(lo, hi, router):
             items.append((j, (int(w.logical_at[j]), int(w.logical_at[j + 1]), SWAP, True, None)))
             w.exchange(j)
         items.append((min(int(w.site_of[a]), int(w.site_of[b])), (a, b, u, False, gid)))
@@ -280,7 +291,7 @@ class Contractor:
         updates of that absorption step (layouts change by routing)."""
         lg = self.c_left.pop(0) if self.c_left else []
         rg = self.c_right.pop(0) if self.c_right else []
-        return plan_step(lg, rg, self.out_w, self.in_w)
+        return plan_step(lg, rg, self.out_w, self.in_w, self.cfg.router)
 
     def retranspile(self) -> None:
         """Rewiring of Alg. 1 in the eager mode: the circuit gates not yet
@@ -288,8 +299,8 @@ class Contractor:
         accepted swaps reindex the qubits), transpiled again."""
         left = [g for g in self.gates_left if g[3] not in self.absorbed]
         right = [g for g in self.gates_right if g[3] not in self.absorbed]
-        self.c_left = transpile(left, self.out_w)
-        self.c_right = transpile(right, self.in_w)
+        self.c_left = transpile(left, self.out_w, self.cfg.router)
+        self.c_right = transpile(right, self.in_w, self.cfg.router)
 
     def record(self, ups: List[Update], infos: List[dict]) -> None:
         for u, r in zip(ups, infos):
@@ -322,16 +333,16 @@ class Contractor:
             fl, fr = self.cfg.fixed_freq
             if self.steps % (fl + fr) < fl:
                 self._pending = ("plain", "L", None)
-                return [(self.m, plan_step(self.c_left.pop(0), [], self.out_w, self.in_w))]
+                return [(self.m, plan_step(self.c_left.pop(0), [], self.out_w, self.in_w, self.cfg.router))]
             self._pending = ("plain", "R", None)
-            return [(self.m, plan_step([], self.c_right.pop(0), self.out_w, self.in_w))]
+            return [(self.m, plan_step([], self.c_right.pop(0), self.out_w, self.in_w, self.cfg.router))]
         if self.m2 is None:
             self.m2 = self._mk()
         self.m2.copy_from(self.m)
         wl = (self.out_w.copy(), self.in_w.copy())
-        ups_l = plan_step(self.c_left[0], [], *wl)
+        ups_l = plan_step(self.c_left[0], [], *wl, self.cfg.router)
         wr = (self.out_w.copy(), self.in_w.copy())
-        ups_r = plan_step([], self.c_right[0], *wr)
+        ups_r = plan_step([], self.c_right[0], *wr, self.cfg.router)
         self._pending = ("adaptive", None, (wl, wr))
         return [(self.m, ups_l), (self.m2, ups_r)]
 

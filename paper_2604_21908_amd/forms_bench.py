@@ -83,6 +83,34 @@ def _load_state(path, c):
     return steps, float(z["seconds"]), int(z["max_k"])
 
 
+def p_closed(circ) -> float:
+    """|<0^n|K|0^n>|^2, the probability of the planted peak (C = X^b K as an
+    operator): the product of K|0^n>'s prefix conditionals P(x_j = 0 | 0..0),
+    which the generator already evaluates exactly for its admissibility
+    check (K's two brickwork layers in their order)."""
+    n = circ.n
+    first = len(cg.brickwork_pairs(n, 0))
+    layers = [circ.k_gates[:first], circ.k_gates[first:]]
+    return float(np.prod(cg.k_prefix_conditionals(n, layers)))
+
+
+def peak_checks(results, circuits) -> dict:
+    """Planted bits bit-exact and p within 1e-3 relative of the closed form
+    (plus the discarded weight the run reports) for every finished circuit."""
+    bits_ok = p_ok = 0
+    worst = 0.0
+    for r, circ in zip(results, circuits):
+        if r is None:
+            continue
+        bits_ok += bool((r.bits == circ.peak).all())
+        pc = p_closed(circ)
+        disc = sum(t.get("discarded", 0.0) for t in r.trace)
+        err = abs(r.prob - pc) / pc
+        worst = max(worst, err)
+        p_ok += err <= 1e-3 + disc / pc
+    return {"bits_ok": bits_ok, "p_ok": p_ok, "worst_p_rel_err": worst}
+
+
 def sample_report(c, circ, count, p_exact, seed=2026):
     """Sec. II.C / Fig. 4 on a contracted circuit: `count` samples of the
     output state (mpo_sample, seeded uniforms), mapped to logical qubits by
@@ -120,7 +148,7 @@ def sawtooth(a):
             for relaxed in (False, True):
                 c = dr.Contractor(circ, dr.RunConfig(chi_max=a.chi, cutoff=1e-8, cutoff_mode="weight",
                                                      precision=prec, tau=tau, unswap=sched, relaxed=relaxed,
-                                                     side=a.side))
+                                                     side=a.side, router=a.router))
                 t0 = time.perf_counter()
                 last = [t0]
                 orig_step, orig_unswap = c.absorb_step, c.unswap
@@ -211,8 +239,12 @@ def main(argv=None):
                     help="peak: after the contraction draw this many seeded samples of the output state (Sec. II.C) "
                          "and report the top-20 histogram and the sampled peak weight beside p*")
     ap.add_argument("--verbose", action="store_true", help="peak: a line for every absorption step over 1 s")
+    ap.add_argument("--router", default="middle", choices=["up", "middle"],
+                    help="routing of non-adjacent gates (the measured workloads use middle)")
+    ap.add_argument("--rewire", default="lazy", choices=["lazy", "eager"], help="peak: rewiring mode")
     ap.add_argument("--n", type=int, default=0, help="peak: a circuit of this width instead of the config's")
     ap.add_argument("--depth", type=int, default=0, help="peak: R depth with --n (default n/4)")
+    ap.add_argument("--seed", type=int, default=-1, help="peak: generator seed with --n (default 1000 * config)")
     ap.add_argument("--count", type=int, default=16)
     ap.add_argument("--rounds", type=int, default=0,
                     help="batch: stop both ways after this many lockstep rounds (0: run every circuit to its peak)")
@@ -230,14 +262,16 @@ def main(argv=None):
     if a.form == "peak":
         import time as _t
         if a.n:
-            circ = cg.mirrored_peaked_circuit(a.n, a.depth or a.n // 4, 1000 * a.config, reading=a.reading)
+            circ = cg.mirrored_peaked_circuit(a.n, a.depth or a.n // 4, a.seed if a.seed >= 0 else 1000 * a.config,
+                                              reading=a.reading)
         else:
             circ = cg.config_circuit(a.config, reading=a.reading)
         tau = a.tau if a.tau != 1e5 else 2e4
         out = {"form": "peak", "config": a.config, "n": circ.n, "chi_max": a.chi, "tau": tau, "runs": []}
         for prec in a.precisions.split(","):
             c = dr.Contractor(circ, dr.RunConfig(chi_max=a.chi, cutoff=1e-8, cutoff_mode="weight", precision=prec,
-                                                 tau=tau, unswap="parallel", side=a.side))
+                                                 tau=tau, unswap="parallel", side=a.side, router=a.router,
+                                                 rewire=a.rewire))
             steps = [0]
             done_s, max_k0 = 0.0, 1
             if a.resume:
@@ -316,7 +350,8 @@ def main(argv=None):
             c.close()
             ks = [x["k"] for x in res.trace if "k" in x]
             secs = done_s + res.seconds
-            out["runs"].append({"precision": prec, "side": a.side, "finished": True, "time_to_peak_s": round(secs, 3),
+            out["runs"].append({"precision": prec, "side": a.side, "router": a.router, "rewire": a.rewire,
+                                "finished": True, "time_to_peak_s": round(secs, 3),
                                 "resumed": bool(a.resume), "bond_updates": res.bond_updates,
                                 "trial_absorb_updates": c.trial_absorb_updates,
                                 "max_chi": max([max_k0] + ks),
@@ -337,16 +372,19 @@ def main(argv=None):
                 continue
             circ = cg.mirrored_peaked_circuit(circ.n, circ.meta["depth"], circ.meta["seed"], reading="A")
             work.append((circ, dr.RunConfig(chi_max=min(chi, a.chi_cap), cutoff=1e-8, cutoff_mode="weight",
-                                            precision=prec, tau=a.tau, side=a.side)))
+                                            precision=prec, tau=a.tau, side=a.side, router=a.router)))
         print(f"  batch of {len(work)} circuits, n = {[c.n for c, _ in work]}, "
               f"chi_max = {[c.chi_max for _, c in work]}", flush=True)
         orig = bt.run_round
         rounds = [0]
+        last = [time.perf_counter()]
 
         def counted(tasks, group, per_update=False):
             rounds[0] += 1
-            if rounds[0] % 10 == 0:
-                print(f"  round {rounds[0]} ({'per-update' if per_update else 'grouped'})", flush=True)
+            if rounds[0] % 10 == 0 or time.perf_counter() - last[0] > 15:
+                last[0] = time.perf_counter()
+                print(f"  round {rounds[0]} ({'per-update' if per_update else 'grouped'}), "
+                      f"{sum(1 for t in tasks if t.done)} of {len(tasks)} finished", flush=True)
             return orig(tasks, group, per_update)
         bt.run_round = counted
         g = bt.run_batched(work, precision=prec, max_rounds=a.rounds)
@@ -355,7 +393,9 @@ def main(argv=None):
         done = [(r, q, c) for r, q, (c, _) in zip(g["results"], p["results"], work) if r is not None and q is not None]
         ok = all((r.bits == c.peak).all() for r, q, c in done)
         same = all((r.bits == q.bits).all() and r.prob == q.prob for r, q, c in done)
+        checks = peak_checks(g["results"], [c for c, _ in work])
         print(json.dumps({"form": "batch", "circuits": len(work), "precision": prec, "tau": a.tau, "side": a.side,
+                          "router": a.router,
                           "rounds_cap": a.rounds, "n": [c.n for c, _ in work], "chi_max": [c.chi_max for _, c in work],
                           "grouped": {"seconds": round(g["seconds"], 3), "bond_updates": g["bond_updates"],
                                       "rounds": g["rounds"], "finished": g["finished"],
@@ -364,19 +404,21 @@ def main(argv=None):
                                                 "rounds": p["rounds"], "finished": p["finished"],
                                                 "updates_per_s": round(p["updates_per_s"], 1)},
                           "speedup": round(p["seconds"] / g["seconds"], 3), "finished_both": len(done),
-                          "peaks_ok": bool(ok), "grouped_equals_per_update": bool(same)}), flush=True)
+                          "peaks_ok": bool(ok), "grouped_equals_per_update": bool(same),
+                          "closed_form_checks": checks}), flush=True)
     else:
         prec = a.precision or "mixed"
         cfg = dr.RunConfig(chi_max=min(512, a.chi_cap), cutoff=1e-8, cutoff_mode="weight", precision=prec,
-                           tau=a.tau)
+                           tau=a.tau, side=a.side, router=a.router)
         reqs = [r for r in sv.poisson_requests(a.rate, a.duration) if r.n <= a.max_n]
         print(f"  {len(reqs)} requests, n = {[r.n for r in reqs]}", flush=True)
         out = sv.serve(reqs, cfg, int(a.budget_gb * 2 ** 30), on_round=_progress("serve"))
         print("  sequential FP32 baseline", flush=True)
         base_cfg = dr.RunConfig(chi_max=cfg.chi_max, cutoff=cfg.cutoff, cutoff_mode=cfg.cutoff_mode,
-                                precision="fp32", tau=cfg.tau)
+                                precision="fp32", tau=cfg.tau, side=cfg.side, router=cfg.router)
         seq = sv.serve_sequential(reqs, base_cfg)
-        print(json.dumps({"form": "serve", "rate": a.rate, "duration": a.duration, "requests": len(reqs),
+        print(json.dumps({"form": "serve", "rate": a.rate, "duration": a.duration, "requests": len(reqs), "side": a.side,
+                          "router": a.router,
                           "chi_max": cfg.chi_max, "max_n": a.max_n,
                           "served": len(out["served"]), "precision": prec, "seconds": round(out["seconds"], 3),
                           "circuits_per_s": round(out["circuits_per_s"], 4), "p50_time_to_peak_s": round(out["p50"], 3),

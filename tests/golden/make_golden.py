@@ -9,6 +9,13 @@ parallel unswapping), contracted by the oracle (Alg. 1 with App. A.1): the
 peak bits and probability of the readout, the final bond dimensions and
 singular values; and the argmax of |<x|C|0>|^2 over all 2^10 bitstrings from
 the dense statevector, with its probability.
+
+config2_middle.json: the n = 56 circuit of the precision workload (literal
+reading, R depth 12, chi_max 1024, discarded-weight cutoff 1e-8, tau 2e4,
+parallel unswapping, Alg. 1 alternation, routing rule "middle"), contracted
+by the oracle (about a minute): the kept rank of every update in order, the
+peak bits and probability, the final bond dimensions and singular values,
+the summed discarded weight, and the closed form |<0|K|0>|^2.
 """
 import json
 import os
@@ -48,5 +55,29 @@ def main():
           "brute p", out["brute"]["prob"])
 
 
+CFG2 = dict(chi_max=1024, cutoff=1e-8, mode="weight", tau=2e4, unswap="parallel", side="both", router="middle")
+
+
+def config2():
+    circ = cg.config_circuit(2, reading="A")
+    res = mo.contract(circ.n, circ.gates, mo.OracleConfig(**CFG2))
+    out = {
+        "circuit": {"workload": 2, "index": 0, "reading": "A", "n": circ.n, "depth": circ.meta["depth"],
+                    "seed": circ.meta["seed"], "gates": len(circ.gates), "planted_peak": [int(b) for b in circ.peak]},
+        "config": CFG2,
+        "oracle": {"bits": [int(b) for b in res.bits], "prob": float(res.prob),
+                   "ranks": [int(t["k"]) for t in res.trace if "k" in t],
+                   "discarded": float(sum(t.get("discarded", 0.0) for t in res.trace)),
+                   "bond_dims": res.mpo.bond_dims(),
+                   "lambdas": [[float(v) for v in l] for l in res.mpo.lam]},
+        "closed_form_prob": float(bf.peak_probability_closed_form(circ.n, circ.k_gates)),
+    }
+    with open(os.path.join(HERE, "config2_middle.json"), "w") as f:
+        json.dump(out, f)
+    print("wrote config2_middle.json: updates", len(out["oracle"]["ranks"]), "p", out["oracle"]["prob"],
+          "closed form", out["closed_form_prob"])
+
+
 if __name__ == "__main__":
     main()
+    config2()

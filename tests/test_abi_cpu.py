@@ -83,9 +83,11 @@ def test_time_layers_and_split_match_the_oracle():
     assert [[(g[0], g[1]) for g in l] for l in a] == [[(g[0], g[1]) for g in l] for l in b]
 
 
-def test_plan_step_matches_the_oracle_update_sequence():
+@pytest.mark.parametrize("router", ["up", "middle"])
+def test_plan_step_matches_the_oracle_update_sequence(router):
     """The driver's ordered update list (routing, fusion, orientation) equals
-    the oracle's on layouts scrambled by random swaps."""
+    the oracle's on layouts scrambled by random swaps, under both routing
+    rules."""
     rng = np.random.default_rng(0)
     for trial in range(20):
         n = int(rng.integers(4, 10))
@@ -93,7 +95,7 @@ def test_plan_step_matches_the_oracle_update_sequence():
         layers = dr.time_layers(c.gates, n)
         lg, rg = layers[len(layers) // 2], layers[len(layers) // 2 - 1]
         out_w, in_w = dr.Wires(n), dr.Wires(n)
-        ct = mo.Contraction(n, [], mo.OracleConfig())
+        ct = mo.Contraction(n, [], mo.OracleConfig(router=router))
         for _ in range(int(rng.integers(0, 3 * n))):
             j = int(rng.integers(0, n - 1))
             if rng.random() < 0.5:
@@ -102,7 +104,7 @@ def test_plan_step_matches_the_oracle_update_sequence():
             else:
                 in_w.exchange(j)
                 ct.lay_r.swap_sites(j)
-        ups = dr.plan_step(lg, rg, out_w, in_w)
+        ups = dr.plan_step(lg, rg, out_w, in_w, router)
         seen = []
         ct._update = lambda i, go, gi, stage, fused=False: seen.append((i, go, gi, stage))
         ct.left, ct.right = [lg], [rg]

@@ -1,0 +1,52 @@
+"""The precision workload end to end on the GPU: the n = 56 circuit (literal
+reading, R depth 12, 2,286 gates, chi_max 1024, discarded-weight cutoff
+1e-8, parallel unswapping at tau 2e4, Alg. 1 alternation, routing rule
+"middle") against the oracle's contraction of the same circuit and settings
+stored in tests/golden/config2_middle.json (written by
+tests/golden/make_golden.py from the oracle only).  In every form: the kept
+rank of every update in order and the peak bits equal; the final bond
+values normwise within the form's tolerance (1e-10 FP64, 1e-4 FP32 and
+mixed); the peak probability within 1e-9 (FP64) or 1e-3 (FP32, mixed)
+relative of the oracle's and of the closed form |<0|K|0>|^2."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2604_21908_amd import circuitgen as cg
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {"fp64": 1e-10, "fp32": 1e-4, "mixed": 1e-4}
+PTOL = {"fp64": 1e-9, "fp32": 1e-3, "mixed": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def gold():
+    with open(os.path.join(HERE, "golden", "config2_middle.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32", "fp64"])
+def test_config2_contraction_matches_oracle(gold, prec):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2604_21908_amd import driver as dr
+    cfg = gold["config"]
+    circ = cg.config_circuit(2, reading="A")
+    assert len(circ.gates) == gold["circuit"]["gates"]
+    c = dr.Contractor(circ, dr.RunConfig(chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], cutoff_mode=cfg["mode"],
+                                         precision=prec, tau=cfg["tau"], unswap=cfg["unswap"], side=cfg["side"],
+                                         router=cfg["router"]))
+    res = c.run()
+    lams = [c.m.singular_values(b) for b in range(circ.n - 1)]
+    c.close()
+    ref = gold["oracle"]
+    assert [t["k"] for t in res.trace if "k" in t] == ref["ranks"]
+    assert [int(b) for b in res.bits] == ref["bits"] == gold["circuit"]["planted_peak"]
+    assert abs(res.prob - ref["prob"]) <= PTOL[prec] * ref["prob"]
+    assert abs(res.prob - gold["closed_form_prob"]) <= PTOL[prec] * gold["closed_form_prob"]
+    for a, r in zip(lams, ref["lambdas"]):
+        r = np.asarray(r)
+        assert len(a) == len(r) and np.max(np.abs(a - r)) <= TOL[prec] * np.linalg.norm(r)

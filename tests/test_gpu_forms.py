@@ -17,7 +17,8 @@ TOL = {"fp64": 1e-10, "fp32": 1e-4, "mixed": 1e-4}
 def oracle_of(circ, cfg):
     return mo.contract(circ.n, circ.gates, mo.OracleConfig(chi_max=cfg.chi_max, cutoff=cfg.cutoff,
                                                            mode=cfg.cutoff_mode, tau=cfg.tau, unswap=cfg.unswap,
-                                                           relaxed=cfg.relaxed))
+                                                           relaxed=cfg.relaxed, side=cfg.side,
+                                                           fixed_freq=cfg.fixed_freq, rewire=cfg.rewire))
 
 
 def check_against_oracle(circ, cfg, bits, prob, lams, prec, planted=True):
@@ -202,3 +203,25 @@ def test_unswap_one_cycle_per_call_equals_sweep(mods, prec):
         assert np.array_equal(ha.read_site(i), hb.read_site(i))
     ha.close()
     hb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_adaptive_side_selection_matches_oracle(mods, prec):
+    """The lockstep runner with the adaptive side selection of App. A.3 (both
+    candidates of every circuit's step in shared group launches, on the MPO
+    and its copy): each circuit equals the oracle's adaptive run (bits, bond
+    values, p, the side taken at every step) and its lone GPU run bitwise."""
+    bt, dr, sv = mods
+    circs = [cg.mirrored_peaked_circuit(n, d, 90 + n, reading=r) for n, d, r in ((8, 3, "A"), (10, 4, "A"), (9, 3, "B"))]
+    cfgs = [dr.RunConfig(chi_max=chi, cutoff=1e-10, cutoff_mode="weight", precision=prec, tau=tau, side="adaptive")
+            for chi, tau in ((64, 300), (64, 500), (256, 400))]
+    out = bt.run_batched(list(zip(circs, cfgs)), precision=prec, keep_lams=True)
+    for circ, cfg, res, lams in zip(circs, cfgs, out["results"], out["lams"]):
+        ref = oracle_of(circ, cfg)
+        sides = [t["side"] for t in res.trace if t.get("stage") == "side"]
+        assert sides == [t["side"] for t in ref.trace if t.get("stage") == "side"] and sides
+        check_against_oracle(circ, cfg, res.bits, res.prob, lams, prec, planted=True)
+        alone, alone_lams = lone(dr, circ, cfg)
+        assert np.array_equal(res.bits, alone.bits) and res.prob == alone.prob
+        for a, b in zip(lams, alone_lams):
+            assert np.array_equal(a, b)

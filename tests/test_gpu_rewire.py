@@ -3,7 +3,8 @@
 the accepted swaps, transpile again) on the GPU, against the oracle's run of
 the same circuit and settings: the same update sequence (stage, bond, kept
 rank), the same peak bits, every bond's values within the precision's
-tolerance; and eager and lazy rewiring both recover the planted peak."""
+tolerance; and eager and lazy rewiring both recover the planted peak, with
+either routing rule (the lower qubit climbs, or the two meet halfway)."""
 import numpy as np
 import pytest
 
@@ -22,11 +23,12 @@ def dr():
     return driver
 
 
+@pytest.mark.parametrize("router", ["up", "middle"])
 @pytest.mark.parametrize("rewire", ["eager", "lazy"])
 @pytest.mark.parametrize("reading", ["A", "B"])
-def test_all_to_all_rewiring_matches_oracle(dr, rewire, reading):
+def test_all_to_all_rewiring_matches_oracle(dr, rewire, reading, router):
     circ = cg.mirrored_peaked_circuit(8, 3, 5, reading=reading, connectivity="all")
-    kw = dict(chi_max=256, cutoff=1e-12, tau=400, unswap="parallel", rewire=rewire)
+    kw = dict(chi_max=256, cutoff=1e-12, tau=400, unswap="parallel", rewire=rewire, router=router)
     c = dr.Contractor(circ, dr.RunConfig(cutoff_mode="rel_sv", precision="fp64", **kw))
     res = c.run()
     lams = [c.m.singular_values(b) for b in range(circ.n - 1)]

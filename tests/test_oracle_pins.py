@@ -473,7 +473,8 @@ def test_all_to_all_generator_is_planted(reading):
     assert abs(abs(psi[idx]) ** 2 - bf.peak_probability_closed_form(c.n, c.k_gates)) < 1e-12
 
 
-def test_transpile_linear_is_nearest_neighbour_and_exact():
+@pytest.mark.parametrize("router", ["up", "middle"])
+def test_transpile_linear_is_nearest_neighbour_and_exact(router):
     """Alg. 1 step 1: the transpiled half is nearest-neighbour on the sites,
     and replaying it on a dense state (circuit gates on their logical qubits,
     SWAPs exchanging the two logical qubits' sites) equals the original
@@ -483,7 +484,7 @@ def test_transpile_linear_is_nearest_neighbour_and_exact():
     gates = [(int(a), int(b), cg.haar_su4(rng), j)
              for j, (a, b) in enumerate(rng.permuted(np.tile(np.arange(n), (8, 1)), axis=1)[:, :2])]
     lay = mo.Layout(n)
-    layers = mo.transpile_linear(gates, lay)
+    layers = mo.transpile_linear(gates, lay, router)
     site_of, logical_at = list(range(n)), list(range(n))
     seen = []
     for layer in layers:
@@ -515,16 +516,17 @@ def test_transpile_linear_is_nearest_neighbour_and_exact():
     assert np.allclose(psi, ref_sites, atol=1e-12)
 
 
+@pytest.mark.parametrize("router", ["up", "middle"])
 @pytest.mark.parametrize("side", ["both", "adaptive"])
 @pytest.mark.parametrize("reading", ["A", "B"])
-def test_eager_rewiring_reproduces_dense_unitary(side, reading):
+def test_eager_rewiring_reproduces_dense_unitary(side, reading, router):
     """Alg. 1 with eager rewiring (transpile, strip the transpilation SWAPs
     after unswapping, reindex, re-transpile) on an all-to-all circuit: the
     contracted operator is the circuit's unitary, the peak is b."""
     c = cg.mirrored_peaked_circuit(6, 2, 5, reading=reading, connectivity="all")
     for rewire in ("lazy", "eager"):
         res = mo.contract(c.n, c.gates, mo.OracleConfig(chi_max=256, cutoff=1e-12, tau=200, unswap="parallel",
-                                                        rewire=rewire, side=side))
+                                                        rewire=rewire, side=side, router=router))
         full = mo.full_operator(res) * 2 ** (c.n / 2)
         assert np.allclose(full, bf.circuit_unitary(c.n, c.gates), atol=1e-9), rewire
         assert np.array_equal(res.bits, c.peak)
