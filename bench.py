@@ -84,30 +84,42 @@ def algorithmic_flops(chil, chi, chir, k):
                 total=theta + gate + gram + eig + back + wb)
 
 
-def kernel_bytes(cls, chi, sweeps, rotations, esz):
+def svd_route(prec_name):
+    """The library's SVD route for a form: FP64 accumulates the rotations
+    (operand rows m, plus r rows of V rotated alongside); the FP32 and mixed
+    forms run the Jacobi on the triangular factor of a second QR (r rows) and
+    take the vectors from its converged columns, unless MPO_SVD=accumulate."""
+    if prec_name == "fp64" or os.environ.get("MPO_SVD") == "accumulate":
+        return "accumulate"
+    return "qr2"
+
+
+def kernel_bytes(cls, chi, sweeps, rotations, esz, route="accumulate"):
     """Algorithmic HBM bytes one bond update asks of a memory-bound kernel
     class: a rotated panel reads and writes its (m + r) x 32 complex entries
-    (theta's rows and V's rows); a Gram step reads m x 32 entries per pair."""
+    (the operand's rows and V's rows; r x 32 on the second-QR route, which
+    rotates no V); a Gram step reads m x 32 entries per pair."""
     m = r = 4 * chi
     nblk = r // 16
     if cls == "jacobi_rot":
-        return rotations * (m + r) * 32 * 2 * esz
+        return rotations * ((m + r) if route == "accumulate" else r) * 32 * 2 * esz
     if cls == "jacobi_gram":
         return sweeps * (nblk - 1) * (nblk // 2) * m * 32 * esz
     return None
 
 
-def kernel_flops(cls, chi, sweeps, rotations):
+def kernel_flops(cls, chi, sweeps, rotations, route="accumulate"):
     """Algorithmic real flops one bond update asks of a kernel class, at
     (chi_l, chi, chi_r) = (chi, chi, chi): m = r = 4 chi rows/columns, 16-column
     blocks, 32-column panels.  Rotation: each rotated panel is an
-    (m + r) x 32 x 32 complex product; Gram: every panel of every step is an
-    m x 32 x 32 complex product; theta-build and write-back are the GEMMs'
-    flops.  None where no such count is meaningful (latency-bound kernels)."""
+    (m + r) x 32 x 32 complex product (r x 32 x 32 on the second-QR route);
+    Gram: every panel of every step is an m x 32 x 32 complex product;
+    theta-build and write-back are the GEMMs' flops.  None where no such count
+    is meaningful (latency-bound kernels)."""
     m = r = 4 * chi
     nblk = r // 16
     if cls == "jacobi_rot":
-        return rotations * (m + r) * 32 * 32 * 8.0
+        return rotations * ((m + r) if route == "accumulate" else r) * 32 * 32 * 8.0
     if cls == "jacobi_gram":
         return sweeps * (nblk - 1) * (nblk // 2) * m * 32 * 32 * 8.0
     if cls == "theta_gemm":
@@ -204,12 +216,12 @@ KERNEL_NAME = {"jacobi_rot": "k_jac_rot", "jacobi_gram": "k_jac_gram",
 KERNEL_NAME_MIXED = {"jacobi_rot": "k_jac_rot_mixed", "jacobi_gram": "k_jac_gram_bf16"}
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, route="accumulate"):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/*_traffic.md, two rocprofv3 --pmc passes scaled by the copy
-    calibration), or None when there is none or the kernel's sources (the
-    comma-separated `source` files, hashed in that order) have changed since
-    the counters were taken."""
+    calibration) taken on the same SVD route, or None when there is none or
+    the kernel's sources (the comma-separated `source` files, hashed in that
+    order) have changed since the counters were taken."""
     import glob
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
@@ -220,6 +232,8 @@ def measured_traffic(kernel):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
         if fields.get("kernel") != kernel or "traffic_bytes_per_launch" not in fields:
+            continue
+        if fields.get("svd_route", "accumulate") != route:
             continue
         digest = hashlib.sha256()
         for name in fields.get("source", "").split(","):
@@ -249,18 +263,22 @@ def roofline_of(run, prec_name, chi, steps):
     rots = sum(i["rotations"] for i in run["infos"])
     esz = 16 if prec_name == "fp64" else 8
     hbm_bound = dom == "jacobi_rot" or (dom == "jacobi_gram" and prec_name == "mixed")
-    byt = kernel_bytes(dom, chi, sweeps, rots, esz) if hbm_bound else None
+    route = svd_route(prec_name)
+    byt = kernel_bytes(dom, chi, sweeps, rots, esz, route) if hbm_bound else None
     names = dict(KERNEL_NAME, **(KERNEL_NAME_MIXED if prec_name == "mixed" else {}))
-    out = {"kernel": names.get(dom, dom), "class": dom, "avg_launch_ms": round(ms / max(launches, 1), 5),
-           "launches_per_update": launches / steps, "traffic": measured_traffic(names.get(dom, dom))}
+    if prec_name == "mixed" and route == "qr2":
+        names["jacobi_rot"] = "k_jac_rot"          # the operand is rotated on FP32 MFMA on this route
+    out = {"kernel": names.get(dom, dom), "class": dom, "svd_route": route,
+           "avg_launch_ms": round(ms / max(launches, 1), 5),
+           "launches_per_update": launches / steps, "traffic": measured_traffic(names.get(dom, dom), route)}
     if byt:
         achieved = byt / (ms * 1e-3) / 1e9
         out.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": byt / max(launches, 1)})
-        f = kernel_flops(dom, chi, sweeps, rots)
+        f = kernel_flops(dom, chi, sweeps, rots, route)
         out["tflops"] = round(f / (ms * 1e-3) / 1e12, 3)
         return out
-    f = kernel_flops(dom, chi, sweeps, rots)
+    f = kernel_flops(dom, chi, sweeps, rots, route)
     if dom == "jacobi_evd" or f is None:
         peak, bound = PEAK_TFLOPS["fp64"], "alu"
     else:
@@ -371,7 +389,7 @@ def main():
                       "jacobi_sweeps": [i["sweeps"] for i in run["infos"]],
                       "bond_dims_unchanged": run["dims_ok"]},
            "roofline": update_roofline(args.precision, chi, 1e3 * secs / args.steps,
-                                       measured_traffic("bond_update_" + args.precision)),
+                                       measured_traffic("bond_update_" + args.precision, svd_route(args.precision))),
            "dominant_kernel_roofline": roofline_of(prof_run, args.precision, chi, args.steps),
            "roofline_pass_ms_per_step": round(1e3 * prof_run["secs"] / args.steps, 3),
            "kernels_ms_per_update": {c: round(v[0] / args.steps, 3) for c, v in prof_run["prof"].items() if v[1]}}

@@ -85,12 +85,22 @@ typedef enum { MPO_CUT_REL_SV = 0, MPO_CUT_DISCARDED_WEIGHT = 1 } mpo_cutoff_mod
 typedef enum {
   MPO_FP64 = 0,             /* complex128 tensors, FP64 MFMA                          */
   MPO_FP32 = 1,             /* complex64 tensors, FP32 arithmetic                      */
-  MPO_MIXED_SPLITBF16 = 2   /* complex64 tensors, Jacobi Gram matrices and theta's
-                               rotations as split-BF16 MFMA products with FP32
-                               accumulation; updates that keep vectors then
-                               re-orthogonalise the accumulated rotations in FP64
-                               (polar step) and recompute the operand from R   */
+  MPO_MIXED_SPLITBF16 = 2   /* complex64 tensors, Jacobi Gram matrices as
+                               split-BF16 MFMA products with FP32 accumulation,
+                               converged to a loose tolerance (1e-3); the operand
+                               rotated on FP32 MFMA.  (On the accumulate route,
+                               theta's operand is rotated in split-BF16 too and
+                               updates that keep vectors re-orthogonalise the
+                               accumulated rotations in FP64 and recompute the
+                               operand from R.)                                */
 } mpo_precision_t;
+/* SVD of the update (Sec. II.B.1).  FP64: QR of (lambda theta)^dag = Q R, block
+ * one-sided Jacobi on L = R^dag with the rotations accumulated (V = Q W).
+ * FP32 and mixed: a second QR, L = Q2 R2, and the one-sided Jacobi on R2^dag
+ * without accumulation: the right singular vectors are Q times the unit-scaled
+ * converged columns, made orthonormal by Newton-Schulz steps after the
+ * truncation decision (the environment variable MPO_SVD=accumulate, read when
+ * a handle is created, selects the FP64 route for them instead). */
 
 typedef struct {
   int32_t n;              /* number of sites (qubits), >= 2                      */
@@ -158,7 +168,7 @@ mpo_status_t mpo_absorb_gate_pair(mpo_handle_t h, int32_t bond, const double* g_
  * per GPU, held until the process ends) instead of being allocated.  The call
  * makes no hipMalloc/hipFree and no call of the alloc hook.  An update whose
  * workspace does not fit (roughly theta above 512 x 512 in FP64, 724 x 724 in
- * FP32, less in the mixed form) fails with MPO_EINVAL and the MPO unchanged.
+ * FP32 and in the mixed form) fails with MPO_EINVAL and the MPO unchanged.
  * Kernel timing must be off.  The call synchronises the handle's stream
  * before it returns.  All calls on one GPU share the array: calls that
  * overlap in time on one GPU (from different host threads) race. */

@@ -102,7 +102,13 @@ def run_round(tasks: Sequence[CircuitTask], group: Optional[_mpo.Group], per_upd
             pend.append(t)
         elif ups:
             steps.append((t, ups))
-    if pend:
+    if pend and per_update:
+        # the same stage, each circuit's sweep launched on its own
+        for t in pend:
+            before = t.c.m.total_elements()
+            log = t.c.m.unswap(t.cfg.unswap, t.cfg.relaxed, t.cfg.max_unswap_iters)
+            t.unswap_done(log, before)
+    elif pend:
         by_opts: Dict[tuple, list] = {}
         for t in pend:
             by_opts.setdefault((t.cfg.relaxed, t.cfg.max_unswap_iters), []).append(t)
@@ -155,7 +161,9 @@ def run_batched(circuits_cfgs, precision: str = "fp32", per_update: bool = False
     unfinished circuits have result None."""
     group = None if per_update else _mpo.Group(_mpo.PRECISIONS[precision])
     t0 = time.perf_counter()
-    tasks = [CircuitTask(c, cfg, tag=i, group_unswap=not per_update, keep_lams=keep_lams)
+    # both ways take the unswapping stage as a round of its own (the grouped
+    # way batches it across circuits), so a round is the same work in both
+    tasks = [CircuitTask(c, cfg, tag=i, group_unswap=True, keep_lams=keep_lams)
              for i, (c, cfg) in enumerate(circuits_cfgs)]
     updates = 0
     rounds = 0

@@ -6,6 +6,7 @@
 //                  lambda scaling, (lambda theta)^dag for the QR preconditioner
 //   k_jac_init / k_jac_sweep_end   state of the block Jacobi SVD (steps: jacobi.hip)
 //   k_colnorms     singular values as column norms (FP64)
+//   k_unit_cols    the converged columns scaled to unit length
 //   k_sort_trunc   descending sort + truncation decision (FP64)
 //   k_env / k_greedy  peak readout of M|0...0> (FP64)
 //   k_sample_pick  one site of conditional sampling of M|0...0> for many samples (FP64)
@@ -289,6 +290,28 @@ __global__ __launch_bounds__(256) void k_colnorms(JacBatch jb) {
     }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
   if (lane == 0) P.norms[col] = sqrt(acc);
+}
+
+// U = A diag(1 / norms): the converged operand's columns scaled to unit
+// length (their directions are the singular vectors the second-QR route
+// keeps), into V (column-major, ncol_pad x ncol_pad); rows past m, columns
+// past ncol and columns of zero norm are zero.  One workgroup per column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_unit_cols(JacBatch jb) {
+  const int pi = blockIdx.y;
+  if (pi >= jb.count) return;
+  const JacProb P = jb.p[pi];
+  const int col = blockIdx.x;
+  if (col >= P.ncol_pad) return;
+  const double nrm = col < P.ncol ? P.norms[col] : 0.0;
+  const T sc = nrm > 0.0 ? (T)(1.0 / nrm) : (T)0;
+  const cx<T>* A = (const cx<T>*)P.A + (size_t)min(col, P.ncol_pad - 1) * P.lda;
+  cx<T>* U = (cx<T>*)P.V + (size_t)col * P.ncol_pad;
+  for (int r = threadIdx.x; r < P.ncol_pad; r += 256) {
+    const cx<T> x = A[min(r, P.m - 1)];
+    const T mk = r < P.m ? sc : (T)0;
+    U[r] = cx<T>{mk * x.re, mk * x.im};
+  }
 }
 
 // ============================================================== sort + truncation
@@ -596,6 +619,10 @@ template <typename T>
 void launch_colnorms(const JacBatch& b, int maxcols, hipStream_t s) {
   hipLaunchKernelGGL(k_colnorms<T>, dim3((maxcols + 3) / 4, b.count), dim3(256), 0, s, b);
 }
+template <typename T>
+void launch_unit_cols(const JacBatch& b, int maxcols, hipStream_t s) {
+  hipLaunchKernelGGL(k_unit_cols<T>, dim3(maxcols, b.count), dim3(256), 0, s, b);
+}
 void launch_sort_trunc(const TruncBatch& b, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_trunc, dim3(b.count), dim3(1024), 0, s, b);
 }
@@ -630,6 +657,7 @@ void launch_convert(cx<TD>* d, const cx<TS>* src, size_t n, hipStream_t s) {
   template void launch_gate<T>(const GateBatch&, int, hipStream_t);                                      \
   template void launch_jac_init<T>(const JacBatch&, hipStream_t);                                        \
   template void launch_colnorms<T>(const JacBatch&, int, hipStream_t);                                   \
+  template void launch_unit_cols<T>(const JacBatch&, int, hipStream_t);                                  \
   template void launch_greedy<T>(const cx<T>*, int, int, const cx<double>*, const cx<double>*,           \
                                  cx<double>*, cx<double>*, unsigned char*, double*, hipStream_t);
 

@@ -28,6 +28,7 @@ template <typename T> void launch_jac_rot(const JacBatch&, int, int, int, int, i
 template <typename T> void launch_ns_corr(const cx<double>*, cx<T>*, int, hipStream_t);
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
+template <typename T> void launch_unit_cols(const JacBatch&, int, hipStream_t);
 void launch_sort_trunc(const TruncBatch&, hipStream_t);
 template <typename T> void launch_qr_panel(const QrBatch&, const QrSyncBatch&, int, int, hipStream_t);
 template <typename T> void launch_qr_apply(const QrApplyBatch&, int, int, hipStream_t);
@@ -114,6 +115,12 @@ struct Slot {
   int* pchk = nullptr;
   size_t cap_mn = 0, cap_A = 0, cap_V = 0, cap_n = 0, cap_r = 0, cap_Y = 0;
   size_t cap_pairs = 0, cap_gch = 0;
+  // second QR (FP32 and mixed forms): L = R^dag (m x r, leading dimension m)
+  // factored in place, and its reflector scalars and panel T factors
+  void* L2 = nullptr;
+  void* tau2 = nullptr;
+  void* Tf2 = nullptr;
+  size_t cap_L2 = 0, cap_r2 = 0;
   unsigned* qcnt = nullptr;   // multi-workgroup QR panel: barrier counter (zeroed once)
   double* qpart = nullptr;    // ... and partial sums
   unsigned qbase = 0;         // the counter's value after the launches so far
@@ -189,6 +196,10 @@ struct mpo_ctx {
   int64_t hook_allocs = 0;
   // spin bound of the QR panel's cross-workgroup barrier (0: give up at once)
   int qr_spin = 1 << 20;
+  // SVD route of the FP32 and mixed forms: true = second QR, vectors from
+  // the converged columns (MPO_SVD=qr2, the default); false = accumulated
+  // rotations, as in FP64 (MPO_SVD=accumulate)
+  bool svd_qr2 = true;
   // Content versions: site_ver[i] changes whenever site i (and, for i >= 1,
   // lambda_{i-1}, which is only written together with site i) is written.
   // A SWAP trial at bond b reads exactly B_b, B_{b+1} and lambda_{b-1}, so
@@ -399,6 +410,26 @@ void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY, size_t nwp, size_t nw2)
   }
 }
 
+void ensure_qr2(mpo_ctx* h, Slot& s, size_t nl, size_t r) {
+  const size_t e = h->esz;
+  if (s.cap_L2 < nl) {
+    dfree(h, s.L2);
+    s.L2 = nullptr;
+    s.cap_L2 = 0;
+    s.L2 = dalloc(h, nl * e);
+    s.cap_L2 = nl;
+  }
+  if (s.cap_r2 < r) {
+    dfree(h, s.tau2);
+    dfree(h, s.Tf2);
+    s.tau2 = s.Tf2 = nullptr;
+    s.cap_r2 = 0;
+    s.tau2 = dalloc(h, r * e);
+    s.Tf2 = dalloc(h, ((r + QNB - 1) / QNB) * QNB * QNB * e);
+    s.cap_r2 = r;
+  }
+}
+
 void ensure_jac(mpo_ctx* h, Slot& s, size_t pairs, size_t gch) {
   if (s.cap_pairs < pairs || s.cap_gch < gch) {
     const size_t np = std::max(pairs, s.cap_pairs), ng = std::max(gch, s.cap_gch);
@@ -451,30 +482,65 @@ RShapes sh_r(const S* sh, int count) {
 // Then the Jacobi operand, whose split-BF16 rotations drifted, is recomputed
 // as A = L W from L = R^dag, so that its columns are an exact unitary
 // transform of L again.
+// Newton-Schulz work buffers: two FP64 and two working-precision arrays of
+// at least nn entries each.
+void ensure_ns(mpo_ctx* h, size_t nn) {
+  if (h->cap_ns >= nn) return;
+  dfree(h, h->ns_x);
+  dfree(h, h->ns_s);
+  dfree(h, h->ns_y);
+  h->ns_x = h->ns_s = h->ns_y = nullptr;
+  h->cap_ns = 0;
+  h->ns_x = dalloc(h, nn * sizeof(cx<double>));
+  h->ns_s = dalloc(h, nn * sizeof(cx<double>));
+  h->ns_y = dalloc(h, 2 * nn * h->esz);   // E and the new W, working precision
+  h->cap_ns = nn;
+}
+void ensure_lbuf(mpo_ctx* h, size_t nl) {
+  if (h->cap_l >= nl) return;
+  dfree(h, h->lbuf);
+  h->lbuf = nullptr;
+  h->cap_l = 0;
+  h->lbuf = dalloc(h, nl * h->esz);
+  h->cap_l = nl;
+}
+
+// Second-QR route, after the truncation decision: the kept columns Y (rows x
+// k, column-major, leading dimension rows) are unit-scaled converged columns,
+// orthogonal to the Jacobi tolerance; `steps` Newton-Schulz steps
+// Y <- Y + Y (I - Y^dag Y) / 2 make them orthonormal (the deviation squares at
+// every step).  The k x k Gram Y^dag Y is formed in FP64 on its upper tiles,
+// the correction applied with a working-precision product.
+template <typename T>
+void polar_cols(mpo_ctx* h, cx<T>* Y, int rows, int k, int steps, hipStream_t st) {
+  const size_t nr = (size_t)rows * k, nk = (size_t)k * k;
+  ensure_ns(h, std::max(nr, nk));
+  cx<double>* X = (cx<double>*)h->ns_x;
+  cx<double>* S = (cx<double>*)h->ns_s;
+  cx<T>* E = (cx<T>*)h->ns_y;
+  cx<T>* Yn = E + nk;
+  for (int it = 0; it < steps; ++it) {
+    launch_convert<double, T>(X, Y, nr, st);
+    GemmBatch g1{};
+    g1.count = 1;
+    g1.p[0] = GemmProb{X, X, S, k, k, rows, rows, rows, k, 1, 1, nullptr};
+    launch_gemm<double>(g1, k, k, st);
+    launch_ns_corr<T>(S, E, k, st);
+    GemmBatch g2{};
+    g2.count = 1;
+    g2.p[0] = GemmProb{E, Y, Yn, k, rows, k, k, rows, rows, 0, 0, Y};
+    launch_gemm<T>(g2, k, rows, st);
+    hip_check(hipMemcpyAsync(Y, Yn, nr * sizeof(cx<T>), hipMemcpyDeviceToDevice, st), "polar copy");
+  }
+}
+
 template <typename T>
 void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStream_t st) {
   for (int p = 0; p < rs.count; ++p) {
     const RShape& s = rs.s[p];
     const size_t nn = (size_t)s.rpad * s.rpad;
-    if (h->cap_ns < nn) {
-      dfree(h, h->ns_x);
-      dfree(h, h->ns_s);
-      dfree(h, h->ns_y);
-      h->ns_x = h->ns_s = h->ns_y = nullptr;
-      h->cap_ns = 0;
-      h->ns_x = dalloc(h, nn * sizeof(cx<double>));
-      h->ns_s = dalloc(h, nn * sizeof(cx<double>));
-      h->ns_y = dalloc(h, 2 * nn * h->esz);   // E and the new W, working precision
-      h->cap_ns = nn;
-    }
-    const size_t nl = (size_t)s.m * s.rpad;
-    if (h->cap_l < nl) {
-      dfree(h, h->lbuf);
-      h->lbuf = nullptr;
-      h->cap_l = 0;
-      h->lbuf = dalloc(h, nl * h->esz);
-      h->cap_l = nl;
-    }
+    ensure_ns(h, nn);
+    ensure_lbuf(h, (size_t)s.m * s.rpad);
     Slot& sl = h->slots[p];
     cx<double>* X = (cx<double>*)h->ns_x;
     cx<double>* S = (cx<double>*)h->ns_s;
@@ -672,8 +738,11 @@ hipGraphExec_t sweep_graph(mpo_ctx* h, const std::string& key, F&& record) {
 template <typename T>
 mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool commit) {
   hipStream_t st = h->stream;
+  // FP32 and mixed forms: Jacobi on the triangular factor of a second QR,
+  // without accumulating the rotations (vectors from the converged columns)
+  const bool qr2 = sizeof(T) == 4 && h->svd_qr2;
   struct Shape {
-    int i, chil, chim, chir, m, n, r, rpad, nblk, lda;
+    int i, chil, chim, chir, m, n, r, rpad, nblk, lda, rows;
   };
   Shape sh[MAXB];
   int maxM = 0, maxN = 0, maxtot = 0, maxr = 0, maxrpad = 0, maxpairs = 0, maxblk = 0, maxgch = 1;
@@ -689,7 +758,8 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     s.n = 4 * s.chir;
     s.r = std::min(s.m, s.n);
     s.rpad = round_up(s.r, 2 * JB);
-    s.lda = lda_jacobi(s.m);
+    s.rows = qr2 ? s.r : s.m;           // rows of the Jacobi operand
+    s.lda = lda_jacobi(s.rows);
     s.nblk = s.rpad / JB;
     maxM = std::max(maxM, s.m);
     maxN = std::max(maxN, s.n);
@@ -701,10 +771,12 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     Slot& sl = h->slots[p];
     ensure_slot(h, sl, (size_t)s.m * s.n, (size_t)s.lda * s.rpad, commit ? (size_t)s.rpad * s.rpad : 0,
                 (size_t)s.rpad);
-    ensure_qr(h, sl, (size_t)s.r, commit ? (size_t)s.n * s.r : 0,
-              (size_t)((s.n + QRC1 - 1) / QRC1) * QNB * s.m, (size_t)QNB * s.m);
-    ensure_jac(h, sl, (size_t)(s.nblk / 2), (size_t)((s.m + GRC - 1) / GRC));
-    maxgch = std::max(maxgch, (s.m + GRC - 1) / GRC);
+    const size_t nwp1 = (size_t)((s.n + QRC1 - 1) / QRC1) * QNB * s.m;
+    const size_t nwp2 = qr2 ? (size_t)((s.m + QRC1 - 1) / QRC1) * QNB * s.r : 0;
+    ensure_qr(h, sl, (size_t)s.r, commit ? (size_t)s.n * s.r : 0, std::max(nwp1, nwp2), (size_t)QNB * s.m);
+    if (qr2) ensure_qr2(h, sl, (size_t)s.m * s.r, (size_t)s.r);
+    ensure_jac(h, sl, (size_t)(s.nblk / 2), (size_t)((s.rows + GRC - 1) / GRC));
+    maxgch = std::max(maxgch, (s.rows + GRC - 1) / GRC);
   }
   // gates -> pinned staging -> device (the staging buffer is free: every
   // call ends with a stream synchronisation)
@@ -777,23 +849,68 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
       launch_qr_apply<T>(tr, p0, maxtrail, st);
     });
   }
-  // L = R^dag, the Jacobi operand (m x r, column-major)
+  if (qr2) {
+    // L = R^dag (m x r, leading dimension m) and its own Householder QR,
+    // L = Q2 R2.  Only R2 is kept: the right singular vectors of the update
+    // are Q times those of R2, which are the left singular vectors of R2^dag
+    // (the converged columns of its one-sided Jacobi, scaled to unit length).
+    LowerBatch l2{};
+    l2.count = count;
+    for (int p = 0; p < count; ++p) {
+      const Shape& s = sh[p];
+      l2.p[p] = LowerProb{h->slots[p].theta0, h->slots[p].L2, s.n, s.m, s.r, s.r, s.m};
+    }
+    timed(h, MPO_PROF_QR, [&] { launch_lower_from_r<T>(l2, maxM, maxr, st); });
+    QrBatch q2{};
+    q2.count = count;
+    QrApplyBatch t2{};
+    t2.count = count;
+    t2.conj_t = 1;
+    for (int p = 0; p < count; ++p) {
+      const Shape& s = sh[p];
+      q2.p[p] = QrProb{h->slots[p].L2, h->slots[p].tau2, h->slots[p].Tf2, s.m, s.r, s.r};
+    }
+    for (int p0 = 0; p0 < maxr; p0 += QNB) {
+      int maxtrail = 0, maxrows = 0;
+      QrSyncBatch sy{};
+      for (int p = 0; p < count; ++p) {
+        const Shape& s = sh[p];
+        Slot& sl = h->slots[p];
+        const int c0 = std::min(p0 + QNB, s.r);
+        t2.p[p] = QrApplyProb{sl.L2, sl.Tf2, sl.L2, sl.qwp, sl.qw2, s.m, s.r, s.m, c0, s.r, s.r};
+        sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase, h->qr_spin, &h->results[p].qr_fail};
+        if (p0 < s.r) {
+          maxtrail = std::max(maxtrail, s.r - c0);
+          maxrows = std::max(maxrows, s.m - p0);
+          const unsigned nwg = (unsigned)((s.m - p0 + QMW_ROWS - 1) / QMW_ROWS);
+          const unsigned nb = (unsigned)std::min(QNB, s.r - p0);
+          sl.qbase += 2 * nb * nwg;
+        }
+      }
+      timed(h, MPO_PROF_QR, [&] {
+        launch_qr_panel<T>(q2, sy, p0, (maxrows + QMW_ROWS - 1) / QMW_ROWS, st);
+        launch_qr_apply<T>(t2, p0, maxtrail, st);
+      });
+    }
+  }
+  // the Jacobi operand (rows x r, column-major): L = R^dag, or R2^dag
   LowerBatch lwb{};
   lwb.count = count;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
-    lwb.p[p] = LowerProb{h->slots[p].theta0, h->slots[p].A, s.n, s.m, s.r, s.rpad, s.lda};
+    lwb.p[p] = qr2 ? LowerProb{h->slots[p].L2, h->slots[p].A, s.m, s.r, s.r, s.rpad, s.lda}
+                   : LowerProb{h->slots[p].theta0, h->slots[p].A, s.n, s.m, s.r, s.rpad, s.lda};
   }
-  timed(h, MPO_PROF_QR, [&] { launch_lower_from_r<T>(lwb, maxM, maxrpad, st); });
+  timed(h, MPO_PROF_QR, [&] { launch_lower_from_r<T>(lwb, qr2 ? maxr : maxM, maxrpad, st); });
 
   JacBatch jb{};
   jb.count = count;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
     Slot& sl = h->slots[p];
-    jb.p[p] = JacProb{sl.A,      commit ? sl.V : nullptr, h->states + p, sl.norms, (cx<double>*)sl.gpart, sl.dmat,
-                      sl.pflag,  sl.bmod, sl.pchk, tol_for(O(p), s.m), s.m, s.lda, s.r, s.rpad, s.nblk,
-                      (int)sl.cap_gch};
+    jb.p[p] = JacProb{sl.A,      (commit && !qr2) ? sl.V : nullptr, h->states + p, sl.norms, (cx<double>*)sl.gpart,
+                      sl.dmat,   sl.pflag, sl.bmod, sl.pchk, tol_for(O(p), s.rows), s.rows, s.lda, s.r, s.rpad,
+                      s.nblk,    (int)sl.cap_gch};
   }
   timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_jac_init<T>(jb, st); });
   const bool mixed = (h->prec == MPO_MIXED_SPLITBF16);
@@ -804,8 +921,8 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   const int rrc = plan.rrc;
   int nrch_a = 1, nrch_v = 0;
   for (int p = 0; p < count; ++p) {
-    nrch_a = std::max(nrch_a, (sh[p].m + rrc - 1) / rrc);
-    if (commit) nrch_v = std::max(nrch_v, (sh[p].r + rrc - 1) / rrc);
+    nrch_a = std::max(nrch_a, (sh[p].rows + rrc - 1) / rrc);
+    if (commit && !qr2) nrch_v = std::max(nrch_v, (sh[p].r + rrc - 1) / rrc);
   }
   const bool use_graph = plan.graph && !h->prof_on;
   auto sweeps = [&](int bf16, int budget) {
@@ -815,7 +932,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
         timed(h, MPO_PROF_JACOBI_GRAM, [&] { launch_jac_gram<T>(jb, maxpairs, maxgch, step, bf16, s); });
         timed(h, MPO_PROF_JACOBI_EVD, [&] { launch_jac_evd<T>(jb, maxpairs, step, bf16 ? 1 : 2, s); });
         timed(h, MPO_PROF_JACOBI_ROT, [&] {
-          launch_jac_rot<T>(jb, maxpairs, nrch_a, nrch_v, step, bf16 ? ROT_MIXED : ROT_FP, rrc, s);
+          launch_jac_rot<T>(jb, maxpairs, nrch_a, nrch_v, step, (bf16 && !qr2) ? ROT_MIXED : ROT_FP, rrc, s);
         });
       }
       launch_jac_sweep_end(jb, s);
@@ -868,7 +985,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     trace_sweeps("fp sweeps");
   } else {
     // split-BF16 sweeps to a loose tolerance ...
-    for (int p = 0; p < count; ++p) jb.p[p].tol = tol_bf16(O(p), sh[p].m);
+    for (int p = 0; p < count; ++p) jb.p[p].tol = tol_bf16(O(p), sh[p].rows);
     sweeps(1, h->max_sweeps);
     trace_sweeps("bf16 sweeps");
     // ... then the FP64 re-orthogonalisation of the accumulated rotations
@@ -877,9 +994,21 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     // it; no FP32 sweep is needed afterwards.  Values-
     // only trials keep the BF16-rotated norms (relative drift ~1e-4), which
     // decide ranks only.
-    if (commit) timed(h, MPO_PROF_REORTH, [&] { reorthogonalise<T>(h, sh_r(sh, count), jb, st); });
+    if (commit && !qr2) timed(h, MPO_PROF_REORTH, [&] { reorthogonalise<T>(h, sh_r(sh, count), jb, st); });
   }
-  timed(h, MPO_PROF_FINALIZE, [&] { launch_colnorms<T>(jb, maxrpad, st); });
+  if (qr2 && commit) {
+    // the converged columns scaled to unit length -> V (their polar step
+    // follows the truncation decision, on the kept columns only).  The
+    // operand is rotated in FP32 in both forms (the rotation is bound by HBM
+    // either way), so its column norms are the singular values to second
+    // order in the tolerance, with no drift, in commits and trials alike.
+    timed(h, MPO_PROF_FINALIZE, [&] { launch_colnorms<T>(jb, maxrpad, st); });
+    JacBatch ub = jb;
+    for (int p = 0; p < count; ++p) ub.p[p].V = h->slots[p].V;
+    timed(h, MPO_PROF_REORTH, [&] { launch_unit_cols<T>(ub, maxrpad, st); });
+  } else {
+    timed(h, MPO_PROF_FINALIZE, [&] { launch_colnorms<T>(jb, maxrpad, st); });
+  }
   TruncBatch trb{};
   trb.count = count;
   for (int p = 0; p < count; ++p) {
@@ -931,6 +1060,15 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     maxk = std::max(maxk, k);
   }
   timed(h, MPO_PROF_WRITEBACK, [&] { launch_build_y<T>(vb, maxel, st); });
+  if (qr2) {
+    size_t nn = 0;
+    for (int p = 0; p < count; ++p)
+      nn = std::max(nn, std::max((size_t)sh[p].n * out[p].k, (size_t)out[p].k * out[p].k));
+    ensure_ns(h, nn);
+    timed(h, MPO_PROF_REORTH, [&] {
+      for (int p = 0; p < count; ++p) polar_cols<T>(h, (cx<T>*)h->slots[p].Y, sh[p].n, out[p].k, 3, st);
+    });
+  }
   for (int p0 = (maxr - 1) / QNB * QNB; p0 >= 0; p0 -= QNB)
     timed(h, MPO_PROF_WRITEBACK, [&] { launch_qr_apply<T>(qa, p0, maxk, st); });
   timed(h, MPO_PROF_WRITEBACK, [&] { launch_vh_rows<T>(vb, maxel, st); });
@@ -1412,6 +1550,9 @@ void destroy(mpo_ctx* h) {
     dfree(h, s.pchk);
     dfree(h, s.qcnt);
     dfree(h, s.qpart);
+    dfree(h, s.L2);
+    dfree(h, s.tau2);
+    dfree(h, s.Tf2);
   }
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);
@@ -1469,6 +1610,8 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
     h->trial_reuse = !(r && r[0] == '0');
     const char* q = std::getenv("MPO_QR_SPIN");
     if (q && q[0]) h->qr_spin = std::max(0, std::atoi(q));
+    const char* v = std::getenv("MPO_SVD");
+    if (v && std::strcmp(v, "accumulate") == 0) h->svd_qr2 = false;
   }
   mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
     const int n = h->n;

@@ -252,6 +252,8 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=1.0)
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--deadline", type=float, default=0.0,
+                    help="serve: cancel a request this many seconds after its arrival (0: never)")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--max-n", type=int, default=64, help="skip workload circuits wider than this")
     ap.add_argument("--chi-cap", type=int, default=1024, help="clip the workload's chi_max to this")
@@ -268,6 +270,8 @@ def main(argv=None):
             circ = cg.config_circuit(a.config, reading=a.reading)
         tau = a.tau if a.tau != 1e5 else 2e4
         out = {"form": "peak", "config": a.config, "n": circ.n, "chi_max": a.chi, "tau": tau, "runs": []}
+        pc = p_closed(circ)
+        lams = {}
         for prec in a.precisions.split(","):
             c = dr.Contractor(circ, dr.RunConfig(chi_max=a.chi, cutoff=1e-8, cutoff_mode="weight", precision=prec,
                                                  tau=tau, unswap="parallel", side=a.side, router=a.router,
@@ -347,6 +351,7 @@ def main(argv=None):
             sampled = None
             if a.samples:
                 sampled = sample_report(c, circ, a.samples, res.prob)
+            lams[prec] = [c.m.singular_values(b) for b in range(circ.n - 1)]
             c.close()
             ks = [x["k"] for x in res.trace if "k" in x]
             secs = done_s + res.seconds
@@ -356,10 +361,21 @@ def main(argv=None):
                                 "trial_absorb_updates": c.trial_absorb_updates,
                                 "max_chi": max([max_k0] + ks),
                                 "peak_ok": bool((res.bits == circ.peak).all()), "p_peak": res.prob,
+                                "p_rel_err_closed_form": abs(res.prob - pc) / pc,
                                 "updates_per_s": round(res.bond_updates / secs, 1)})
             if sampled:
                 out["runs"][-1]["sampling"] = sampled
             print(json.dumps(out["runs"][-1]), flush=True)
+        if "fp64" in lams:
+            # every bond's final values against the FP64 run's (itself within
+            # 1e-10 of the oracle), normwise per bond, worst bond
+            for run in out["runs"]:
+                got = lams.get(run["precision"])
+                if got is None or not run.get("finished"):
+                    continue
+                errs = [float(np.max(np.abs(x - r)) / np.linalg.norm(r)) if len(x) == len(r) else float("inf")
+                        for x, r in zip(got, lams["fp64"])]
+                run["lambda_err_vs_fp64"] = max(errs)
         print(json.dumps(out), flush=True)
         return
     if a.form == "batch":
@@ -412,23 +428,29 @@ def main(argv=None):
                            tau=a.tau, side=a.side, router=a.router)
         reqs = [r for r in sv.poisson_requests(a.rate, a.duration) if r.n <= a.max_n]
         print(f"  {len(reqs)} requests, n = {[r.n for r in reqs]}", flush=True)
-        out = sv.serve(reqs, cfg, int(a.budget_gb * 2 ** 30), on_round=_progress("serve"))
+        out = sv.serve(reqs, cfg, int(a.budget_gb * 2 ** 30), on_round=_progress("serve"), deadline_s=a.deadline)
         print("  sequential FP32 baseline", flush=True)
         base_cfg = dr.RunConfig(chi_max=cfg.chi_max, cutoff=cfg.cutoff, cutoff_mode=cfg.cutoff_mode,
                                 precision="fp32", tau=cfg.tau, side=cfg.side, router=cfg.router)
-        seq = sv.serve_sequential(reqs, base_cfg)
+        seq = sv.serve_sequential(reqs, base_cfg, deadline_s=a.deadline,
+                                  on_request=lambda i, secs, ok: print(f"  [sequential] request {i}: {secs:.2f} s"
+                                                                       f"{'' if ok else ' (deadline)'}", flush=True))
         print(json.dumps({"form": "serve", "rate": a.rate, "duration": a.duration, "requests": len(reqs), "side": a.side,
                           "router": a.router,
                           "chi_max": cfg.chi_max, "max_n": a.max_n,
-                          "served": len(out["served"]), "precision": prec, "seconds": round(out["seconds"], 3),
+                          "deadline_s": a.deadline, "tau": a.tau,
+                          "served": len(out["served"]), "timed_out": len(out["timed_out"]),
+                          "refused": len(out["refused"]), "precision": prec, "seconds": round(out["seconds"], 3),
                           "circuits_per_s": round(out["circuits_per_s"], 4), "p50_time_to_peak_s": round(out["p50"], 3),
                           "p99_time_to_peak_s": round(out["p99"], 3), "all_peaks_ok": out["all_peaks_ok"],
                           "bond_updates": out["bond_updates"],
                           "peak_projected_gb": round(out["peak_projected_bytes"] / 2 ** 30, 3),
+                          "peak_device_gb": round(out["peak_device_bytes"] / 2 ** 30, 3),
                           "sequential_fp32": {"seconds": round(seq["seconds"], 3),
                                               "circuits_per_s": round(seq["circuits_per_s"], 4),
                                               "p50_time_to_peak_s": round(seq["p50"], 3),
                                               "p99_time_to_peak_s": round(seq["p99"], 3),
+                                              "finished": seq["finished"], "timed_out": seq["timed_out"],
                                               "all_peaks_ok": seq["all_peaks_ok"]}}), flush=True)
 
 

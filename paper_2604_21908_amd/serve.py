@@ -88,9 +88,18 @@ def _device_used_bytes(torch) -> int:
     return int(total - free)
 
 
+def _percentiles(ttp: Sequence[float]):
+    ttp = np.asarray(ttp, dtype=np.float64) if len(ttp) else np.zeros(1)
+    return float(np.percentile(ttp, 50)), float(np.percentile(ttp, 99))
+
+
 def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max_slots: int = 64,
           reading: str = "A", on_round: Optional[Callable[[int, int], None]] = None,
-          keep_lams: bool = False) -> dict:
+          keep_lams: bool = False, deadline_s: float = 0.0) -> dict:
+    """Serves `requests` (see the module docstring).  With `deadline_s` > 0 a
+    request still resident that long after its arrival is cancelled (its
+    MPO freed at once) and reported in `timed_out`; the percentiles then
+    count it at the deadline, so they are lower bounds when any timed out."""
     import torch
     reqs = sorted(requests, key=lambda r: r.t_arrival)
     prepare(reqs, reading)
@@ -99,6 +108,7 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
     active: List[tuple] = []
     done: List[Served] = []
     refused: List[Request] = []
+    timed_out: List[Request] = []
     used = 0
     peak_used = 0
     torch.cuda.synchronize()
@@ -130,21 +140,25 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
         if on_round:
             on_round(rounds, len(active))
         still = []
+        now = time.perf_counter() - t0
         for (r, task, t_adm, need) in active:
             if task.done:
                 res = task.result
                 done.append(Served(r, t_adm, task.t_done - t0, bool((res.bits == task.circuit.peak).all()),
                                    float(res.prob), res.bond_updates, res.bits, task.lams))
                 used -= need
+            elif deadline_s > 0 and now - r.t_arrival > deadline_s:
+                task.c.close()
+                timed_out.append(r)
+                used -= need
             else:
                 still.append((r, task, t_adm, need))
         active = still
     secs = time.perf_counter() - t0
     group.close()
-    ttp = np.array([d.time_to_peak for d in done]) if done else np.zeros(1)
-    return dict(served=done, refused=refused, seconds=secs, rounds=rounds,
-                circuits_per_s=len(done) / secs if secs else 0.0,
-                p50=float(np.percentile(ttp, 50)), p99=float(np.percentile(ttp, 99)),
+    p50, p99 = _percentiles([d.time_to_peak for d in done] + [deadline_s] * len(timed_out))
+    return dict(served=done, refused=refused, timed_out=timed_out, seconds=secs, rounds=rounds,
+                circuits_per_s=len(done) / secs if secs else 0.0, p50=p50, p99=p99,
                 all_peaks_ok=all(d.bits_ok for d in done), peak_projected_bytes=peak_used,
                 peak_device_bytes=dev_peak, bond_updates=sum(d.updates for d in done))
 
@@ -167,24 +181,58 @@ def poisson_requests(rate: float, duration: float, seed: int = 4000, sizes=(24, 
     return out
 
 
-def serve_sequential(requests: Sequence[Request], cfg: dr.RunConfig, reading: str = "A") -> dict:
+class _Deadline(Exception):
+    pass
+
+
+def _contract_within(circ, cfg: dr.RunConfig, limit_s: float):
+    """dr.contract with a limit on the wall time (checked before every
+    absorption step); None when the limit is reached."""
+    c = dr.Contractor(circ, cfg)
+    t0 = time.perf_counter()
+    if limit_s > 0:
+        step = c.absorb_step
+
+        def bounded():
+            if time.perf_counter() - t0 > limit_s:
+                raise _Deadline()
+            step()
+        c.absorb_step = bounded
+    try:
+        return c.run()
+    except _Deadline:
+        return None
+    finally:
+        c.close()
+
+
+def serve_sequential(requests: Sequence[Request], cfg: dr.RunConfig, reading: str = "A",
+                     deadline_s: float = 0.0, on_request: Optional[Callable[[int, float, bool], None]] = None) -> dict:
     """Baseline for the served form: the same arrivals handled one circuit at
     a time, first come first served, each contracted alone with one launch per
     update wave.  The solo service time of every circuit is measured; the
     queue is then exact for a single server: a request starts when it has
-    arrived and the previous one has finished."""
+    arrived and the previous one has finished.  With `deadline_s` > 0 a
+    circuit's service stops after that long (the limit applies to service
+    time alone, which favours the baseline); such requests are counted at
+    their time in the queue plus the limit."""
     reqs = sorted(requests, key=lambda r: r.t_arrival)
     prepare(reqs, reading)
     service = []
     ok = []
+    finished = 0
     updates = 0
     for r in reqs:
         circ = r.circuit
         t0 = time.perf_counter()
-        res = dr.contract(circ, cfg)
+        res = _contract_within(circ, cfg, deadline_s)
         service.append(time.perf_counter() - t0)
-        ok.append(bool((res.bits == circ.peak).all()))
-        updates += res.bond_updates
+        if on_request:
+            on_request(len(service), service[-1], res is not None)
+        if res is not None:
+            finished += 1
+            ok.append(bool((res.bits == circ.peak).all()))
+            updates += res.bond_updates
     done = []
     t_free = 0.0
     for r, s in zip(reqs, service):
@@ -192,7 +240,7 @@ def serve_sequential(requests: Sequence[Request], cfg: dr.RunConfig, reading: st
         t_free = start + s
         done.append(t_free - r.t_arrival)
     makespan = t_free if reqs else 0.0
-    ttp = np.array(done) if done else np.zeros(1)
-    return dict(seconds=makespan, circuits_per_s=len(reqs) / makespan if makespan else 0.0,
-                p50=float(np.percentile(ttp, 50)), p99=float(np.percentile(ttp, 99)),
+    p50, p99 = _percentiles(done)
+    return dict(seconds=makespan, circuits_per_s=finished / makespan if makespan else 0.0,
+                p50=p50, p99=p99, finished=finished, timed_out=len(reqs) - finished,
                 all_peaks_ok=all(ok), bond_updates=updates, service_s=service)

@@ -331,9 +331,12 @@ def _full_size_oracle():
     return _FULL
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp32", "fp64"])
-def test_full_size_chi1024_update(lib, prec):
-    """The benchmarked update itself (theta 4096 x 4096, chi_max = 1024 binds)
+@pytest.mark.parametrize("prec,route", [("mixed", "qr2"), ("fp32", "qr2"), ("fp64", "accumulate"),
+                                        ("mixed", "accumulate"), ("fp32", "accumulate")])
+def test_full_size_chi1024_update(lib, prec, route, monkeypatch):
+    """The benchmarked update itself (theta 4096 x 4096, chi_max = 1024 binds),
+    on both SVD routes of the FP32 and mixed forms (second QR with vectors from
+    the converged columns, the default; or accumulated rotations, as FP64),
     against the oracle: kept rank, singular values (normwise), discarded weight,
     orthonormal rows of the new right tensor, and the written two-site operator.
     With the left bond values applied, lambda B_i' B_i+1' is a rank-k
@@ -345,6 +348,7 @@ def test_full_size_chi1024_update(lib, prec):
     f = _full_size_oracle()
     r = f["r"]
     tol = TOL[prec]
+    monkeypatch.setenv("MPO_SVD", route)
     g = lib.MPO(f["n"], 1024, 1e-8, 1, PREC[prec])
     g.load_state(f["sites"], f["lams"])
     info = g.absorb(f["bond"], f["go"], f["gi"])
