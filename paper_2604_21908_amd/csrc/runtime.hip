@@ -735,6 +735,40 @@ hipGraphExec_t sweep_graph(mpo_ctx* h, const std::string& key, F&& record) {
 // One batch (<= MAXB problems): theta-build, gate, QR-preconditioned Jacobi
 // SVD, truncation; with `commit` the new tensors are written (bonds must be
 // pairwise non-adjacent).  Returns per-problem results.  Throws HipError / NoMem.
+// Householder QR of every problem's matrix in qb (n x m, leading dimension
+// n, its first r columns factored), panel by panel: each panel factored by
+// ceil(rows / QMW_ROWS) workgroups that meet at counter barriers (the
+// per-slot counter's base advanced here as the kernel advances it), then the
+// trailing columns updated.
+template <typename T>
+void householder_qr(mpo_ctx* h, const QrBatch& qb, int count, int maxr, hipStream_t st) {
+  QrApplyBatch tr{};
+  tr.count = count;
+  tr.conj_t = 1;
+  for (int p0 = 0; p0 < maxr; p0 += QNB) {
+    int maxrows = 0, maxtrail = 0;
+    QrSyncBatch sy{};
+    for (int p = 0; p < count; ++p) {
+      const QrProb& q = qb.p[p];
+      Slot& sl = h->slots[p];
+      const int c0 = std::min(p0 + QNB, q.r);
+      tr.p[p] = QrApplyProb{q.M, q.Tf, q.M, sl.qwp, sl.qw2, q.n, q.r, q.n, c0, q.m, q.m};
+      sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase, h->qr_spin, &h->results[p].qr_fail};
+      if (p0 < q.r) {
+        maxrows = std::max(maxrows, q.n - p0);
+        maxtrail = std::max(maxtrail, q.m - c0);
+        const unsigned nwg = (unsigned)((q.n - p0 + QMW_ROWS - 1) / QMW_ROWS);
+        const unsigned nb = (unsigned)std::min(QNB, q.r - p0);
+        sl.qbase += 2 * nb * nwg;
+      }
+    }
+    timed(h, MPO_PROF_QR, [&] {
+      launch_qr_panel<T>(qb, sy, p0, (maxrows + QMW_ROWS - 1) / QMW_ROWS, st);
+      launch_qr_apply<T>(tr, p0, maxtrail, st);
+    });
+  }
+}
+
 template <typename T>
 mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool commit) {
   hipStream_t st = h->stream;
@@ -812,43 +846,14 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   }
   timed(h, MPO_PROF_GATE, [&] { launch_gate<T>(tb, maxtot, st); });
 
-  // Householder QR of M (n x m), panel by panel
+  // Householder QR of M (n x m)
   QrBatch qb{};
   qb.count = count;
-  QrApplyBatch tr{};
-  tr.count = count;
-  tr.conj_t = 1;
   for (int p = 0; p < count; ++p) {
     const Shape& s = sh[p];
     qb.p[p] = QrProb{h->slots[p].theta0, h->slots[p].tau, h->slots[p].Tf, s.n, s.m, s.r};
   }
-  for (int p0 = 0; p0 < maxr; p0 += QNB) {
-    int maxtrail = 0;
-    for (int p = 0; p < count; ++p) {
-      const Shape& s = sh[p];
-      const int c0 = std::min(p0 + QNB, s.r), c1 = s.m;
-      tr.p[p] = QrApplyProb{h->slots[p].theta0, h->slots[p].Tf, h->slots[p].theta0, h->slots[p].qwp,
-                            h->slots[p].qw2, s.n, s.r, s.n, c0, c1, s.m};
-      if (p0 < s.r) maxtrail = std::max(maxtrail, c1 - c0);
-    }
-    // the panel on ceil(rows / QMW_ROWS) workgroups that meet at counter barriers
-    int maxN = 0;
-    QrSyncBatch sy{};
-    for (int p = 0; p < count; ++p) {
-      Slot& sl = h->slots[p];
-      sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase, h->qr_spin, &h->results[p].qr_fail};
-      if (p0 < sh[p].r) {
-        maxN = std::max(maxN, sh[p].n - p0);
-        const unsigned nwg = (unsigned)((sh[p].n - p0 + QMW_ROWS - 1) / QMW_ROWS);
-        const unsigned nb = (unsigned)std::min(QNB, sh[p].r - p0);
-        sl.qbase += 2 * nb * nwg;
-      }
-    }
-    timed(h, MPO_PROF_QR, [&] {
-      launch_qr_panel<T>(qb, sy, p0, (maxN + QMW_ROWS - 1) / QMW_ROWS, st);
-      launch_qr_apply<T>(tr, p0, maxtrail, st);
-    });
-  }
+  householder_qr<T>(h, qb, count, maxr, st);
   if (qr2) {
     // L = R^dag (m x r, leading dimension m) and its own Householder QR,
     // L = Q2 R2.  Only R2 is kept: the right singular vectors of the update
@@ -863,35 +868,11 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     timed(h, MPO_PROF_QR, [&] { launch_lower_from_r<T>(l2, maxM, maxr, st); });
     QrBatch q2{};
     q2.count = count;
-    QrApplyBatch t2{};
-    t2.count = count;
-    t2.conj_t = 1;
     for (int p = 0; p < count; ++p) {
       const Shape& s = sh[p];
       q2.p[p] = QrProb{h->slots[p].L2, h->slots[p].tau2, h->slots[p].Tf2, s.m, s.r, s.r};
     }
-    for (int p0 = 0; p0 < maxr; p0 += QNB) {
-      int maxtrail = 0, maxrows = 0;
-      QrSyncBatch sy{};
-      for (int p = 0; p < count; ++p) {
-        const Shape& s = sh[p];
-        Slot& sl = h->slots[p];
-        const int c0 = std::min(p0 + QNB, s.r);
-        t2.p[p] = QrApplyProb{sl.L2, sl.Tf2, sl.L2, sl.qwp, sl.qw2, s.m, s.r, s.m, c0, s.r, s.r};
-        sy.p[p] = QrSyncProb{sl.qcnt, sl.qpart, sl.qbase, h->qr_spin, &h->results[p].qr_fail};
-        if (p0 < s.r) {
-          maxtrail = std::max(maxtrail, s.r - c0);
-          maxrows = std::max(maxrows, s.m - p0);
-          const unsigned nwg = (unsigned)((s.m - p0 + QMW_ROWS - 1) / QMW_ROWS);
-          const unsigned nb = (unsigned)std::min(QNB, s.r - p0);
-          sl.qbase += 2 * nb * nwg;
-        }
-      }
-      timed(h, MPO_PROF_QR, [&] {
-        launch_qr_panel<T>(q2, sy, p0, (maxrows + QMW_ROWS - 1) / QMW_ROWS, st);
-        launch_qr_apply<T>(t2, p0, maxtrail, st);
-      });
-    }
+    householder_qr<T>(h, q2, count, maxr, st);
   }
   // the Jacobi operand (rows x r, column-major): L = R^dag, or R2^dag
   LowerBatch lwb{};

@@ -252,6 +252,8 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=1.0)
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--light-chi", type=int, default=64,
+                    help="serve: round policy (circuits with bonds up to this all step; 0: lockstep)")
     ap.add_argument("--deadline", type=float, default=0.0,
                     help="serve: cancel a request this many seconds after its arrival (0: never)")
     ap.add_argument("--precision", default=None)
@@ -428,7 +430,8 @@ def main(argv=None):
                            tau=a.tau, side=a.side, router=a.router)
         reqs = [r for r in sv.poisson_requests(a.rate, a.duration) if r.n <= a.max_n]
         print(f"  {len(reqs)} requests, n = {[r.n for r in reqs]}", flush=True)
-        out = sv.serve(reqs, cfg, int(a.budget_gb * 2 ** 30), on_round=_progress("serve"), deadline_s=a.deadline)
+        out = sv.serve(reqs, cfg, int(a.budget_gb * 2 ** 30), on_round=_progress("serve"), deadline_s=a.deadline,
+                       light_chi=a.light_chi)
         print("  sequential FP32 baseline", flush=True)
         base_cfg = dr.RunConfig(chi_max=cfg.chi_max, cutoff=cfg.cutoff, cutoff_mode=cfg.cutoff_mode,
                                 precision="fp32", tau=cfg.tau, side=cfg.side, router=cfg.router)
@@ -438,7 +441,7 @@ def main(argv=None):
         print(json.dumps({"form": "serve", "rate": a.rate, "duration": a.duration, "requests": len(reqs), "side": a.side,
                           "router": a.router,
                           "chi_max": cfg.chi_max, "max_n": a.max_n,
-                          "deadline_s": a.deadline, "tau": a.tau,
+                          "deadline_s": a.deadline, "tau": a.tau, "light_chi": a.light_chi,
                           "served": len(out["served"]), "timed_out": len(out["timed_out"]),
                           "refused": len(out["refused"]), "precision": prec, "seconds": round(out["seconds"], 3),
                           "circuits_per_s": round(out["circuits_per_s"], 4), "p50_time_to_peak_s": round(out["p50"], 3),

@@ -3,10 +3,11 @@
 Requests arrive over time (e.g. Poisson).  A request is admitted when a slot
 is free and its projected MPO memory n * chi_max^2 * 16 B fits in what the
 admitted requests leave of the budget; admitted circuits stay resident on the
-device.  Every scheduling round advances all resident circuits by one
-absorption step through shared group launches (batch.run_round), so requests
-that arrive while others are on the GPU join the running batch at the next
-round and their work overlaps on the device.  A finished circuit releases its
+device.  Every scheduling round advances resident circuits by one absorption
+step through shared group launches (batch.run_round): all the light ones
+(small bond dimensions) and the earliest-arrived heavy one (pick_round), so
+requests that arrive while others are on the GPU join the running batch at
+the next round and their work overlaps on the device.  A finished circuit releases its
 slot and memory at once.  Time-to-peak is measured from arrival to the end of
 its peak readout.
 """
@@ -93,13 +94,36 @@ def _percentiles(ttp: Sequence[float]):
     return float(np.percentile(ttp, 50)), float(np.percentile(ttp, 99))
 
 
+def pick_round(active: Sequence[tuple], light_chi: int) -> List[tuple]:
+    """The resident circuits a round advances.  A step costs about the cube
+    of the MPO's bond dimensions, so circuits whose largest bond is at most
+    `light_chi` ("light") all take a step in every round, sharing the group
+    launches, while of the heavier ones only the earliest arrival does: the
+    light requests are not held back by the rounds of the heavy ones, and the
+    heavy ones are served one after the other, as a single queue would.
+    light_chi <= 0 advances every resident circuit (plain lockstep)."""
+    if light_chi <= 0:
+        return list(active)
+    light, heavy = [], []
+    for a in active:
+        c = a[1].c
+        # an adaptive step also absorbs into a copy: the last discarded
+        # candidate (held in m2) tells what that costs
+        chi = max(max(c.m.bond_dims()), max(c.m2.bond_dims()) if c.m2 is not None else 1)
+        (light if chi <= light_chi else heavy).append(a)
+    if heavy:
+        light.append(min(heavy, key=lambda a: a[0].t_arrival))
+    return light
+
+
 def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max_slots: int = 64,
           reading: str = "A", on_round: Optional[Callable[[int, int], None]] = None,
-          keep_lams: bool = False, deadline_s: float = 0.0) -> dict:
-    """Serves `requests` (see the module docstring).  With `deadline_s` > 0 a
-    request still resident that long after its arrival is cancelled (its
-    MPO freed at once) and reported in `timed_out`; the percentiles then
-    count it at the deadline, so they are lower bounds when any timed out."""
+          keep_lams: bool = False, deadline_s: float = 0.0, light_chi: int = 64) -> dict:
+    """Serves `requests` (see the module docstring; `light_chi` is the round
+    policy of pick_round).  With `deadline_s` > 0 a request still resident
+    that long after its arrival is cancelled (its MPO freed at once) and
+    reported in `timed_out`; the percentiles then count it at the deadline,
+    so they are lower bounds when any timed out."""
     import torch
     reqs = sorted(requests, key=lambda r: r.t_arrival)
     prepare(reqs, reading)
@@ -134,7 +158,7 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
             if i < len(reqs):
                 time.sleep(max(0.0, min(0.05, reqs[i].t_arrival - (time.perf_counter() - t0))))
             continue
-        bt.run_round([a[1] for a in active], group)
+        bt.run_round([a[1] for a in pick_round(active, light_chi)], group)
         rounds += 1
         dev_peak = max(dev_peak, _device_used_bytes(torch) - dev0)
         if on_round:
@@ -212,33 +236,43 @@ def serve_sequential(requests: Sequence[Request], cfg: dr.RunConfig, reading: st
     a time, first come first served, each contracted alone with one launch per
     update wave.  The solo service time of every circuit is measured; the
     queue is then exact for a single server: a request starts when it has
-    arrived and the previous one has finished.  With `deadline_s` > 0 a
-    circuit's service stops after that long (the limit applies to service
-    time alone, which favours the baseline); such requests are counted at
-    their time in the queue plus the limit."""
+    arrived and the previous one has finished.  With `deadline_s` > 0 the
+    deadline counts from arrival, as in serve(): a request is served for at
+    most what is left of it when it starts (none if nothing is left) and is
+    counted at the deadline when it does not finish."""
     reqs = sorted(requests, key=lambda r: r.t_arrival)
     prepare(reqs, reading)
     service = []
+    solo_done = []
     ok = []
-    finished = 0
     updates = 0
     for r in reqs:
         circ = r.circuit
         t0 = time.perf_counter()
         res = _contract_within(circ, cfg, deadline_s)
         service.append(time.perf_counter() - t0)
+        solo_done.append(res is not None)
         if on_request:
             on_request(len(service), service[-1], res is not None)
         if res is not None:
-            finished += 1
             ok.append(bool((res.bits == circ.peak).all()))
             updates += res.bond_updates
     done = []
     t_free = 0.0
-    for r, s in zip(reqs, service):
+    finished = 0
+    for r, s, res_ok in zip(reqs, service, solo_done):
         start = max(r.t_arrival, t_free)
-        t_free = start + s
-        done.append(t_free - r.t_arrival)
+        left = deadline_s - (start - r.t_arrival) if deadline_s > 0 else float("inf")
+        if left <= 0:
+            done.append(deadline_s)           # expired while waiting
+            continue
+        if res_ok and s <= left:
+            t_free = start + s
+            done.append(t_free - r.t_arrival)
+            finished += 1
+        else:
+            t_free = start + min(s, left)
+            done.append(deadline_s)
     makespan = t_free if reqs else 0.0
     p50, p99 = _percentiles(done)
     return dict(seconds=makespan, circuits_per_s=finished / makespan if makespan else 0.0,

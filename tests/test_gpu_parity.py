@@ -423,3 +423,4 @@ def test_fp64_rank_deficient_tall_panels(lib):
     assert info["k"] == r.k <= 8
     assert sv_err(s_gpu, r.s[:r.k]) <= TOL["fp64"]
     assert np.max(np.abs(right @ right.conj().T - np.eye(info["k"]))) <= 1e-10
+
