@@ -114,14 +114,19 @@ def kernel_flops(cls, chi, sweeps, rotations, route="accumulate"):
     blocks, 32-column panels.  Rotation: each rotated panel is an
     (m + r) x 32 x 32 complex product (r x 32 x 32 on the second-QR route);
     Gram: every panel of every step is an m x 32 x 32 complex product;
-    theta-build and write-back are the GEMMs' flops.  None where no such count
-    is meaningful (latency-bound kernels)."""
+    QR: the Householder factorisations' flops (one, or two on the second-QR
+    route); theta-build and write-back are the GEMMs' flops.  None where no
+    such count is meaningful (latency-bound kernels)."""
     m = r = 4 * chi
     nblk = r // 16
     if cls == "jacobi_rot":
         return rotations * ((m + r) if route == "accumulate" else r) * 32 * 32 * 8.0
     if cls == "jacobi_gram":
         return sweeps * (nblk - 1) * (nblk // 2) * m * 32 * 32 * 8.0
+    if cls == "qr":
+        # complex Householder QR of an n x n matrix, 8 n^3 - (8/3) n^3 real
+        # flops; the second-QR route factors twice
+        return (2 if route == "qr2" else 1) * 16.0 / 3.0 * r ** 3
     if cls == "theta_gemm":
         return 128.0 * chi ** 3
     if cls == "writeback_gemm":
@@ -216,7 +221,7 @@ KERNEL_NAME = {"jacobi_rot": "k_jac_rot", "jacobi_gram": "k_jac_gram",
 KERNEL_NAME_MIXED = {"jacobi_rot": "k_jac_rot_mixed", "jacobi_gram": "k_jac_gram_bf16"}
 
 
-def measured_traffic(kernel, route="accumulate"):
+def measured_traffic(kernel, route="accumulate", precision="mixed"):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/*_traffic.md, two rocprofv3 --pmc passes scaled by the copy
     calibration) taken on the same SVD route, or None when there is none or
@@ -233,7 +238,7 @@ def measured_traffic(kernel, route="accumulate"):
                 fields[k.strip()] = v.strip()
         if fields.get("kernel") != kernel or "traffic_bytes_per_launch" not in fields:
             continue
-        if fields.get("svd_route", "accumulate") != route:
+        if fields.get("svd_route", "accumulate") != route or fields.get("precision", "mixed") != precision:
             continue
         digest = hashlib.sha256()
         for name in fields.get("source", "").split(","):
@@ -270,7 +275,8 @@ def roofline_of(run, prec_name, chi, steps):
         names["jacobi_rot"] = "k_jac_rot"          # the operand is rotated on FP32 MFMA on this route
     out = {"kernel": names.get(dom, dom), "class": dom, "svd_route": route,
            "avg_launch_ms": round(ms / max(launches, 1), 5),
-           "launches_per_update": launches / steps, "traffic": measured_traffic(names.get(dom, dom), route)}
+           "launches_per_update": launches / steps,
+           "traffic": measured_traffic(names.get(dom, dom), route, prec_name)}
     if byt:
         achieved = byt / (ms * 1e-3) / 1e9
         out.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

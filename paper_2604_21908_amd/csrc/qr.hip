@@ -388,6 +388,14 @@ __global__ __launch_bounds__(QMW_ROWS) void k_qr_panel(QrBatch qb, QrSyncBatch s
   // orders the other threads' loads) per barrier.
   auto grid_sum = [&](int C) {
     __syncthreads();
+    if (nwg == 1) {
+      // a panel of at most QMW_ROWS rows: no other workgroup to meet, so no
+      // counter, no agent-scope release/acquire and no round trip through
+      // memory (the sum is the one the exchange would give: 0 + x)
+      if (tid < C) tot[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+      __syncthreads();
+      return;
+    }
     double* mine = S.part + ((size_t)(bar & 1) * QMW_MAXWG + w) * QMW_VALS;
     if (tid < C) mine[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
     __syncthreads();
