@@ -122,6 +122,23 @@ struct JacBatch {
   int count;
 };
 
+// Column ordering of the Jacobi operand before the first sweeps (second-QR
+// route): the columns by decreasing norm, ties by index; the pair-skip
+// bookkeeping is cleared since the blocks then hold other columns.
+struct ColSortProb {
+  const double* norms;  // ncol_pad column norms of the operand
+  int* perm;            // out: perm[j] = the column that goes to position j
+  const void* A;        // operand, column-major, lda x ncol_pad
+  void* A2;             // out: the operand with its columns in that order
+  int* pchk;
+  int* bmod;
+  int m, lda, ncol, ncol_pad, nblk;
+};
+struct ColSortBatch {
+  ColSortProb p[MAXB];
+  int count;
+};
+
 // ---------------------------------------------------------------- QR
 // Householder QR of M (n x m, column-major, leading dimension n) over its
 // first r = min(n, m) columns, in panels of QNB columns: R on and above the

@@ -7,6 +7,7 @@
 //   k_jac_init / k_jac_sweep_end   state of the block Jacobi SVD (steps: jacobi.hip)
 //   k_colnorms     singular values as column norms (FP64)
 //   k_unit_cols    the converged columns scaled to unit length
+//   k_col_order / k_permute_cols   columns by decreasing norm (second-QR route)
 //   k_sort_trunc   descending sort + truncation decision (FP64)
 //   k_env / k_greedy  peak readout of M|0...0> (FP64)
 //   k_sample_pick  one site of conditional sampling of M|0...0> for many samples (FP64)
@@ -312,6 +313,70 @@ __global__ __launch_bounds__(256) void k_unit_cols(JacBatch jb) {
     const T mk = r < P.m ? sc : (T)0;
     U[r] = cx<T>{mk * x.re, mk * x.im};
   }
+}
+
+// Columns by decreasing norm (ties by index; a non-finite norm sorts first,
+// so it stays among the real columns and the truncation still reports it;
+// padding columns last), and the pair-skip bookkeeping cleared.  One
+// workgroup per problem, bitonic sort in LDS.
+__global__ __launch_bounds__(1024) void k_col_order(ColSortBatch cb) {
+  const int pi = blockIdx.x;
+  if (pi >= cb.count) return;
+  const ColSortProb P = cb.p[pi];
+  __shared__ double key[4096];
+  __shared__ int idx[4096];
+  int N2 = 1;
+  while (N2 < P.ncol_pad) N2 <<= 1;
+  for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+    double v = (i < P.ncol) ? P.norms[i] : -1.0;
+    if (!isfinite(v)) v = __builtin_huge_val();
+    key[i] = (i < P.ncol_pad) ? v : -2.0;
+    idx[i] = i;
+  }
+  const int nb = P.nblk;
+  for (int i = threadIdx.x; i < nb * nb + nb; i += blockDim.x) {
+    if (i < nb * nb) P.pchk[i] = 0;
+    else P.bmod[i - nb * nb] = 0;
+  }
+  __syncthreads();
+  for (int k = 2; k <= N2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = ((i & k) == 0);
+          const double ki = key[i], kl = key[l];
+          const int ii = idx[i], il = idx[l];
+          const bool l_before_i = (kl > ki) || (kl == ki && il < ii);
+          if (up ? l_before_i : !l_before_i) {
+            key[i] = kl;
+            key[l] = ki;
+            idx[i] = il;
+            idx[l] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < P.ncol_pad; i += blockDim.x) P.perm[i] = idx[i];
+}
+
+// A2[:, j] = A[:, perm[j]] over the m used rows: column blockIdx.x, rows in
+// chunks of 1024 (blockIdx.y).
+template <typename T>
+__global__ __launch_bounds__(256) void k_permute_cols(ColSortBatch cb) {
+  const int pi = blockIdx.z;
+  if (pi >= cb.count) return;
+  const ColSortProb P = cb.p[pi];
+  const int j = blockIdx.x;
+  if (j >= P.ncol_pad) return;
+  const int r0 = blockIdx.y * 1024;
+  if (r0 >= P.m) return;
+  const cx<T>* src = (const cx<T>*)P.A + (size_t)P.perm[j] * P.lda;
+  cx<T>* dst = (cx<T>*)P.A2 + (size_t)j * P.lda;
+  const int r1 = min(P.m, r0 + 1024);
+  for (int r = r0 + threadIdx.x; r < r1; r += 256) dst[r] = src[r];
 }
 
 // ============================================================== sort + truncation
@@ -620,6 +685,11 @@ void launch_colnorms(const JacBatch& b, int maxcols, hipStream_t s) {
   hipLaunchKernelGGL(k_colnorms<T>, dim3((maxcols + 3) / 4, b.count), dim3(256), 0, s, b);
 }
 template <typename T>
+void launch_col_order(const ColSortBatch& b, int maxcols, int maxrows, hipStream_t s) {
+  hipLaunchKernelGGL(k_col_order, dim3(b.count), dim3(1024), 0, s, b);
+  hipLaunchKernelGGL(k_permute_cols<T>, dim3(maxcols, (maxrows + 1023) / 1024, b.count), dim3(256), 0, s, b);
+}
+template <typename T>
 void launch_unit_cols(const JacBatch& b, int maxcols, hipStream_t s) {
   hipLaunchKernelGGL(k_unit_cols<T>, dim3(maxcols, b.count), dim3(256), 0, s, b);
 }
@@ -658,6 +728,7 @@ void launch_convert(cx<TD>* d, const cx<TS>* src, size_t n, hipStream_t s) {
   template void launch_jac_init<T>(const JacBatch&, hipStream_t);                                        \
   template void launch_colnorms<T>(const JacBatch&, int, hipStream_t);                                   \
   template void launch_unit_cols<T>(const JacBatch&, int, hipStream_t);                                  \
+  template void launch_col_order<T>(const ColSortBatch&, int, int, hipStream_t);                         \
   template void launch_greedy<T>(const cx<T>*, int, int, const cx<double>*, const cx<double>*,           \
                                  cx<double>*, cx<double>*, unsigned char*, double*, hipStream_t);
 

@@ -29,6 +29,7 @@ template <typename T> void launch_ns_corr(const cx<double>*, cx<T>*, int, hipStr
 void launch_jac_sweep_end(const JacBatch&, hipStream_t);
 template <typename T> void launch_colnorms(const JacBatch&, int, hipStream_t);
 template <typename T> void launch_unit_cols(const JacBatch&, int, hipStream_t);
+template <typename T> void launch_col_order(const ColSortBatch&, int, int, hipStream_t);
 void launch_sort_trunc(const TruncBatch&, hipStream_t);
 template <typename T> void launch_qr_panel(const QrBatch&, const QrSyncBatch&, int, int, hipStream_t);
 template <typename T> void launch_qr_apply(const QrApplyBatch&, int, int, hipStream_t);
@@ -121,6 +122,11 @@ struct Slot {
   void* tau2 = nullptr;
   void* Tf2 = nullptr;
   size_t cap_L2 = 0, cap_r2 = 0;
+  // ... and the column ordering of its first sweeps: a second operand
+  // buffer (the two are swapped) and the permutation
+  void* A2 = nullptr;
+  int* cperm = nullptr;
+  size_t cap_A2 = 0, cap_cperm = 0;
   unsigned* qcnt = nullptr;   // multi-workgroup QR panel: barrier counter (zeroed once)
   double* qpart = nullptr;    // ... and partial sums
   unsigned qbase = 0;         // the counter's value after the launches so far
@@ -410,8 +416,22 @@ void ensure_qr(mpo_ctx* h, Slot& s, size_t r, size_t nY, size_t nwp, size_t nw2)
   }
 }
 
-void ensure_qr2(mpo_ctx* h, Slot& s, size_t nl, size_t r) {
+void ensure_qr2(mpo_ctx* h, Slot& s, size_t nl, size_t r, size_t nA, size_t ncol) {
   const size_t e = h->esz;
+  if (s.cap_A2 < nA) {
+    dfree(h, s.A2);
+    s.A2 = nullptr;
+    s.cap_A2 = 0;
+    s.A2 = dalloc(h, nA * e);
+    s.cap_A2 = nA;
+  }
+  if (s.cap_cperm < ncol) {
+    dfree(h, s.cperm);
+    s.cperm = nullptr;
+    s.cap_cperm = 0;
+    s.cperm = (int*)dalloc(h, ncol * sizeof(int));
+    s.cap_cperm = ncol;
+  }
   if (s.cap_L2 < nl) {
     dfree(h, s.L2);
     s.L2 = nullptr;
@@ -569,6 +589,10 @@ void reorthogonalise(mpo_ctx* h, const RShapes& rs, const JacBatch& jb, hipStrea
 }
 
 constexpr size_t GRAPH_CACHE = 64;
+// column ordering of the second-QR route: before the first sweeps, operands
+// at least this wide
+constexpr int COL_SORT_SWEEPS = 3;
+constexpr int COL_SORT_MIN_R = 1024;
 
 // ---- launch choices of the Jacobi sweeps, and their autotuner ---------------
 // A batch's sweeps can split the panel rotation into row chunks of 64, 128 or
@@ -808,7 +832,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     const size_t nwp1 = (size_t)((s.n + QRC1 - 1) / QRC1) * QNB * s.m;
     const size_t nwp2 = qr2 ? (size_t)((s.m + QRC1 - 1) / QRC1) * QNB * s.r : 0;
     ensure_qr(h, sl, (size_t)s.r, commit ? (size_t)s.n * s.r : 0, std::max(nwp1, nwp2), (size_t)QNB * s.m);
-    if (qr2) ensure_qr2(h, sl, (size_t)s.m * s.r, (size_t)s.r);
+    if (qr2) ensure_qr2(h, sl, (size_t)s.m * s.r, (size_t)s.r, (size_t)s.lda * s.rpad, (size_t)s.rpad);
     ensure_jac(h, sl, (size_t)(s.nblk / 2), (size_t)((s.rows + GRC - 1) / GRC));
     maxgch = std::max(maxgch, (s.rows + GRC - 1) / GRC);
   }
@@ -906,6 +930,30 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     if (commit && !qr2) nrch_v = std::max(nrch_v, (sh[p].r + rrc - 1) / rrc);
   }
   const bool use_graph = plan.graph && !h->prof_on;
+  // Second-QR route, wide operands: the operand's columns are put in order of
+  // decreasing norm before each of the first sweeps (a permutation of the
+  // operand, which the final sort of the values absorbs); the sweeps then
+  // converge in fewer rounds (de Rijk's ordering for one-sided Jacobi).
+  const bool reorder = qr2 && maxr >= COL_SORT_MIN_R;
+  auto reorder_columns = [&]() {
+    timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_colnorms<T>(jb, maxrpad, st); });
+    ColSortBatch cb{};
+    cb.count = count;
+    int maxrows = 0;
+    for (int p = 0; p < count; ++p) {
+      const Shape& s = sh[p];
+      Slot& sl = h->slots[p];
+      cb.p[p] = ColSortProb{sl.norms, sl.cperm, sl.A, sl.A2, sl.pchk, sl.bmod, s.rows, s.lda, s.r, s.rpad, s.nblk};
+      maxrows = std::max(maxrows, s.rows);
+    }
+    timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_col_order<T>(cb, maxrpad, maxrows, st); });
+    for (int p = 0; p < count; ++p) {
+      Slot& sl = h->slots[p];
+      std::swap(sl.A, sl.A2);
+      std::swap(sl.cap_A, sl.cap_A2);
+      jb.p[p].A = sl.A;
+    }
+  };
   auto sweeps = [&](int bf16, int budget) {
     bool active_left = true;
     auto record = [&](hipStream_t s) {
@@ -919,7 +967,9 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
       launch_jac_sweep_end(jb, s);
     };
     std::string key;
-    if (use_graph) {
+    auto make_key = [&]() {
+      if (!use_graph) return;
+      key.clear();
       key.reserve(64 + count * sizeof(JacProb));
       key_put(key, count), key_put(key, maxblk), key_put(key, maxpairs), key_put(key, maxgch);
       key_put(key, nrch_a), key_put(key, nrch_v), key_put(key, rrc), key_put(key, bf16), key_put(key, sizeof(T));
@@ -930,8 +980,13 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
         key_put(key, q.m), key_put(key, q.lda), key_put(key, q.ncol), key_put(key, q.ncol_pad), key_put(key, q.nblk);
         key_put(key, q.ngchunk);
       }
-    }
+    };
+    make_key();
     for (int sw = 0; sw < budget && active_left; ++sw) {
+      if (reorder && sw < COL_SORT_SWEEPS) {
+        reorder_columns();
+        make_key();
+      }
       const auto t0 = std::chrono::steady_clock::now();
       bool captured = false;
       if (use_graph) {
@@ -1534,6 +1589,8 @@ void destroy(mpo_ctx* h) {
     dfree(h, s.L2);
     dfree(h, s.tau2);
     dfree(h, s.Tf2);
+    dfree(h, s.A2);
+    dfree(h, s.cperm);
   }
   for (auto& p : h->pending) {
     (void)hipEventDestroy(p.a);
