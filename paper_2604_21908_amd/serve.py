@@ -5,7 +5,8 @@ is free and its projected MPO memory n * chi_max^2 * 16 B fits in what the
 admitted requests leave of the budget; admitted circuits stay resident on the
 device.  Every scheduling round advances resident circuits by one absorption
 step through shared group launches (batch.run_round): all the light ones
-(small bond dimensions) and the earliest-arrived heavy one (pick_round), so
+(small bond dimensions), and in every few rounds the earliest-arrived heavy
+one (pick_round), so
 requests that arrive while others are on the GPU join the running batch at
 the next round and their work overlaps on the device.  A finished circuit releases its
 slot and memory at once.  Time-to-peak is measured from arrival to the end of
@@ -94,14 +95,16 @@ def _percentiles(ttp: Sequence[float]):
     return float(np.percentile(ttp, 50)), float(np.percentile(ttp, 99))
 
 
-def pick_round(active: Sequence[tuple], light_chi: int) -> List[tuple]:
+def pick_round(active: Sequence[tuple], light_chi: int, round_no: int = 0, heavy_every: int = 4) -> List[tuple]:
     """The resident circuits a round advances.  A step costs about the cube
     of the MPO's bond dimensions, so circuits whose largest bond is at most
     `light_chi` ("light") all take a step in every round, sharing the group
-    launches, while of the heavier ones only the earliest arrival does: the
-    light requests are not held back by the rounds of the heavy ones, and the
-    heavy ones are served one after the other, as a single queue would.
-    light_chi <= 0 advances every resident circuit (plain lockstep)."""
+    launches, while of the heavier ones only the earliest arrival does, and
+    only in every `heavy_every`-th round while light ones are resident: the
+    light requests (the short jobs) are not held back by the steps of the
+    heavy ones, and the heavy ones are served one after the other, as a
+    single queue would.  light_chi <= 0 advances every resident circuit
+    (plain lockstep)."""
     if light_chi <= 0:
         return list(active)
     light, heavy = [], []
@@ -111,7 +114,7 @@ def pick_round(active: Sequence[tuple], light_chi: int) -> List[tuple]:
         # candidate (held in m2) tells what that costs
         chi = max(max(c.m.bond_dims()), max(c.m2.bond_dims()) if c.m2 is not None else 1)
         (light if chi <= light_chi else heavy).append(a)
-    if heavy:
+    if heavy and (not light or round_no % max(1, heavy_every) == 0):
         light.append(min(heavy, key=lambda a: a[0].t_arrival))
     return light
 
@@ -158,7 +161,7 @@ def serve(requests: Sequence[Request], cfg: dr.RunConfig, budget_bytes: int, max
             if i < len(reqs):
                 time.sleep(max(0.0, min(0.05, reqs[i].t_arrival - (time.perf_counter() - t0))))
             continue
-        bt.run_round([a[1] for a in pick_round(active, light_chi)], group)
+        bt.run_round([a[1] for a in pick_round(active, light_chi, rounds)], group)
         rounds += 1
         dev_peak = max(dev_peak, _device_used_bytes(torch) - dev0)
         if on_round:
