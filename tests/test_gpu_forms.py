@@ -77,14 +77,17 @@ def test_batched_with_binding_chi_matches_oracle(mods, prec):
     """Reading-B circuits whose permutation content exceeds chi_max (the cap
     binds and unswapping runs): each circuit of the group run equals the oracle
     run of the same circuit and settings (bits, bond values, p), and the lone
-    run bitwise.  The circuits and settings are ones whose oracle trajectory
-    (every kept rank, the bits, every bond's values to 1e-5) does not change
-    when each SVD input carries 1e-7 relative noise: with chi_max binding, a
-    trajectory that did change under such noise (several settings with
-    smaller chi_max and tau do; their summed discarded weight is close to 1)
-    would make any comparison of FP32 runs arbitrary."""
+    run bitwise.  The circuits and settings are ones whose oracle result (the
+    bits, p to 1e-3) does not change when each SVD input carries 1e-6
+    relative noise, the level an FP32 update's rounding reaches: with chi_max
+    binding, a trajectory that does change under such noise (several
+    settings with smaller chi_max and tau do; their summed discarded weight
+    is close to 1) would make any comparison of FP32 runs arbitrary.  (The
+    9-qubit circuit of seed 79 passed at 1e-7 but not at 1e-6, where two of
+    six noise draws end at p = 0.1826 instead of 0.1773; seed 279 replaces
+    it.)"""
     bt, dr, sv = mods
-    circs = [cg.mirrored_peaked_circuit(n, d, 70 + n, reading="B") for n, d in ((8, 3), (9, 2), (10, 3))]
+    circs = [cg.mirrored_peaked_circuit(n, d, seed, reading="B") for n, d, seed in ((8, 3, 78), (9, 2, 279), (10, 3, 80))]
     cfgs = [dr.RunConfig(chi_max=chi, cutoff=1e-10, cutoff_mode="weight", precision=prec, tau=tau)
             for chi, tau in ((16, 400), (16, 400), (16, 400))]
     out = bt.run_batched(list(zip(circs, cfgs)), precision=prec, keep_lams=True)
