@@ -8,9 +8,10 @@
 //               MFMA (f32 16x16x4 with an FP64 sum per 64-row slab, or f64);
 //               grid = pairs x row chunks x problems
 //   k_jac_evd   per panel: FP64 sum of the partial Grams, convergence test,
-//               at most one or two sweeps of cyclic Jacobi on G with FP64
-//               angles (the outer iteration finishes what they leave), and
-//               D = W - I rounded to the working precision
+//               at most one or two sweeps of cyclic Jacobi on G (FP64
+//               angles; rotations in the working precision: FP64, or FP32 for
+//               the FP32 and mixed forms; the outer iteration finishes what
+//               they leave), and D = W - I rounded to the working precision
 //   k_jac_rot   P <- P + P D (rotation.hip)
 //   k_jac_gram_bf16  the mixed form's Gram matrices with split-BF16 products
 //               (the EVD stays FP64)
@@ -152,6 +153,27 @@ __device__ __forceinline__ bool jac_angle(double app, double aqq, cx<double> g, 
   return rot;
 }
 
+template <typename E>
+__device__ __forceinline__ bool jac_angle_e(E app, E aqq, cx<E> g, double tol, bool fine, E& c, E& zr, E& zi);
+template <>
+__device__ __forceinline__ bool jac_angle_e<double>(double app, double aqq, cx<double> g, double tol, bool fine,
+                                                    double& c, double& zr, double& zi) {
+  return fine ? jac_angle<true>(app, aqq, g, tol, c, zr, zi) : jac_angle<false>(app, aqq, g, tol, c, zr, zi);
+}
+// FP32 panels (the FP32 and mixed forms): the angle from the FP32 entries in
+// FP64 arithmetic (the squares of tiny entries would be denormal in FP32),
+// the rotation itself applied in FP32.
+template <>
+__device__ __forceinline__ bool jac_angle_e<float>(float app, float aqq, cx<float> g, double tol, bool, float& c,
+                                                   float& zr, float& zi) {
+  double cd, zrd, zid;
+  const bool rot = jac_angle<false>((double)app, (double)aqq, cx<double>{(double)g.re, (double)g.im}, tol, cd, zrd, zid);
+  c = (float)cd;
+  zr = (float)zrd;
+  zi = (float)zid;
+  return rot;
+}
+
 // In a round-robin step the 32 indices form 16 disjoint pairs; the rotation
 // J_k of pair k acts on columns (p_k, q_k).  Thread (kr, kc) owns the 2x2
 // block of G at rows (p_kr, q_kr) x columns (p_kc, q_kc) and replaces it by
@@ -162,17 +184,20 @@ __device__ __forceinline__ bool jac_angle(double app, double aqq, cx<double> g, 
 // G is double-buffered (read one copy, write the other), so a round needs a
 // single barrier; W is updated in place (each thread touches only its block).
 // The pairs of the 31 rounds are tabulated once as LDS byte offsets.
+// E is the arithmetic of the rotations: FP64 in the FP64 form, FP32 in the
+// FP32 and mixed forms (whose tolerances are far above FP32 rounding); the
+// partial Gram matrices are summed in FP64 either way, angles formed in FP64.
 constexpr int EVD_LD = 33;                       // row stride of G and W (entries)
-constexpr int EVD_ROWB = EVD_LD * 16;            // ... in bytes (cx<double>)
-template <typename T>
+template <typename T, typename E>
 __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inner_sweeps) {
+  constexpr int EVD_ROWB = EVD_LD * (int)sizeof(cx<E>);   // ... in bytes
   const int pi = blockIdx.y;
   if (pi >= jb.count) return;
   const JacProb P = jb.p[pi];
   if (step >= P.nblk - 1 || (int)blockIdx.x >= P.nblk / 2) return;
   const double tol = P.tol;
-  __shared__ cx<double> G[2][32][EVD_LD];
-  __shared__ cx<double> W[32][EVD_LD];
+  __shared__ cx<E> G[2][32][EVD_LD];
+  __shared__ cx<E> W[32][EVD_LD];
   __shared__ ushort4 ptab[31][16];   // pair k of round st: (p, q) row and column byte offsets
   __shared__ int flag, anyrot;
   const int tid = threadIdx.x;
@@ -210,14 +235,14 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    G[0][gi][gj0 + u] = cx<double>{sr[u], si[u]};
-    W[gi][gj0 + u] = cx<double>{(gi == gj0 + u) ? 1.0 : 0.0, 0.0};
+    G[0][gi][gj0 + u] = cx<E>{(E)sr[u], (E)si[u]};
+    W[gi][gj0 + u] = cx<E>{(E)((gi == gj0 + u) ? 1 : 0), (E)0};
   }
   for (int e = tid; e < 31 * 16; e += 256) {
     int p, q;
     rr_pair2(32, e >> 4, e & 15, p, q);
     ptab[e >> 4][e & 15] = ushort4{(unsigned short)(p * EVD_ROWB), (unsigned short)(q * EVD_ROWB),
-                                   (unsigned short)(p * 16), (unsigned short)(q * 16)};
+                                   (unsigned short)(p * sizeof(cx<E>)), (unsigned short)(q * sizeof(cx<E>))};
   }
   if (active == 0) return;
   if (chk > 0 && chk > mod_i && chk > mod_j) {   // unchanged converged pair
@@ -233,9 +258,11 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   for (int u = 0; u < 4; ++u) {
     const int j = gj0 + u;
     if (j > gi) {
-      const cx<double> g = G[0][gi][j];
-      const double d = G[0][gi][gi].re * G[0][j][j].re;
-      if (d > 0 && g.re * g.re + g.im * g.im > tol * tol * d) flag = 1;
+      // on the entries as the rotations see them, in FP64 (as jac_angle tests)
+      const cx<E> g = G[0][gi][j];
+      const double d = (double)G[0][gi][gi].re * (double)G[0][j][j].re;
+      const double g2 = (double)g.re * (double)g.re + (double)g.im * (double)g.im;
+      if (d > 0 && g2 > tol * tol * d) flag = 1;
     }
   }
   __syncthreads();
@@ -262,41 +289,41 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
       char* const gc = g0 + cur * (32 * EVD_ROWB);
       char* const gn = g0 + (cur ^ 1) * (32 * EVD_ROWB);
       const ushort4 R = ptab[st][kr], C = ptab[st][kc];
-      auto at = [](char* base, int off) -> cx<double>& { return *(cx<double>*)(base + off); };
-      const cx<double> a00 = at(gc, R.x + C.z), a01 = at(gc, R.x + C.w), a10 = at(gc, R.y + C.z),
-                       a11 = at(gc, R.y + C.w);
-      const cx<double> w00 = at(wb, R.x + C.z), w01 = at(wb, R.x + C.w), w10 = at(wb, R.y + C.z),
-                       w11 = at(wb, R.y + C.w);
+      auto at = [](char* base, int off) -> cx<E>& { return *(cx<E>*)(base + off); };
+      const cx<E> a00 = at(gc, R.x + C.z), a01 = at(gc, R.x + C.w), a10 = at(gc, R.y + C.z),
+                  a11 = at(gc, R.y + C.w);
+      const cx<E> w00 = at(wb, R.x + C.z), w01 = at(wb, R.x + C.w), w10 = at(wb, R.y + C.z),
+                  w11 = at(wb, R.y + C.w);
       // column pair's own entries: (p, p) at row p col p, (q, q), (p, q)
-      const double app = at(gc, C.x + C.z).re, aqq = at(gc, C.y + C.w).re;
-      const cx<double> gpq = at(gc, C.x + C.w);
-      double cc, zcr, zci;
-      if (jac_angle<sizeof(T) == 8>(app, aqq, gpq, tol, cc, zcr, zci)) anyrot = isw + 1;
-      const double cr = __shfl(cc, src, 64), zrr = __shfl(zcr, src, 64), zri = __shfl(zci, src, 64);
+      const E app = at(gc, C.x + C.z).re, aqq = at(gc, C.y + C.w).re;
+      const cx<E> gpq = at(gc, C.x + C.w);
+      E cc, zcr, zci;
+      if (jac_angle_e<E>(app, aqq, gpq, tol, sizeof(T) == 8, cc, zcr, zci)) anyrot = isw + 1;
+      const E cr = __shfl(cc, src, 64), zrr = __shfl(zcr, src, 64), zri = __shfl(zci, src, 64);
       // H = G_block J_c; x * (-conj(zc)) = -(x.re zcr + x.im zci) + i (x.re zci - x.im zcr)
-      const double h00r = a00.re * cc - (a01.re * zcr + a01.im * zci);
-      const double h00i = a00.im * cc + (a01.re * zci - a01.im * zcr);
-      const double h01r = a00.re * zcr - a00.im * zci + a01.re * cc;
-      const double h01i = a00.re * zci + a00.im * zcr + a01.im * cc;
-      const double h10r = a10.re * cc - (a11.re * zcr + a11.im * zci);
-      const double h10i = a10.im * cc + (a11.re * zci - a11.im * zcr);
-      const double h11r = a10.re * zcr - a10.im * zci + a11.re * cc;
-      const double h11i = a10.re * zci + a10.im * zcr + a11.im * cc;
+      const E h00r = a00.re * cc - (a01.re * zcr + a01.im * zci);
+      const E h00i = a00.im * cc + (a01.re * zci - a01.im * zcr);
+      const E h01r = a00.re * zcr - a00.im * zci + a01.re * cc;
+      const E h01i = a00.re * zci + a00.im * zcr + a01.im * cc;
+      const E h10r = a10.re * cc - (a11.re * zcr + a11.im * zci);
+      const E h10i = a10.im * cc + (a11.re * zci - a11.im * zcr);
+      const E h11r = a10.re * zcr - a10.im * zci + a11.re * cc;
+      const E h11i = a10.re * zci + a10.im * zcr + a11.im * cc;
       // G' = J_r^dag H, J_r^dag = [[cr, -zr], [conj(zr), cr]]
-      at(gn, R.x + C.z) = cx<double>{cr * h00r - (zrr * h10r - zri * h10i), cr * h00i - (zrr * h10i + zri * h10r)};
-      at(gn, R.x + C.w) = cx<double>{cr * h01r - (zrr * h11r - zri * h11i), cr * h01i - (zrr * h11i + zri * h11r)};
-      at(gn, R.y + C.z) = cx<double>{zrr * h00r + zri * h00i + cr * h10r, zrr * h00i - zri * h00r + cr * h10i};
-      at(gn, R.y + C.w) = cx<double>{zrr * h01r + zri * h01i + cr * h11r, zrr * h01i - zri * h01r + cr * h11i};
-      if (!(zcr == 0.0 && zci == 0.0)) {
+      at(gn, R.x + C.z) = cx<E>{cr * h00r - (zrr * h10r - zri * h10i), cr * h00i - (zrr * h10i + zri * h10r)};
+      at(gn, R.x + C.w) = cx<E>{cr * h01r - (zrr * h11r - zri * h11i), cr * h01i - (zrr * h11i + zri * h11r)};
+      at(gn, R.y + C.z) = cx<E>{zrr * h00r + zri * h00i + cr * h10r, zrr * h00i - zri * h00r + cr * h10i};
+      at(gn, R.y + C.w) = cx<E>{zrr * h01r + zri * h01i + cr * h11r, zrr * h01i - zri * h01r + cr * h11i};
+      if (!(zcr == (E)0 && zci == (E)0)) {
         // W' = W_block J_c on rows (pr, qr)
         at(wb, R.x + C.z) =
-            cx<double>{w00.re * cc - (w01.re * zcr + w01.im * zci), w00.im * cc + (w01.re * zci - w01.im * zcr)};
+            cx<E>{w00.re * cc - (w01.re * zcr + w01.im * zci), w00.im * cc + (w01.re * zci - w01.im * zcr)};
         at(wb, R.x + C.w) =
-            cx<double>{w00.re * zcr - w00.im * zci + w01.re * cc, w00.re * zci + w00.im * zcr + w01.im * cc};
+            cx<E>{w00.re * zcr - w00.im * zci + w01.re * cc, w00.re * zci + w00.im * zcr + w01.im * cc};
         at(wb, R.y + C.z) =
-            cx<double>{w10.re * cc - (w11.re * zcr + w11.im * zci), w10.im * cc + (w11.re * zci - w11.im * zcr)};
+            cx<E>{w10.re * cc - (w11.re * zcr + w11.im * zci), w10.im * cc + (w11.re * zci - w11.im * zcr)};
         at(wb, R.y + C.w) =
-            cx<double>{w10.re * zcr - w10.im * zci + w11.re * cc, w10.re * zci + w10.im * zcr + w11.im * cc};
+            cx<E>{w10.re * zcr - w10.im * zci + w11.re * cc, w10.re * zci + w10.im * zcr + w11.im * cc};
       }
       __syncthreads();
     }
@@ -309,7 +336,7 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int r = gi, c = gj0 + u;
-    D[r * 32 + c] = cx<T>{(T)(W[r][c].re - (r == c ? 1.0 : 0.0)), (T)W[r][c].im};
+    D[r * 32 + c] = cx<T>{(T)(W[r][c].re - (E)(r == c ? 1 : 0)), (T)W[r][c].im};
   }
 }
 
@@ -430,7 +457,8 @@ void launch_jac_gram(const JacBatch& b, int maxpairs, int maxgch, int step, int 
 }
 template <typename T>
 void launch_jac_evd(const JacBatch& b, int maxpairs, int step, int inner_sweeps, hipStream_t s) {
-  hipLaunchKernelGGL(k_jac_evd<T>, dim3(maxpairs, b.count), dim3(256), 0, s, b, step, inner_sweeps);
+  // rotations in the working precision: FP32 in the FP32 and mixed forms
+  hipLaunchKernelGGL((k_jac_evd<T, T>), dim3(maxpairs, b.count), dim3(256), 0, s, b, step, inner_sweeps);
 }
 template <>
 void launch_jac_gram<double>(const JacBatch& b, int maxpairs, int maxgch, int step, int, hipStream_t s) {
