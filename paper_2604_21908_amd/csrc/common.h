@@ -133,6 +133,7 @@ struct ColSortProb {
   int* pchk;
   int* bmod;
   int m, lda, ncol, ncol_pad, nblk;
+  int on;               // 0: this problem is left as it is (both kernels skip it)
 };
 struct ColSortBatch {
   ColSortProb p[MAXB];

@@ -323,6 +323,7 @@ __global__ __launch_bounds__(1024) void k_col_order(ColSortBatch cb) {
   const int pi = blockIdx.x;
   if (pi >= cb.count) return;
   const ColSortProb P = cb.p[pi];
+  if (!P.on) return;
   __shared__ double key[4096];
   __shared__ int idx[4096];
   int N2 = 1;
@@ -369,6 +370,7 @@ __global__ __launch_bounds__(256) void k_permute_cols(ColSortBatch cb) {
   const int pi = blockIdx.z;
   if (pi >= cb.count) return;
   const ColSortProb P = cb.p[pi];
+  if (!P.on) return;
   const int j = blockIdx.x;
   if (j >= P.ncol_pad) return;
   const int r0 = blockIdx.y * 1024;

@@ -933,21 +933,30 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
   // Second-QR route, wide operands: the operand's columns are put in order of
   // decreasing norm before each of the first sweeps (a permutation of the
   // operand, which the final sort of the values absorbs); the sweeps then
-  // converge in fewer rounds (de Rijk's ordering for one-sided Jacobi).
+  // converge in fewer rounds (de Rijk's ordering for one-sided Jacobi).  The
+  // choice is made per problem from its own width and state, never from the
+  // batch, so a problem updated in a group gives the bits of its lone update:
+  // ordered before sweep sw only if it is wide and still active then.
   const bool reorder = qr2 && maxr >= COL_SORT_MIN_R;
-  auto reorder_columns = [&]() {
-    timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_colnorms<T>(jb, maxrpad, st); });
+  auto reorder_columns = [&](int sw) {
     ColSortBatch cb{};
     cb.count = count;
     int maxrows = 0;
+    bool any = false;
     for (int p = 0; p < count; ++p) {
       const Shape& s = sh[p];
       Slot& sl = h->slots[p];
-      cb.p[p] = ColSortProb{sl.norms, sl.cperm, sl.A, sl.A2, sl.pchk, sl.bmod, s.rows, s.lda, s.r, s.rpad, s.nblk};
-      maxrows = std::max(maxrows, s.rows);
+      const int on = s.r >= COL_SORT_MIN_R && (sw == 0 || h->h_states[p].active != 0);
+      cb.p[p] = ColSortProb{sl.norms, sl.cperm, sl.A, sl.A2, sl.pchk, sl.bmod, s.rows, s.lda, s.r, s.rpad, s.nblk,
+                            on};
+      if (on) maxrows = std::max(maxrows, s.rows);
+      any |= on != 0;
     }
+    if (!any) return;
+    timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_colnorms<T>(jb, maxrpad, st); });
     timed(h, MPO_PROF_JACOBI_INIT, [&] { launch_col_order<T>(cb, maxrpad, maxrows, st); });
     for (int p = 0; p < count; ++p) {
+      if (!cb.p[p].on) continue;
       Slot& sl = h->slots[p];
       std::swap(sl.A, sl.A2);
       std::swap(sl.cap_A, sl.cap_A2);
@@ -984,7 +993,7 @@ mpo_status_t run_batch(mpo_ctx* h, const Req* reqs, int count, Res* out, bool co
     make_key();
     for (int sw = 0; sw < budget && active_left; ++sw) {
       if (reorder && sw < COL_SORT_SWEEPS) {
-        reorder_columns();
+        reorder_columns(sw);
         make_key();
       }
       const auto t0 = std::chrono::steady_clock::now();

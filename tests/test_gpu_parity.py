@@ -129,6 +129,42 @@ def test_batch_equals_one_by_one(lib):
     b.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_group_of_mixed_widths_equals_lone_updates(lib, prec):
+    """A grouped launch holding a wide update (theta 1024 x 1024, whose Jacobi
+    operand is put in order of decreasing column norms before its first
+    sweeps) and a narrow one (never ordered) gives each MPO the bits of its
+    lone update: per-problem choices must not depend on the rest of the batch."""
+    import bench
+    nb, sites, lams, bb = bench.micro_state(256, seed=3)
+    small = random_state(9, 21, 4)
+    rng = np.random.default_rng(31)
+    gates = [(cg.haar_su4(rng), cg.haar_su4(rng)) for _ in range(2)]
+    bs = 3
+
+    def fresh():
+        big = lib.MPO(nb, 256, 1e-8, 1, PREC[prec])
+        big.load_state(sites, lams)
+        return big, gpu_mpo(lib, small, prec, chi_max=256, cutoff=1e-8, mode=1)
+
+    lone_big, lone_small = fresh()
+    ib = lone_big.absorb(bb, *gates[0])
+    i_s = lone_small.absorb(bs, *gates[1])
+    assert ib["k"] == 256
+    grp = lib.Group(PREC[prec])
+    g_big, g_small = fresh()
+    infos = grp.absorb([g_big, g_small], [bb, bs], [gates[0][0], gates[1][0]], [gates[0][1], gates[1][1]])
+    assert [x["k"] for x in infos] == [ib["k"], i_s["k"]]
+    for a, b, n in ((lone_big, g_big, nb), (lone_small, g_small, small.n)):
+        for i in range(n):
+            assert np.array_equal(a.read_site(i), b.read_site(i))
+        for i in range(n - 1):
+            assert np.array_equal(a.singular_values(i), b.singular_values(i))
+    for x in (lone_big, lone_small, g_big, g_small):
+        x.close()
+    grp.close()
+
+
 def test_error_codes_leave_state_unchanged(lib):
     m = random_state(5, 4, 3)
     g = gpu_mpo(lib, m, "fp64")
