@@ -1632,6 +1632,24 @@ const char* mpo_version(void) {
   return "libmpo 0.1 gfx950: MFMA complex GEMM (f32/f64), block one-sided Jacobi SVD with FP64 angles";
 }
 
+// Switches read from the environment when a context (an MPO's or a group's)
+// is created, so that grouped and lone updates take the same choices:
+// MPO_TRACE=1 prints the sweep counts; MPO_TRIAL_REUSE=0 re-runs every SWAP
+// trial (the memo is exact, so this only changes the time); MPO_QR_SPIN sets
+// the QR barrier's poll bound (0 makes every multi-workgroup panel give up at
+// once: a forced failure); MPO_SVD=accumulate selects the accumulating SVD
+// route for the FP32 and mixed forms.
+static void read_env(mpo_ctx* h) {
+  const char* t = std::getenv("MPO_TRACE");
+  h->trace = t && t[0] == '1';
+  const char* r = std::getenv("MPO_TRIAL_REUSE");
+  h->trial_reuse = !(r && r[0] == '0');
+  const char* q = std::getenv("MPO_QR_SPIN");
+  if (q && q[0]) h->qr_spin = std::max(0, std::atoi(q));
+  const char* v = std::getenv("MPO_SVD");
+  if (v && std::strcmp(v, "accumulate") == 0) h->svd_qr2 = false;
+}
+
 mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_handle_t* out) {
   if (!cfg || !out) return MPO_EINVAL;
   *out = nullptr;
@@ -1647,19 +1665,7 @@ mpo_status_t mpo_init_identity(const mpo_config_t* cfg, void* hip_stream, mpo_ha
   h->stream = (hipStream_t)hip_stream;
   h->n = cfg->n;
   h->max_sweeps = cfg->max_sweeps > 0 ? cfg->max_sweeps : 30;
-  {
-    const char* t = std::getenv("MPO_TRACE");
-    h->trace = t && t[0] == '1';
-    // MPO_TRIAL_REUSE=0 re-runs every SWAP trial (the memo is exact, so this
-    // only changes the time); MPO_QR_SPIN sets the QR barrier's poll bound
-    // (0 makes every multi-workgroup panel give up at once: a forced failure).
-    const char* r = std::getenv("MPO_TRIAL_REUSE");
-    h->trial_reuse = !(r && r[0] == '0');
-    const char* q = std::getenv("MPO_QR_SPIN");
-    if (q && q[0]) h->qr_spin = std::max(0, std::atoi(q));
-    const char* v = std::getenv("MPO_SVD");
-    if (v && std::strcmp(v, "accumulate") == 0) h->svd_qr2 = false;
-  }
+  read_env(h);
   mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
     const int n = h->n;
     h->chi.assign(n + 1, 1);
@@ -1717,10 +1723,7 @@ mpo_status_t mpo_group_create(int32_t precision, void* hip_stream, mpo_group_t* 
   h->esz = (precision == MPO_FP64) ? 16 : 8;
   h->stream = (hipStream_t)hip_stream;
   h->n = 0;
-  {
-    const char* t = std::getenv("MPO_TRACE");
-    h->trace = t && t[0] == '1';
-  }
+  read_env(h);
   mpo_status_t s = guarded(h, [&]() -> mpo_status_t {
     init_workspace(h);
     return MPO_OK;
