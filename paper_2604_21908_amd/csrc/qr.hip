@@ -428,114 +428,121 @@ __global__ __launch_bounds__(QMW_ROWS) void k_qr_panel(QrBatch qb, QrSyncBatch s
 
   double xn2 = 0, ar = 0, ai = 0;   // column j's tail norm and alpha, when carried over
   bool exact = true;                // sum column j's tail norm directly
-  for (int j = 0; j < nb; ++j) {
-    cx<double> xj{0.0, 0.0};
+  // The column loop is unrolled (a constant trip count, the body guarded by
+  // the uniform j < nb), so every access to the register array a[] has a
+  // constant index: a loop with a variable j would turn each of them into a
+  // chain of selects over all QNB entries.
 #pragma unroll
-    for (int k = 0; k < QNB; ++k)
-      if (k == j) xj = a[k];
-    if (exact) {
-      const double v1[3] = {rr > j ? xj.re * xj.re + xj.im * xj.im : 0.0, rr == j ? xj.re : 0.0,
-                            rr == j ? xj.im : 0.0};
-      qmw_block_sum<3>(v1, red, big, tid);
-      grid_sum(3);
-      xn2 = tot[0];
-      ar = tot[1];
-      ai = tot[2];
-    }
-    double tr = 0, ti = 0, scr = 0, sci = 0, beta = ar;
-    if (xn2 > 0 || ai != 0) {
-      const double nrm = sqrt(ar * ar + ai * ai + xn2);
-      beta = (ar >= 0) ? -nrm : nrm;
-      tr = (beta - ar) / beta;
-      ti = -ai / beta;
-      const double dr = ar - beta, di = ai, d2 = dr * dr + di * di;
-      scr = dr / d2;
-      sci = -di / d2;
-    }
-    const bool trivial = (tr == 0.0 && ti == 0.0);
-    // this row of column j: beta on the diagonal, the scaled tail below
-    cx<double> vj{0.0, 0.0};
-    if (rr == j) {
-      xj = cx<double>{beta, 0.0};
-      vj = cx<double>{1.0, 0.0};
-    } else if (rr > j) {
-      if (!trivial) xj = cx<double>{xj.re * scr - xj.im * sci, xj.re * sci + xj.im * scr};
-      vj = xj;
-    }
+  for (int j = 0; j < QNB; ++j) {
+    if (j < nb) {
+      cx<double> xj{0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < QNB; ++k)
-      if (k == j) a[k] = xj;
-    // w_k (slot k - 1, k > j), z_q (slot q, q < j), and column j + 1's
-    // A, B, C and row-(j + 1) entries of a_{j+1} and v_j (slots 30..37)
-    const int jn = j + 1;
-    {
-      constexpr int NV = 2 * (QNB - 1) + 8;
-      double v2[NV];
-      cx<double> an{0.0, 0.0};
-#pragma unroll
-      for (int sidx = 0; sidx < QNB - 1; ++sidx) {
-        const bool isw = sidx >= j;
-        const cx<double> ak = a[sidx + 1];
-        const cx<double> aq = a[sidx];
-        if (sidx + 1 == jn) an = ak;
-        const cx<double> vq = (rr == sidx) ? cx<double>{1.0, 0.0} : (rr > sidx ? aq : cx<double>{0.0, 0.0});
-        // w: conj(vj) a_k ; z: conj(vq) vj
-        const cx<double> x = isw ? vj : vq, y = isw ? ak : vj;
-        v2[2 * sidx] = x.re * y.re + x.im * y.im;
-        v2[2 * sidx + 1] = x.re * y.im - x.im * y.re;
+      for (int k = 0; k < QNB; ++k)
+        if (k == j) xj = a[k];
+      if (exact) {
+        const double v1[3] = {rr > j ? xj.re * xj.re + xj.im * xj.im : 0.0, rr == j ? xj.re : 0.0,
+                              rr == j ? xj.im : 0.0};
+        qmw_block_sum<3>(v1, red, big, tid);
+        grid_sum(3);
+        xn2 = tot[0];
+        ar = tot[1];
+        ai = tot[2];
       }
-      const bool below = rr > jn, at = rr == jn;
-      v2[30] = below ? an.re * an.re + an.im * an.im : 0.0;
-      v2[31] = below ? an.re * vj.re + an.im * vj.im : 0.0;   // conj(a) v
-      v2[32] = below ? an.re * vj.im - an.im * vj.re : 0.0;
-      v2[33] = below ? vj.re * vj.re + vj.im * vj.im : 0.0;
-      v2[34] = at ? an.re : 0.0;
-      v2[35] = at ? an.im : 0.0;
-      v2[36] = at ? vj.re : 0.0;
-      v2[37] = at ? vj.im : 0.0;
-      qmw_block_sum<NV>(v2, red, big, tid);
-    }
-    grid_sum(2 * (QNB - 1) + 8);
-    // a_k -= conj(tau) w_k v_j for k > j
-    const double ctr = tr, cti = -ti;
+      double tr = 0, ti = 0, scr = 0, sci = 0, beta = ar;
+      if (xn2 > 0 || ai != 0) {
+        const double nrm = sqrt(ar * ar + ai * ai + xn2);
+        beta = (ar >= 0) ? -nrm : nrm;
+        tr = (beta - ar) / beta;
+        ti = -ai / beta;
+        const double dr = ar - beta, di = ai, d2 = dr * dr + di * di;
+        scr = dr / d2;
+        sci = -di / d2;
+      }
+      const bool trivial = (tr == 0.0 && ti == 0.0);
+      // this row of column j: beta on the diagonal, the scaled tail below
+      cx<double> vj{0.0, 0.0};
+      if (rr == j) {
+        xj = cx<double>{beta, 0.0};
+        vj = cx<double>{1.0, 0.0};
+      } else if (rr > j) {
+        if (!trivial) xj = cx<double>{xj.re * scr - xj.im * sci, xj.re * sci + xj.im * scr};
+        vj = xj;
+      }
 #pragma unroll
-    for (int k = 1; k < QNB; ++k) {
-      if (k > j) {
-        const double wr = tot[2 * (k - 1)], wi = tot[2 * (k - 1) + 1];
-        const double fr = ctr * wr - cti * wi, fi = ctr * wi + cti * wr;
-        a[k].re -= vj.re * fr - vj.im * fi;
-        a[k].im -= vj.re * fi + vj.im * fr;
+      for (int k = 0; k < QNB; ++k)
+        if (k == j) a[k] = xj;
+      // w_k (slot k - 1, k > j), z_q (slot q, q < j), and column j + 1's
+      // A, B, C and row-(j + 1) entries of a_{j+1} and v_j (slots 30..37)
+      const int jn = j + 1;
+      {
+        constexpr int NV = 2 * (QNB - 1) + 8;
+        double v2[NV];
+        cx<double> an{0.0, 0.0};
+#pragma unroll
+        for (int sidx = 0; sidx < QNB - 1; ++sidx) {
+          const bool isw = sidx >= j;
+          const cx<double> ak = a[sidx + 1];
+          const cx<double> aq = a[sidx];
+          if (sidx + 1 == jn) an = ak;
+          const cx<double> vq = (rr == sidx) ? cx<double>{1.0, 0.0} : (rr > sidx ? aq : cx<double>{0.0, 0.0});
+          // w: conj(vj) a_k ; z: conj(vq) vj
+          const cx<double> x = isw ? vj : vq, y = isw ? ak : vj;
+          v2[2 * sidx] = x.re * y.re + x.im * y.im;
+          v2[2 * sidx + 1] = x.re * y.im - x.im * y.re;
+        }
+        const bool below = rr > jn, at = rr == jn;
+        v2[30] = below ? an.re * an.re + an.im * an.im : 0.0;
+        v2[31] = below ? an.re * vj.re + an.im * vj.im : 0.0;   // conj(a) v
+        v2[32] = below ? an.re * vj.im - an.im * vj.re : 0.0;
+        v2[33] = below ? vj.re * vj.re + vj.im * vj.im : 0.0;
+        v2[34] = at ? an.re : 0.0;
+        v2[35] = at ? an.im : 0.0;
+        v2[36] = at ? vj.re : 0.0;
+        v2[37] = at ? vj.im : 0.0;
+        qmw_block_sum<NV>(v2, red, big, tid);
       }
-    }
-    // column j + 1's tail norm and alpha from the expansion, unless it may
-    // have cancelled
-    if (jn < nb) {
-      const double wr = tot[2 * j], wi = tot[2 * j + 1];
-      const double cr = ctr * wr - cti * wi, ci = ctr * wi + cti * wr;   // c = conj(tau) w_{j+1}
-      const double A = tot[30], Br = tot[31], Bi = tot[32], Cv = tot[33];
-      const double c2 = cr * cr + ci * ci;
-      const double est = A - 2.0 * (cr * Br - ci * Bi) + c2 * Cv;
-      const double scale = A + 2.0 * sqrt(c2 * (Br * Br + Bi * Bi)) + c2 * Cv;
-      exact = !(est >= 0.1 * scale);
-      xn2 = est;
-      // alpha' = a_{j+1}[j+1] - c v_j[j+1]
-      ar = tot[34] - (cr * tot[36] - ci * tot[37]);
-      ai = tot[35] - (cr * tot[37] + ci * tot[36]);
-    }
-    // column j of T
-    if (tid == 0) Tl[j][j] = cx<double>{tr, ti};
-    if (tid < j) {
-      double sr = 0, si = 0;
-      for (int b = tid; b < j; ++b) {
-        const cx<double> t = Tl[tid][b];
-        const double zr = tot[2 * b], zi = tot[2 * b + 1];
-        sr += t.re * zr - t.im * zi;
-        si += t.re * zi + t.im * zr;
+      grid_sum(2 * (QNB - 1) + 8);
+      // a_k -= conj(tau) w_k v_j for k > j
+      const double ctr = tr, cti = -ti;
+#pragma unroll
+      for (int k = 1; k < QNB; ++k) {
+        if (k > j) {
+          const double wr = tot[2 * (k - 1)], wi = tot[2 * (k - 1) + 1];
+          const double fr = ctr * wr - cti * wi, fi = ctr * wi + cti * wr;
+          a[k].re -= vj.re * fr - vj.im * fi;
+          a[k].im -= vj.re * fi + vj.im * fr;
+        }
       }
-      Tl[tid][j] = cx<double>{-(tr * sr - ti * si), -(tr * si + ti * sr)};
+      // column j + 1's tail norm and alpha from the expansion, unless it may
+      // have cancelled
+      if (jn < nb) {
+        const double wr = tot[2 * j], wi = tot[2 * j + 1];
+        const double cr = ctr * wr - cti * wi, ci = ctr * wi + cti * wr;   // c = conj(tau) w_{j+1}
+        const double A = tot[30], Br = tot[31], Bi = tot[32], Cv = tot[33];
+        const double c2 = cr * cr + ci * ci;
+        const double est = A - 2.0 * (cr * Br - ci * Bi) + c2 * Cv;
+        const double scale = A + 2.0 * sqrt(c2 * (Br * Br + Bi * Bi)) + c2 * Cv;
+        exact = !(est >= 0.1 * scale);
+        xn2 = est;
+        // alpha' = a_{j+1}[j+1] - c v_j[j+1]
+        ar = tot[34] - (cr * tot[36] - ci * tot[37]);
+        ai = tot[35] - (cr * tot[37] + ci * tot[36]);
+      }
+      // column j of T
+      if (tid == 0) Tl[j][j] = cx<double>{tr, ti};
+      if (tid < j) {
+        double sr = 0, si = 0;
+        for (int b = tid; b < j; ++b) {
+          const cx<double> t = Tl[tid][b];
+          const double zr = tot[2 * b], zi = tot[2 * b + 1];
+          sr += t.re * zr - t.im * zi;
+          si += t.re * zi + t.im * zr;
+        }
+        Tl[tid][j] = cx<double>{-(tr * sr - ti * si), -(tr * si + ti * sr)};
+      }
+      if (w == 0 && tid == 0) tau[p0 + j] = cx<T>{(T)tr, (T)ti};
+      __syncthreads();
     }
-    if (w == 0 && tid == 0) tau[p0 + j] = cx<T>{(T)tr, (T)ti};
-    __syncthreads();
   }
   if (live) {
 #pragma unroll
