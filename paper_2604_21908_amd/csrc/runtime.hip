@@ -317,13 +317,14 @@ double tol_for(const mpo_ctx* h, int m) {
   return std::max(8.0 * std::sqrt((double)std::max(m, 1)) * eps, eps * 4);
 }
 
-// Convergence tolerance of the split-BF16 sweeps of the mixed form.  After
-// them the accumulated rotations are re-orthogonalised and the operand is
-// recomputed from R, so the column norms match the singular values to second
-// order in this tolerance: at 1e-3 the chi = 1024 update's values are within
-// 3e-5 (normwise) of the FP64 oracle's, against 1e-4 allowed, and the
-// written operator's excess over the optimal discarded weight is 2e-6 of the
-// total (measured; 3e-3 exceeds 1e-4).  A caller's jacobi_tol overrides it.
+// Convergence tolerance of the split-BF16 sweeps of the mixed form.  The
+// column norms of the converged operand (rotated in FP32 on the second-QR
+// route; recomputed from R with the re-orthogonalised rotations on the
+// accumulating one) match the singular values to second order in it: at 1e-3
+// the chi = 1024 update's values are within 3e-5 (normwise) of the FP64
+// oracle's, against 1e-4 allowed, and the written operator's excess over the
+// optimal discarded weight is below 2e-6 of the total (measured; 3e-3 exceeds
+// 1e-4 on the accumulating route).  A caller's jacobi_tol overrides it.
 double tol_bf16(const mpo_ctx* h, int m) {
   if (h->cfg.jacobi_tol > 0) return h->cfg.jacobi_tol;
   return std::max(1e-3, tol_for(h, m));
