@@ -61,20 +61,23 @@ __global__ __launch_bounds__(256) void k_jac_gram(JacBatch jb, int step) {
     for (int u = 0; u < 8; ++u) Pc[lane][wave + 4 * u] = nxt[u];
     __syncthreads();
     if (s0 + 64 < r1) fetch(s0 + 64);
-    acc_t are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+    // conj(x) y as three real products (Gauss): k1 = xr yr, k2 = xi yi,
+    // k3 = (xr - xi)(yr + yi); Re = k1 + k2, Im = k3 - k1 + k2 (formed in FP64
+    // from the slab's FP32 or FP64 sums) -- three MFMA chains instead of four
+    acc_t k1 = {0, 0, 0, 0}, k2 = {0, 0, 0, 0}, k3 = {0, 0, 0, 0};
 #pragma unroll 4
     for (int kk = 0; kk < 64; kk += 4) {
       const cx<T> x = Pc[kk + (lane >> 4)][I * 16 + (lane & 15)];   // A = P^dag: conj applied below
       const cx<T> y = Pc[kk + (lane >> 4)][J * 16 + (lane & 15)];
-      are = MF<T>::mma(x.re, y.re, are);
-      are = MF<T>::mma(x.im, y.im, are);
-      aim = MF<T>::mma(x.re, y.im, aim);
-      aim = MF<T>::mma(-x.im, y.re, aim);
+      k1 = MF<T>::mma(x.re, y.re, k1);
+      k2 = MF<T>::mma(x.im, y.im, k2);
+      k3 = MF<T>::mma(x.re - x.im, y.re + y.im, k3);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      gr[r] += (double)are[r];
-      gi[r] += (double)aim[r];
+      const double a1 = (double)k1[r], a2 = (double)k2[r];
+      gr[r] += a1 + a2;
+      gi[r] += ((double)k3[r] - a1) + a2;
     }
     __syncthreads();
   }

@@ -76,27 +76,35 @@ __device__ __forceinline__ void rot_rows(const JacProb& P, int bi, int bj, int c
 #pragma unroll
     for (int u = 0; u < 8; ++u) Sw[lane & 15][(lane >> 4) + 4 * u] = v[u];
     __builtin_amdgcn_wave_barrier();
-    acc_t cre[2], cim[2];
+    T pre[2][4], pim[2][4];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const cx<T> a = Sw[lane & 15][t * 16 + MF<T>::row(lane, r)];
-        cre[t][r] = a.re;
-        cim[t][r] = a.im;
+        pre[t][r] = a.re;
+        pim[t][r] = a.im;
       }
     __builtin_amdgcn_wave_barrier();
+    // The increment P D as three real products (Gauss): with D = Dr + i Di and
+    // P = Pr + i Pi, t1 = Dr Pr, t2 = Di Pi, t3 = (Dr + Di)(Pr + Pi), then
+    // Re = t1 - t2 and Im = t3 - t1 - t2 -- three MFMA chains instead of four.
+    // The increment is formed on its own and only then added to P, so no
+    // product is taken of P's own (large) values.
+    acc_t t1[2], t2[2], t3[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) t1[t] = t2[t] = t3[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
       const int k = 4 * kk + (lane >> 4);
       const cx<T> x = v[kk];
+      const T xs = x.re + x.im;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const cx<T> d = Ds[k][t * 16 + (lane & 15)];   // A[c][k] = D[k][c]
-        cre[t] = MF<T>::mma(d.re, x.re, cre[t]);
-        cre[t] = MF<T>::mma(-d.im, x.im, cre[t]);
-        cim[t] = MF<T>::mma(d.re, x.im, cim[t]);
-        cim[t] = MF<T>::mma(d.im, x.re, cim[t]);
+        t1[t] = MF<T>::mma(d.re, x.re, t1[t]);
+        t2[t] = MF<T>::mma(d.im, x.im, t2[t]);
+        t3[t] = MF<T>::mma(d.re + d.im, xs, t3[t]);
       }
     }
     const int rho = s0 + (lane & 15);
@@ -105,7 +113,9 @@ __device__ __forceinline__ void rot_rows(const JacProb& P, int bi, int bj, int c
 #pragma unroll
       for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sb.base[colA[4 * t + r] * sb.ld + sb.row] = cx<T>{cre[t][r], cim[t][r]};
+        for (int r = 0; r < 4; ++r)
+          sb.base[colA[4 * t + r] * sb.ld + sb.row] =
+              cx<T>{pre[t][r] + (t1[t][r] - t2[t][r]), pim[t][r] + ((t3[t][r] - t1[t][r]) - t2[t][r])};
     }
     if (more) {
 #pragma unroll
