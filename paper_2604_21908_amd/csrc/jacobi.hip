@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
   char* const wb = (char*)&W[0][0];
   int cur = 0;
   for (int isw = 0; isw < inner_sweeps; ++isw) {
-    for (int st = 0; st < 31; ++st, cur ^= 1) {
+    for (int st = 0; st < 31; ++st) {
       char* const gc = g0 + cur * (32 * EVD_ROWB);
       char* const gn = g0 + (cur ^ 1) * (32 * EVD_ROWB);
       const ushort4 R = ptab[st][kr], C = ptab[st][kc];
@@ -301,7 +301,13 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
       const E app = at(gc, C.x + C.z).re, aqq = at(gc, C.y + C.w).re;
       const cx<E> gpq = at(gc, C.x + C.w);
       E cc, zcr, zci;
-      if (jac_angle_e<E>(app, aqq, gpq, tol, sizeof(T) == 8, cc, zcr, zci)) anyrot = isw + 1;
+      const bool rot = jac_angle_e<E>(app, aqq, gpq, tol, sizeof(T) == 8, cc, zcr, zci);
+      // A round in which none of the 16 pairs rotates would rewrite G and W
+      // unchanged: skipped, with no barrier and no buffer swap.  Every wave
+      // holds all 16 column pairs (kc = lane & 15) and reads the same G, so all
+      // waves take the same decision.
+      if (!__any(rot)) continue;
+      if (rot) anyrot = isw + 1;
       const E cr = __shfl(cc, src, 64), zrr = __shfl(zcr, src, 64), zri = __shfl(zci, src, 64);
       // H = G_block J_c; x * (-conj(zc)) = -(x.re zcr + x.im zci) + i (x.re zci - x.im zcr)
       const E h00r = a00.re * cc - (a01.re * zcr + a01.im * zci);
@@ -329,9 +335,11 @@ __global__ __launch_bounds__(256) void k_jac_evd(JacBatch jb, int step, int inne
             cx<E>{w10.re * zcr - w10.im * zci + w11.re * cc, w10.re * zci + w10.im * zcr + w11.im * cc};
       }
       __syncthreads();
+      cur ^= 1;
     }
     // anyrot only grows and is isw + 1 or more iff some pair rotated in this
-    // sweep; every thread reads it after the sweep's last barrier
+    // sweep; every thread reads it after the barrier of the sweep's last
+    // rotating round (a skipped round writes nothing)
     if (anyrot <= isw) break;
   }
   // D = W - I, rounded entry by entry (see k_jac_rot)
